@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X: multistep EPI steps of the DFR
+shallow-water model, each one KIOPS phi-combination driven by complex-step
+J*v products, plus the J*v kernel alone.
+
+Default workload: ne = 30, p = 5 (194,400 nodes, 583,200 unknowns), EPI5,
+dt = 1800 s, KIOPS tol 1e-10, Krylov dimension <= 64, plain FP64, on the
+balanced zonal flow with seeded perturbations (synthetic; see
+paper_2101_05617_amd/inputs.py).  One "step" is one EPI5 step.
+
+Prints ONE JSON line (rank 0).  Usage:
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "complex-step Jv/s + EPI steps/s, FP64 plain vs FP32-Jv batched at stated error"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def jv_bytes_per_node(form):
+    # algorithmic bytes of one complex-step J*v per node: read q, read v, write J*v
+    return {"fp64": 72, "fp32_jv": 12 + 24 + 24}[form]
+
+
+def arnoldi_jv_bytes_per_node(p, iop=2):
+    # the J*v kernel as launched inside KIOPS additionally reads the p scaled
+    # b-columns of the augmented operator and the previous basis vector for the
+    # fused inner products: 72 + 24 p + 24 (iop = 2)
+    return 72 + 24 * p + (24 if iop >= 2 else 0)
+
+
+def time_jv(g, q, vs, outs, eps, prec, reps):
+    """Mean duration (ms) of back-to-back J*v launches, HIP events on the
+    library's (torch's current) stream; v and out rotate through buffers."""
+    import torch
+    from paper_2101_05617_amd import dfrsw
+    for k in range(3):
+        dfrsw.dfr_jvp_complex_step(g, q, vs[k % len(vs)], eps, prec, outs[k % len(outs)])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(reps):
+        dfrsw.dfr_jvp_complex_step(g, q, vs[k % len(vs)], eps, prec, outs[k % len(outs)])
+    e1.record()
+    torch.cuda.synchronize()
+    dfrsw.dfr_sync(g)
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline_leg(workload_name):
+    """Time the oracle on this host: one steady-state EPI step after the
+    start-up steps (untimed, one EPI2 sub-step each)."""
+    import numpy as np
+
+    import oracle
+    from oracle import epi as oepi
+    from paper_2101_05617_amd import inputs
+    w = inputs.WORKLOADS[workload_name]
+    G = oracle.OracleGrid(w.ne, w.ns, *w.constants())
+    P, B1, B2 = G.node_frames()
+    Q, _ = inputs.initial_state(w, P, B1, B2)
+    E = oepi.EPI(G.rhs, lambda a, b: G.jvp(a, b, w.eps), w.order, w.dt_nd, Q, startup_substeps=1,
+                 kiops_opts=dict(tol=w.tol, m_max=w.m_max))
+    for _ in range(E.P):
+        E.step()
+    t0 = time.perf_counter()
+    E.step()
+    dt = time.perf_counter() - t0
+    st = E.stats[-1]
+    V = np.random.default_rng(0).standard_normal(3 * G.N)
+    t1 = time.perf_counter()
+    for _ in range(10):
+        G.jvp(Q, V, w.eps)
+    tj = (time.perf_counter() - t1) / 10
+    return {"step_s": dt, "jv_s": tj, "n_matvec": st.n_matvec}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="c1_ne30_p5")
+    ap.add_argument("--jv-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the ne=60, p=6 J*v roofline figures")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)
+        return 0
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(the multi-GPU design is described, not built); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    w = inputs.WORKLOADS[args.workload]
+    log(f"workload {w.name}: ne={w.ne} p={w.p} N={w.n_nodes} EPI{w.order} dt={w.dt_s}s tol={w.tol} m<={w.m_max}")
+
+    g = dfrsw.Grid(w.ne, w.p, *w.constants())
+    P, B1, B2 = g.node_frames()
+    Q, hB = inputs.initial_state(w, P, B1, B2)
+    q0 = torch.from_numpy(Q).cuda()
+    st = dfrsw.epi_create(g, w.order, w.dt_nd, q0, startup_substeps=w.startup_substeps, eps=w.eps, prec="fp64")
+    opts = dfrsw.kiops_opts(tol=w.tol, m_max=w.m_max)
+    P_hist = 0 if w.order == 2 else w.order - 2
+
+    for k in range(args.warmup):
+        s = dfrsw.epi_step(g, st, opts)
+        log(f"warmup step {k + 1}/{args.warmup}: {s}")
+    timed_includes_startup = args.warmup < P_hist
+
+    # ---- timed region: K whole EPI steps
+    dfrsw.dfr_timing_enable(g, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(dfrsw.epi_step(g, st, opts))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = {k: dfrsw.dfr_timing_read(g, k) for k in dfrsw.KERNEL_KINDS}
+    dfrsw.dfr_timing_enable(g, False)
+    log(f"timed {args.steps} steps in {wall:.3f}s; kernels {kern}")
+    ms_per_step = 1e3 * wall / args.steps
+    steps_per_s = args.steps / wall
+    n_jv = sum(s["n_matvec"] for s in stats)
+    kernel_ms_total = sum(v[0] for v in kern.values())
+
+    N = w.n_nodes
+    M = w.order - 2 if w.order > 2 else 1      # phi-columns of the combination
+    ms_jva, n_jva = kern["jv_arnoldi"]
+    avg_jva_ms = ms_jva / max(n_jva, 1)
+    bytes_jva = arnoldi_jv_bytes_per_node(M) * N
+    achieved = bytes_jva / (avg_jva_ms * 1e-3) / 1e9 if n_jva else 0.0
+
+    # ---- the J*v kernel alone (plain FP64), rotating buffers
+    vs = [torch.randn(3 * N, dtype=torch.float64, device="cuda") * 1e-3 for _ in range(4)]
+    outs = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(4)]
+    q = dfrsw.epi_get_state(st)
+    jv_ms = time_jv(g, q, vs, outs, w.eps, "fp64", args.jv_reps)
+    jv32_ms = time_jv(g, q, vs, outs, 1e-20, "fp32_jv", args.jv_reps)
+    log(f"plain J*v: fp64 {jv_ms * 1e3:.1f} us, fp32 {jv32_ms * 1e3:.1f} us")
+
+    sim_days_per_hour = (args.steps * w.dt_s / 86400.0) / (wall / 3600.0)
+
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "EPI steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: rotated cubed sphere ne={w.ne}, p={w.p} ({N} nodes, {3 * N} unknowns), "
+                               f"EPI{w.order}, dt={w.dt_s:g}s, KIOPS tol={w.tol:g}, m<={w.m_max}, plain FP64",
+                   "ne": w.ne, "p": w.p, "nodes": N, "order": w.order, "dt_s": w.dt_s,
+                   "timed_steps_include_startup": timed_includes_startup},
+        "jv_per_s": 1e3 / jv_ms,
+        "jv_per_s_fp32": 1e3 / jv32_ms,
+        "jv_in_step_per_s": n_jv / wall,
+        "sim_days_per_wall_hour": sim_days_per_hour,
+        "kiops_per_step": {"n_matvec": n_jv / args.steps,
+                           "n_substeps": sum(s["n_substeps"] for s in stats) / args.steps,
+                           "n_rejected": sum(s["n_rejected"] for s in stats) / args.steps,
+                           "n_expm": sum(s["n_expm"] for s in stats) / args.steps},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "kernel_launches_per_step": {k: v[1] / args.steps for k, v in kern.items()},
+        "gpu_busy_fraction": kernel_ms_total / (1e3 * wall),
+        "roofline": {
+            "kernel": "dfr_kernel complex-step J*v with fused Arnoldi epilogue (inside KIOPS)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_node": arnoldi_jv_bytes_per_node(M), "avg_launch_us": avg_jva_ms * 1e3,
+            "launches": n_jva,
+        },
+        "roofline_plain_jv": {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "fp64": {"bytes_per_node": 72, "avg_launch_us": jv_ms * 1e3,
+                     "achieved": 72 * N / (jv_ms * 1e-3) / 1e9,
+                     "frac": 72 * N / (jv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "fp32_jv": {"bytes_per_node": 60, "avg_launch_us": jv32_ms * 1e3,
+                        "achieved": 60 * N / (jv32_ms * 1e-3) / 1e9,
+                        "frac": 60 * N / (jv32_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        },
+    }
+    del st, vs, outs, q, q0
+    torch.cuda.synchronize()
+
+    # ---- the ne = 60, p = 6 J*v (the roofline target size), buffers rotated
+    if not args.no_c2:
+        w2 = inputs.WORKLOADS["c2_ne60_p6_jet"]
+        g2 = dfrsw.Grid(w2.ne, w2.p, *w2.constants())
+        P2, B12, B22 = g2.node_frames()
+        Q2, _ = inputs.initial_state(w2, P2, B12, B22)
+        q2 = torch.from_numpy(Q2).cuda()
+        N2 = w2.n_nodes
+        nbuf = 8   # 8 x (v, out) x 25 MB = 406 MB > 256 MB last-level cache
+        v2 = [torch.randn(3 * N2, dtype=torch.float64, device="cuda") * 1e-3 for _ in range(nbuf)]
+        o2 = [torch.empty(3 * N2, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+        t64 = time_jv(g2, q2, v2, o2, 1e-150, "fp64", args.jv_reps)
+        t32 = time_jv(g2, q2, v2, o2, 1e-20, "fp32_jv", args.jv_reps)
+        log(f"ne=60 p=6 J*v: fp64 {t64 * 1e3:.1f} us, fp32 {t32 * 1e3:.1f} us")
+        out["jv_ne60_p6"] = {
+            "nodes": N2,
+            "fp64": {"us": t64 * 1e3, "jv_per_s": 1e3 / t64, "GBs": 72 * N2 / (t64 * 1e-3) / 1e9,
+                     "frac_hbm": 72 * N2 / (t64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "fp32_jv": {"us": t32 * 1e3, "jv_per_s": 1e3 / t32, "GBs": 60 * N2 / (t32 * 1e-3) / 1e9,
+                        "frac_hbm": 60 * N2 / (t32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        }
+        del v2, o2, q2, g2
+
+    # ---- the oracle on this host's cores (bounded sample, one thread)
+    if not args.no_cpu_baseline:
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        log("cpu baseline: oracle, one thread")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                            "--workload", args.workload], capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode == 0:
+            cb = json.loads(r.stdout.strip().splitlines()[-1])
+            out["cpu_baseline"] = {"value": 1.0 / cb["step_s"], "unit": "EPI steps/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"one EPI{w.order} step of {w.name} after {P_hist} untimed EPI2 "
+                                             f"start-up steps ({cb['n_matvec']} J*v); J*v alone "
+                                             f"{cb['jv_s'] * 1e3:.1f} ms",
+                                   "jv_per_s": 1.0 / cb["jv_s"]}
+        else:
+            log("cpu baseline failed: " + r.stderr[-2000:])
+            out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

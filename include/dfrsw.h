@@ -1,0 +1,162 @@
+/*
+ * dfrsw.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * direct-flux-reconstruction (DFR) shallow-water model with exponential time
+ * integration on the rotated cubed sphere (Gaudreault, Charron, Dallerit,
+ * Tokman, arXiv 2101.05617).
+ *
+ * Conventions (all entry points):
+ *   - State vectors hold 3*N values, field-major: H, H u^1, H u^2, each over
+ *     the N = 6 ne^2 (p+1)^2 Gauss-Legendre nodes ordered
+ *     (panel, element row, element column, node row, node column), node
+ *     column (x^1 direction) fastest.  u^i are contravariant components in the
+ *     equiangular panel coordinates x^i (angle per unit time).
+ *   - Pointers named q, v, w, jv, dqdt, b[k] are DEVICE pointers owned by the
+ *     caller (e.g. torch tensors); the library never frees them.  Pointers
+ *     named host_* and the descriptor's hB are HOST pointers.
+ *   - Work is enqueued on the stream given to dfr_create.  dfr_rhs and
+ *     dfr_jvp_complex_step are asynchronous; kiops_phi_apply and epi_step
+ *     synchronise the stream (their adaptive control reads small scalars back).
+ *   - Units: any consistent system.  The equations keep their form for
+ *     radius = 1, omega = 1 and a rescaled gravity; the complex-FP32 form needs
+ *     such a scaled state so that eps times the state stays far above the
+ *     FP32 underflow threshold.
+ *   - Return value 0 on success, a negative DFR_E_* code on error; the message
+ *     is in dfr_last_error() (thread-local).  Errors found inside kernels
+ *     (non-finite input, non-positive depth) are latched in the context and
+ *     returned by the next synchronising call (dfr_sync, kiops_phi_apply,
+ *     epi_step).  Outputs are unspecified after an error.
+ */
+#ifndef DFRSW_H
+#define DFRSW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DFR_OK = 0,
+  DFR_E_INVAL = -1,      /* bad argument or descriptor */
+  DFR_E_NOMEM = -2,      /* device or host allocation failed */
+  DFR_E_HIP = -3,        /* a HIP runtime call failed */
+  DFR_E_NONFINITE = -4,  /* NaN or Inf in an input state or direction */
+  DFR_E_DEPTH = -5,      /* non-positive fluid depth H */
+  DFR_E_KIOPS = -6       /* the Krylov controller did not converge */
+};
+
+typedef enum { DFR_FP64 = 0, DFR_FP32_JV = 1 } dfr_precision;
+
+typedef struct dfr_ctx dfr_ctx;
+typedef struct epi_state epi_state;
+
+/* Grid and physical constants.  Sec. 2 and App. B: a = radius, Omega =
+ * omega, g_r = gravity; (lambda0, phi0, alpha0) the rotation of panel 0
+ * (the paper uses (0, pi/4, 0)).  p = DFR degree, 1 <= p <= 7 (p+1 GL points
+ * per element edge); ne >= 1.  hB: NULL, or N host values of the bottom
+ * orography h_B at the nodes (Eq. 2); its derivative is taken element-locally
+ * on the GL points. */
+typedef struct {
+  int ne, p;
+  double radius, omega, gravity;
+  double lambda0, phi0, alpha0;
+  const double *hB;
+} dfr_grid_desc;
+
+/* Adaptive Krylov (KIOPS-type) controller settings; see kiops_phi_apply. */
+typedef struct {
+  double tol;        /* relative tolerance of the phi-combination */
+  int m_init;        /* initial Krylov dimension */
+  int m_min, m_max;  /* bounds of the Krylov dimension (m_max <= 64) */
+  int iop;           /* incomplete orthogonalisation length (>= 1) */
+  int max_attempts;  /* cap on sub-step attempts before DFR_E_KIOPS */
+} kiops_opts;
+
+typedef struct {
+  int n_matvec;      /* complex-step J*v products */
+  int n_substeps;    /* accepted sub-steps */
+  int n_rejected;    /* rejected attempts */
+  int m_last;        /* Krylov dimension of the last accepted sub-step */
+  int happy;         /* 1 if a happy breakdown ended a sub-step */
+  int n_expm;        /* small exponentials evaluated */
+} kiops_stats;
+
+/* Create a discretisation context on the current HIP device.  hip_stream is
+ * a hipStream_t (NULL = default stream).  Allocates the geometry tables and
+ * all workspace.  Sec. 3 (DFR), App. B (geometry), App. C (interfaces). */
+int dfr_create(const dfr_grid_desc *desc, void *hip_stream, dfr_ctx **out);
+int dfr_destroy(dfr_ctx *ctx);
+/* N = 6 ne^2 (p+1)^2 */
+int64_t dfr_num_nodes(const dfr_ctx *ctx);
+/* Per node: unit position P and the coordinate basis dP/dx^1, dP/dx^2 on the
+ * unit sphere (3 doubles each, node order as above).  Host outputs of size 3N. */
+int dfr_node_frames(const dfr_ctx *ctx, double *host_P, double *host_B1, double *host_B2);
+/* Wait for the context's stream; return (and clear) any latched kernel error. */
+int dfr_sync(dfr_ctx *ctx);
+
+/* dqdt = F(q): the DFR right-hand side of the covariant shallow-water
+ * equations, Eqs. (1)-(2) with the flux reconstruction of Eqs. (10)-(14),
+ * Rusanov interface fluxes with the wave speeds of Eqs. (147)-(148), panel
+ * interfaces per App. C.  q, dqdt: device, 3N doubles each, may not alias. */
+int dfr_rhs(dfr_ctx *ctx, const double *q, double *dqdt);
+
+/* jv = Im F(q + i eps v) / eps (Eq. 28), one complex evaluation of the same
+ * right-hand side.  prec = DFR_FP64: complex FP64.  prec = DFR_FP32_JV: the
+ * complex evaluation runs in FP32 on FP32 roundings of q and v (eps must
+ * keep eps*|v| far above 1e-38 on the caller's scale); jv is written in FP64.
+ * Branches of |.| and max(.,.) in the Rusanov flux are those of the real
+ * evaluation at q.  q, v, jv: device, 3N doubles; jv may not alias q or v. */
+int dfr_jvp_complex_step(dfr_ctx *ctx, const double *q, const double *v, double eps,
+                         dfr_precision prec, double *jv);
+
+/* w = sum_{k=0}^{n_phi} tau_out^k phi_k(tau_out J(q_lin)) b_k   (Eq. 29)
+ * with phi_k of Eq. (26) and J(q_lin) applied by complex-step products
+ * (dfr_jvp_complex_step with the given eps and prec).  b: host array of
+ * n_phi+1 device pointers (3N doubles each); b[0] may be NULL (zero).
+ * n_phi >= 0 (n_phi = 0 is the exponential).  Adaptive sub-stepping with
+ * incomplete orthogonalisation (KIOPS); the controller is deterministic and
+ * documented in the library source.  w: device, 3N doubles, may not alias
+ * q_lin or any b[k].  stats may be NULL.  Synchronises the stream. */
+int kiops_phi_apply(dfr_ctx *ctx, const double *q_lin, double tau_out, int n_phi,
+                    const double *const *b, const kiops_opts *opts, double eps,
+                    dfr_precision prec, double *w, kiops_stats *stats);
+
+/* Multistep EPI integrator (Sec. 4): order 2 (exponential Euler, Eq. 25),
+ * 3 (Eq. 30) or 4, 5, 6 (Eqs. 34-38).  The first P = order-2 steps use EPI2
+ * with startup_substeps equal sub-steps.  q0: device, 3N doubles (copied).
+ * The state owns the history q_{n-i}, F(q_{n-i}). */
+int epi_create(dfr_ctx *ctx, int order, double dt, int startup_substeps, const double *q0,
+               double eps, dfr_precision prec, epi_state **out);
+/* Advance one step of size dt.  q_out (device, 3N doubles, may be NULL)
+ * receives q_{n+1}.  stats (may be NULL) accumulates over the step's KIOPS
+ * calls.  Synchronises the stream. */
+int epi_step(dfr_ctx *ctx, epi_state *st, const kiops_opts *opts, double *q_out, kiops_stats *stats);
+/* Copy the current state q_n to a device buffer of 3N doubles. */
+int epi_get_state(const epi_state *st, double *q);
+/* Number of steps taken. */
+int64_t epi_num_steps(const epi_state *st);
+int epi_destroy(epi_state *st);
+
+/* Kernel timing with HIP events, for measurement.  While enabled, every
+ * kernel the library launches on the context's stream is bracketed by a pair
+ * of events, classified by kind:
+ *   DFR_K_JV_ARNOLDI  complex-step DFR kernel with the fused Arnoldi epilogue
+ *   DFR_K_JV          complex-step DFR kernel (plain J*v, EPI remainder terms)
+ *   DFR_K_RHS         real DFR kernel F(q)
+ *   DFR_K_UPDATE      Gram-Schmidt update / normalisation kernel
+ *   DFR_K_EXPM        small exponential (one workgroup)
+ *   DFR_K_OTHER       vector kernels (start, combine, axpby, norms, checks)
+ * dfr_timing_enable(ctx, 1) clears the totals; dfr_timing_read synchronises
+ * and returns the summed duration (ms) and launch count of one kind. */
+enum { DFR_K_JV_ARNOLDI = 0, DFR_K_JV = 1, DFR_K_RHS = 2, DFR_K_UPDATE = 3, DFR_K_EXPM = 4, DFR_K_OTHER = 5,
+       DFR_K_NKINDS = 6 };
+int dfr_timing_enable(dfr_ctx *ctx, int enable);
+int dfr_timing_read(dfr_ctx *ctx, int kind, double *total_ms, int64_t *launches);
+
+const char *dfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFRSW_H */

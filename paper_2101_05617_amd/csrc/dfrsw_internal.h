@@ -1,0 +1,150 @@
+// Internal declarations of the MI355X DFR shallow-water library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dfrsw.h"
+
+namespace dfrsw {
+
+constexpr int MAX_NS = 8;        // p <= 7
+constexpr int MAX_M = 64;        // Krylov dimension cap
+constexpr int MAX_P = 8;         // phi-functions in one combination
+constexpr int BLOCK = 256;       // threads per block of the DFR and vector kernels
+
+void set_error(const std::string &msg);
+
+#define DFR_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::dfrsw::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+      return DFR_E_HIP;                                                             \
+    }                                                                               \
+  } while (0)
+
+// 1-D operators on the Gauss-Legendre points (Sec. 3.1).
+struct Ops1D {
+  double Dt[MAX_NS][MAX_NS + 2];   // derivative of the extended interpolant at the GL points
+  double lm[MAX_NS], lp[MAX_NS];   // Lagrange basis at xi = -1, +1
+};
+
+// Per-abscissa tangent data: X = tan x, 1 + X^2, 1/(1 + X^2).
+struct Tan3 {
+  double x, ax, rax, pad;
+};
+
+// Everything the DFR kernel needs about the grid (passed by value).
+struct GridArgs {
+  int ne;
+  int64_t nelem;          // 6 ne^2
+  int64_t n;              // nodes
+  double g_red;           // gravity / radius^2
+  double omega;
+  double two_over_delta;  // 2 / element width in x
+  double cA[6], cB[6], cC[6];      // Coriolis factor A + X B + Y C per panel
+  int nb_q[6][4], nb_e[6][4], nb_rev[6][4];   // panel-edge neighbours
+  const Tan3 *tnode;      // ne*ns abscissae of GL nodes
+  const double *tedge;    // ne+1 element-edge tangents
+  const double *xform;    // [6][4][ne*ns][4]: own <- neighbour contravariant map at panel edges
+  const double *orog;     // NULL or [2][N]: (g/a^2) (h^{i1} dhB_1 + h^{i2} dhB_2) * a^2 ... per node
+  int *err_flag;          // latched kernel error (vector atomics only)
+};
+
+// Optional Arnoldi epilogue of the J*v kernel (KIOPS iteration).
+struct ArnoldiArgs {
+  int on;                 // 0: plain J*v
+  int j;                  // index of the basis vector being multiplied
+  int p;                  // number of W columns
+  const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
+  const double *vprev;    // V_{j-1} (normalised) or NULL
+  double *partials;       // [gridDim][2]
+  unsigned *counter;
+  struct KDev *kd;
+  double tol;
+};
+
+// Device-side KIOPS state (one per context).
+struct KDev {
+  double H[(MAX_M + 2) * (MAX_M + 2)];     // Hessenberg, row-major, ld = MAX_M + 2
+  double sigma[MAX_M + 2];                 // scale of the stored (unnormalised) top vectors
+  double bot[(MAX_M + 2) * MAX_P];         // bottom blocks (true values)
+  double beta;
+  double wnorm2_bot;
+  double E0[MAX_M + 2];                    // first column of the small exponential
+  double err;                              // error estimate of the last exponential
+  double hlast;                            // h_{J,J-1}
+  double eJ;                               // E[J-1][J]
+  int J;
+  int happy;
+  int pad[2];
+};
+
+// Result block copied to the host after each small exponential.
+struct KHost {
+  double err, beta, hlast, eJ;
+  int J, happy, pad[2];
+};
+
+struct Ctx {
+  int ne, ns, p_deg;
+  int64_t n, nelem;
+  double radius, omega, gravity;
+  double lam0, phi0, alp0;
+  hipStream_t stream;
+  int device;
+  // host geometry
+  std::vector<double> xi, wgl;
+  Ops1D ops;
+  double ec[6][3], e1[6][3], e2[6][3];
+  GridArgs ga;
+  // device buffers
+  Tan3 *d_tnode = nullptr;
+  double *d_tedge = nullptr, *d_xform = nullptr, *d_orog = nullptr;
+  int *d_err = nullptr;
+  // KIOPS workspace
+  int kiops_mmax = 0, kiops_p = 0;
+  int max_m = MAX_M;              // Krylov cap from the LDS available to one workgroup
+  double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N
+  double *d_W = nullptr;          // MAX_P scaled b columns of 3N
+  double *d_partials = nullptr;   // per-block partial sums
+  unsigned *d_counter = nullptr;
+  KDev *d_kd = nullptr;
+  double *d_expm_scratch = nullptr;
+  KHost *h_res = nullptr;         // pinned
+  double *d_qf32 = nullptr;       // FP32 copy of the linearisation state (as float*)
+  double *d_tmp = nullptr;        // scratch vector 3N
+  // optional per-kernel event timing
+  bool timing = false;
+  struct EvPair { hipEvent_t a, b; int kind; };
+  std::vector<EvPair> evpool;
+  size_t evused = 0;
+  double t_ms[DFR_K_NKINDS] = {0};
+  int64_t t_n[DFR_K_NKINDS] = {0};
+};
+
+// event bracket around one launch (no-op unless timing is enabled)
+void tbegin(Ctx *c, int kind);
+void tend(Ctx *c);
+
+// kernels.hip
+int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const double *vscale,
+               double eps, bool complex_step, bool fp32, double *out, const ArnoldiArgs *ar);
+int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out);
+int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, double tol);
+int launch_start(Ctx *c, const double *x, double *v0, int p, const double *ybot);
+int launch_combine(Ctx *c, double *x);
+int launch_expm(Ctx *c, double tau);
+int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
+int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
+int launch_check_state(Ctx *c, const double *q);
+
+}  // namespace dfrsw
+
+struct dfr_ctx {
+  dfrsw::Ctx c;
+};

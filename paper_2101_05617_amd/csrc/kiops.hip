@@ -1,0 +1,545 @@
+// KIOPS-type adaptive Krylov evaluation of phi-combinations (Eq. 29) and the
+// multistep EPI integrators (Sec. 4, Eqs. 25, 30, 34-38) on the GPU.
+//
+// Host code here only takes control decisions (sub-step size tau, Krylov
+// dimension m, accept/reject) from a few scalars read back once per small
+// exponential; every vector operation, inner product, norm, the Hessenberg
+// matrix and its exponential live on the device.
+//
+// Controller (the paper defers KIOPS's internals to its own publication; this
+// is a complete statement of the one used here):
+//   augmented operator A~ = [[J, W], [0, K]], W = nu [b_p .. b_1], bottom
+//     state mu y(t), y(t) = (t^{p-1}/(p-1)!, .., t, 1), nu = 2^-e, mu = 2^e,
+//     e = ceil(log2 max_k ||b_k||) (k >= 1); p = 0 runs as p = 1, b_1 = 0
+//   Arnoldi with incomplete orthogonalisation against the last iop (<= 2)
+//     vectors, classical Gram-Schmidt; happy breakdown if ||w|| < tol
+//   E = exp(tau [[H_J, e_1], [0, 0]]); x(t+tau) = beta V_J E[:J, 0];
+//     err = beta h_{J+1,J} |E[J-1, J]|
+//   omega = (tau_out/tau) err / (tol beta_0), accept if omega <= 1.2
+//   order q = log(omega/omega_old)/log(tau/tau_old) (>= 1) after a rejection
+//     with equal m, else J/4; rate k = (omega/omega_old)^(1/(m_old-m)) (>= 1.1)
+//     after a rejection with equal tau, else 2
+//   tau_opt = clamp(tau (0.2/omega)^(1/q), tau/5, 5 tau) <= remaining
+//   m_opt = clamp(ceil(J + log(omega/0.2)/log k), max(m_min, floor(3m/4)),
+//                 min(m_max, ceil(4m/3)))
+//   J == m_max: reject -> tau_new = max(tau/5, tau (0.6/omega)^(1/q)), m = J;
+//               accept -> tau_new = tau_opt; otherwise m_new = m_opt, tau kept
+//   a rejected attempt keeps the basis (larger m continues Arnoldi)
+#include "dfrsw_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace dfrsw {
+
+int latched_error(Ctx &c);
+
+// ||x||_2^2 of several vectors, one after the other, into out[k] (device)
+__global__ __launch_bounds__(BLOCK) void norm2_kernel(int64_t n, const double *x, double *partials, unsigned *counter,
+                                                      double *out) {
+  __shared__ double red[BLOCK / 64];
+  __shared__ bool last;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) acc += x[i] * x[i];
+  // block reduction
+  {
+    double v = acc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
+      partials[blockIdx.x] = s;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (unsigned k = 0; k < gridDim.x; ++k) s += __builtin_nontemporal_load(partials + k);
+      *out = s;
+      *counter = 0u;
+    }
+  }
+}
+
+static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
+  const int64_t n3 = 3 * c.n;
+  int64_t b = (n3 + BLOCK - 1) / BLOCK;
+  if (b > 2048) b = 2048;
+  double *d_out = (double *)c.d_expm_scratch;   // KHost block reused as 4 doubles
+  double got[MAX_P + 1];
+  for (int i = 0; i < k; ++i) {
+    if (!x[i]) {
+      got[i] = 0.0;
+      continue;
+    }
+    tbegin(&c, DFR_K_OTHER);
+    hipLaunchKernelGGL(norm2_kernel, dim3((unsigned)b), dim3(BLOCK), 0, c.stream, n3, x[i], c.d_partials, c.d_counter,
+                       d_out);
+    tend(&c);
+    DFR_HIP(hipGetLastError());
+    DFR_HIP(hipMemcpyAsync(&got[i], d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    DFR_HIP(hipStreamSynchronize(c.stream));
+  }
+  for (int i = 0; i < k; ++i) host_out[i] = got[i];
+  return DFR_OK;
+}
+
+struct KiopsRun {
+  int n_matvec = 0, n_substeps = 0, n_rejected = 0, m_last = 0, happy = 0, n_expm = 0;
+};
+
+static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out, int n_phi, const double *const *b,
+                      const kiops_opts &o, double eps, bool fp32, double *w, KiopsRun &st) {
+  const int64_t n3 = 3 * c.n;
+  if (!(tau_out > 0.0) || !(o.tol > 0.0) || o.m_max < 1 || o.m_max > MAX_M || o.m_min < 1 || o.iop < 1 ||
+      n_phi < 0 || n_phi > MAX_P) {
+    set_error("kiops: invalid options (need tau > 0, tol > 0, 1 <= m_min, m_max <= 64, iop >= 1, n_phi <= 8)");
+    return DFR_E_INVAL;
+  }
+  if (o.m_max > c.max_m) {
+    set_error("kiops: m_max exceeds the Krylov dimension this device supports (" + std::to_string(c.max_m) + ")");
+    return DFR_E_INVAL;
+  }
+  const bool b0_absent = (b[0] == nullptr);
+  int p = n_phi;
+  // norms of b_0..b_p
+  double nrm2[MAX_P + 1];
+  int rc = norms2(c, n_phi + 1, b, nrm2);
+  if (rc) return rc;
+  double nb = 0.0;
+  for (int k = 1; k <= n_phi; ++k) nb = std::max(nb, std::sqrt(nrm2[k]));
+  if (nb == 0.0 && nrm2[0] == 0.0) {
+    DFR_HIP(hipMemsetAsync(w, 0, sizeof(double) * n3, c.stream));
+    DFR_HIP(hipStreamSynchronize(c.stream));
+    return DFR_OK;
+  }
+  double nu = 1.0, mu = 1.0;
+  if (nb > 0.0) {
+    const int e = (int)std::ceil(std::log2(nb));
+    nu = std::ldexp(1.0, -e);
+    mu = std::ldexp(1.0, e);
+  }
+  if (p == 0) {
+    p = 1;
+    DFR_HIP(hipMemsetAsync(c.d_W, 0, sizeof(double) * n3, c.stream));
+  } else {
+    for (int k = 0; k < p; ++k) {
+      const double *bk = b[p - k];
+      if (bk) rc = launch_axpby(&c, n3, nu, bk, 0.0, nullptr, c.d_W + k * n3);
+      else {
+        DFR_HIP(hipMemsetAsync(c.d_W + k * n3, 0, sizeof(double) * n3, c.stream));
+        rc = DFR_OK;
+      }
+      if (rc) return rc;
+    }
+  }
+  c.kiops_p = p;
+  if (b0_absent) {
+    DFR_HIP(hipMemsetAsync(w, 0, sizeof(double) * n3, c.stream));
+  } else {
+    DFR_HIP(hipMemcpyAsync(w, b[0], sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
+  }
+
+  const double DELTA = 1.2, GAMMA = 0.2, GAMMA_MMAX = 0.6;
+  const int m_max = o.m_max, m_min = std::min(o.m_min, o.m_max);
+  c.kiops_mmax = m_max;
+  int m = std::max(m_min, std::min(o.m_init, m_max));
+  double t = 0.0, tau = tau_out;
+  int j = 0;
+  double beta0 = -1.0;
+  int ireject = 0;
+  double old_tau = 0.0, old_omega = 0.0;
+  int old_m = -1;
+  int attempts = 0;
+  double *V = c.d_V;
+  KDev *kd = c.d_kd;
+
+  while (t < tau_out) {
+    if (++attempts > o.max_attempts) {
+      set_error("kiops: no convergence within max_attempts");
+      return DFR_E_KIOPS;
+    }
+    const int j_sweep = j;
+    bool skipped = false;
+    if (j == 0) {
+      double y[MAX_P];
+      for (int k = 0; k < p; ++k) {
+        const int pw = p - 1 - k;
+        double f = 1.0;
+        for (int i = 2; i <= pw; ++i) f *= i;
+        y[k] = mu * std::pow(t, (double)pw) / f;
+      }
+      rc = launch_start(&c, w, V, p, y);
+      if (rc) return rc;
+    }
+    while (j < m) {
+      ArnoldiArgs ar{};
+      ar.on = 1;
+      ar.j = j;
+      ar.p = p;
+      for (int k = 0; k < p; ++k) ar.W[k] = c.d_W + k * n3;
+      ar.vprev = (j >= 1 && o.iop >= 2) ? V + (int64_t)(j - 1) * n3 : nullptr;
+      ar.partials = c.d_partials;
+      ar.counter = c.d_counter;
+      ar.kd = kd;
+      ar.tol = o.tol;
+      double *out = V + (int64_t)(j + 1) * n3;
+      if (j == 0 && t == 0.0 && b0_absent) {
+        rc = launch_arnoldi_first(&c, ar, out);
+        skipped = true;
+      } else {
+        rc = launch_dfr(&c, q, q32, V + (int64_t)j * n3, &kd->sigma[j], eps, true, fp32, out, &ar);
+      }
+      if (rc) return rc;
+      rc = launch_update(&c, j, out, V + (int64_t)j * n3, ar.vprev, o.tol);
+      if (rc) return rc;
+      ++j;
+    }
+    rc = launch_expm(&c, tau);
+    if (rc) return rc;
+    DFR_HIP(hipMemcpyAsync(c.h_res, c.d_expm_scratch, sizeof(KHost), hipMemcpyDeviceToHost, c.stream));
+    DFR_HIP(hipStreamSynchronize(c.stream));
+    st.n_expm++;
+    const KHost r = *c.h_res;
+    const int J = r.J;
+    st.n_matvec += (J - j_sweep) - (skipped ? 1 : 0);
+    if (beta0 < 0.0) beta0 = r.beta;
+    if (!std::isfinite(r.err) || !std::isfinite(r.beta)) {
+      set_error("kiops: non-finite Krylov quantities");
+      int le = latched_error(c);
+      return le ? le : DFR_E_NONFINITE;
+    }
+    bool accept;
+    double omega, tau_new;
+    int m_new;
+    if (r.happy) {
+      j = J;
+      omega = 0.0;
+      accept = true;
+      m_new = m;
+      tau_new = std::min(tau_out - (t + tau), tau);
+      st.happy = 1;
+    } else {
+      omega = (tau_out / tau) * r.err / (o.tol * beta0);
+      omega = std::max(omega, 1e-300);
+      accept = omega <= DELTA;
+      double order;
+      if (ireject >= 1 && m == old_m && tau != old_tau)
+        order = std::max(1.0, std::log(omega / old_omega) / std::log(tau / old_tau));
+      else
+        order = J / 4.0;
+      double kest;
+      if (ireject >= 1 && m != old_m && tau == old_tau)
+        kest = std::max(1.1, std::pow(omega / old_omega, 1.0 / (old_m - m)));
+      else
+        kest = 2.0;
+      const double remaining = accept ? tau_out - (t + tau) : tau_out - t;
+      double tau_opt = tau * std::pow(GAMMA / omega, 1.0 / order);
+      tau_opt = std::min(remaining, std::max(tau / 5.0, std::min(5.0 * tau, tau_opt)));
+      int m_opt = (int)std::ceil(J + std::log(omega / GAMMA) / std::log(kest));
+      m_opt = std::max(m_min, std::min(m_max, std::max((int)std::floor(0.75 * m),
+                                                        std::min(m_opt, (int)std::ceil(4.0 * m / 3.0)))));
+      if (J == m_max) {
+        if (omega > DELTA) {
+          m_new = J;
+          tau_new = tau * std::pow(GAMMA_MMAX / omega, 1.0 / order);
+          tau_new = std::min(remaining, std::max(tau / 5.0, tau_new));
+        } else {
+          m_new = m;
+          tau_new = tau_opt;
+        }
+      } else {
+        m_new = m_opt;
+        tau_new = std::min(remaining, tau);
+      }
+    }
+    if (accept) {
+      rc = launch_combine(&c, w);
+      if (rc) return rc;
+      if (tau >= tau_out - t) t = tau_out;
+      else t = t + tau;
+      st.n_substeps++;
+      st.m_last = J;
+      j = 0;
+      ireject = 0;
+    } else {
+      ireject++;
+      st.n_rejected++;
+    }
+    old_tau = tau;
+    old_m = m;
+    old_omega = omega;
+    tau = tau_new;
+    m = m_new;
+    if (t < tau_out && !(tau > 0.0)) {
+      set_error("kiops: step size collapsed");
+      return DFR_E_KIOPS;
+    }
+  }
+  DFR_HIP(hipStreamSynchronize(c.stream));
+  return latched_error(c);
+}
+
+// ---------------------------------------------------------------------------
+// EPI
+}  // namespace dfrsw
+
+struct epi_state {
+  dfrsw::Ctx *c;
+  int order, P, M;
+  double dt;
+  int s;
+  double eps;
+  dfr_precision prec;
+  int64_t nsteps;
+  double *q, *F, *qs, *w, *d, *jd;
+  std::vector<double *> hq, hF, R, bm;
+  std::vector<std::vector<double>> A;   // alpha_{m,i}
+};
+
+namespace dfrsw {
+
+// Eq. (30) and Eqs. (36)-(38): rows m = 1..M, columns i = 1..P
+static void epi_table(int order, std::vector<std::vector<double>> &A) {
+  A.clear();
+  switch (order) {
+    case 3: A = {{0.0}, {2.0 / 3.0}}; break;
+    case 4: A = {{0.0, 0.0}, {-3.0 / 10.0, 3.0 / 40.0}, {32.0 / 5.0, -11.0 / 10.0}}; break;
+    case 5:
+      A = {{0.0, 0.0, 0.0}, {-4.0 / 5.0, 2.0 / 5.0, -4.0 / 45.0}, {12.0, -9.0 / 2.0, 8.0 / 9.0}, {3.0, 0.0, -1.0 / 3.0}};
+      break;
+    case 6:
+      A = {{0.0, 0.0, 0.0, 0.0},
+           {-49.0 / 60.0, 351.0 / 560.0, -359.0 / 1260.0, 367.0 / 6720.0},
+           {92.0 / 7.0, -99.0 / 14.0, 176.0 / 63.0, -1.0 / 2.0},
+           {485.0 / 21.0, -151.0 / 14.0, 23.0 / 9.0, -31.0 / 168.0}};
+      break;
+    default: break;
+  }
+}
+
+static void add_stats(kiops_stats *acc, const KiopsRun &r) {
+  if (!acc) return;
+  acc->n_matvec += r.n_matvec;
+  acc->n_substeps += r.n_substeps;
+  acc->n_rejected += r.n_rejected;
+  acc->m_last = r.m_last;
+  acc->happy |= r.happy;
+  acc->n_expm += r.n_expm;
+}
+
+static const float *prep_q32(Ctx &c, const double *q, bool fp32, int &rc) {
+  rc = DFR_OK;
+  if (!fp32) return nullptr;
+  rc = launch_copy_to_f32(&c, 3 * c.n, q, (float *)c.d_qf32);
+  return (const float *)c.d_qf32;
+}
+
+}  // namespace dfrsw
+
+using namespace dfrsw;
+
+extern "C" {
+
+int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, const double *const *b, const kiops_opts *o,
+                    double eps, dfr_precision prec, double *w, kiops_stats *stats) {
+  if (!h || !q || !b || !o || !w || !(eps > 0.0) || (prec != DFR_FP64 && prec != DFR_FP32_JV)) {
+    set_error("kiops_phi_apply: invalid argument");
+    return DFR_E_INVAL;
+  }
+  for (int k = 0; k <= n_phi && k <= MAX_P; ++k)
+    if (b[k] == w || q == w) {
+      set_error("kiops_phi_apply: w aliases an input");
+      return DFR_E_INVAL;
+    }
+  Ctx &c = h->c;
+  int rc = launch_check_state(&c, q);
+  if (rc) return rc;
+  const bool fp32 = prec == DFR_FP32_JV;
+  const float *q32 = prep_q32(c, q, fp32, rc);
+  if (rc) return rc;
+  KiopsRun r;
+  rc = kiops_core(c, q, q32, tau_out, n_phi, b, *o, eps, fp32, w, r);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    add_stats(stats, r);
+  }
+  return rc;
+}
+
+int epi_create(dfr_ctx *h, int order, double dt, int startup_substeps, const double *q0, double eps, dfr_precision prec,
+               epi_state **out) {
+  if (!h || !q0 || !out || order < 2 || order > 6 || !(dt > 0.0) || startup_substeps < 1 || !(eps > 0.0)) {
+    set_error("epi_create: invalid argument");
+    return DFR_E_INVAL;
+  }
+  *out = nullptr;
+  epi_state *st = new (std::nothrow) epi_state();
+  if (!st) return DFR_E_NOMEM;
+  Ctx &c = h->c;
+  st->c = &c;
+  st->order = order;
+  epi_table(order, st->A);
+  st->M = (int)st->A.size();
+  st->P = order == 2 ? 0 : (int)st->A[0].size();
+  st->dt = dt;
+  st->s = startup_substeps;
+  st->eps = eps;
+  st->prec = prec;
+  st->nsteps = 0;
+  const size_t bytes = sizeof(double) * 3 * c.n;
+  auto alloc = [&](double **p) { return hipMalloc(p, bytes) == hipSuccess; };
+  bool ok = alloc(&st->q) && alloc(&st->F) && alloc(&st->qs) && alloc(&st->w) && alloc(&st->d) && alloc(&st->jd);
+  for (int i = 0; ok && i < st->P; ++i) {
+    double *a, *b2, *r;
+    ok = alloc(&a) && alloc(&b2) && alloc(&r);
+    if (ok) {
+      st->hq.push_back(a);
+      st->hF.push_back(b2);
+      st->R.push_back(r);
+    }
+  }
+  for (int m = 0; ok && m < std::max(st->M, 1); ++m) {
+    double *a;
+    ok = alloc(&a);
+    if (ok) st->bm.push_back(a);
+  }
+  if (!ok) {
+    set_error("epi_create: out of device memory");
+    epi_destroy(st);
+    return DFR_E_NOMEM;
+  }
+  if (hipMemcpyAsync(st->q, q0, bytes, hipMemcpyDeviceToDevice, c.stream) != hipSuccess) {
+    epi_destroy(st);
+    set_error("epi_create: copy failed");
+    return DFR_E_HIP;
+  }
+  *out = st;
+  return DFR_OK;
+}
+
+int epi_destroy(epi_state *st) {
+  if (!st) return DFR_OK;
+  (void)hipStreamSynchronize(st->c->stream);
+  for (double *p : {st->q, st->F, st->qs, st->w, st->d, st->jd}) (void)hipFree(p);
+  for (double *p : st->hq) (void)hipFree(p);
+  for (double *p : st->hF) (void)hipFree(p);
+  for (double *p : st->R) (void)hipFree(p);
+  for (double *p : st->bm) (void)hipFree(p);
+  delete st;
+  return DFR_OK;
+}
+
+int64_t epi_num_steps(const epi_state *st) { return st ? st->nsteps : -1; }
+
+int epi_get_state(const epi_state *st, double *q) {
+  if (!st || !q) return DFR_E_INVAL;
+  Ctx &c = *st->c;
+  DFR_HIP(hipMemcpyAsync(q, st->q, sizeof(double) * 3 * c.n, hipMemcpyDeviceToDevice, c.stream));
+  return DFR_OK;
+}
+
+int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiops_stats *stats) {
+  if (!h || !st || !o || st->c != &h->c) {
+    set_error("epi_step: invalid argument");
+    return DFR_E_INVAL;
+  }
+  Ctx &c = h->c;
+  const int64_t n3 = 3 * c.n;
+  const bool fp32 = st->prec == DFR_FP32_JV;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  int rc = launch_check_state(&c, st->q);
+  if (rc) return rc;
+  rc = launch_dfr(&c, st->q, nullptr, nullptr, nullptr, 0.0, false, false, st->F, nullptr);
+  if (rc) return rc;
+  double *q_new = st->qs;
+  if (st->nsteps < st->P || st->order == 2) {
+    // EPI2 start-up (Eq. 25) with s sub-steps, or plain EPI2
+    const int s = st->order == 2 ? 1 : st->s;
+    const double hstep = st->dt / s;
+    DFR_HIP(hipMemcpyAsync(st->qs, st->q, sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
+    for (int k = 0; k < s; ++k) {
+      const double *Fs = st->F;
+      if (k > 0) {
+        rc = launch_dfr(&c, st->qs, nullptr, nullptr, nullptr, 0.0, false, false, st->d, nullptr);
+        if (rc) return rc;
+        Fs = st->d;
+      }
+      const float *q32 = prep_q32(c, st->qs, fp32, rc);
+      if (rc) return rc;
+      const double *bb[2] = {nullptr, Fs};
+      KiopsRun r;
+      rc = kiops_core(c, st->qs, q32, hstep, 1, bb, *o, st->eps, fp32, st->w, r);
+      add_stats(stats, r);
+      if (rc) return rc;
+      rc = launch_axpby(&c, n3, 1.0, st->qs, 1.0, st->w, st->qs);
+      if (rc) return rc;
+    }
+  } else {
+    const float *q32 = prep_q32(c, st->q, fp32, rc);
+    if (rc) return rc;
+    for (int i = 0; i < st->P; ++i) {
+      // R_i = F(q_{n-i}) - F_n - J_n (q_{n-i} - q_n)   (Eq. 33 generalised)
+      rc = launch_axpby(&c, n3, 1.0, st->hq[i], -1.0, st->q, st->d);
+      if (!rc) rc = launch_dfr(&c, st->q, q32, st->d, nullptr, st->eps, true, fp32, st->jd, nullptr);
+      if (!rc) rc = launch_axpby(&c, n3, 1.0, st->hF[i], -1.0, st->F, st->R[i]);
+      if (!rc) rc = launch_axpby(&c, n3, 1.0, st->R[i], -1.0, st->jd, st->R[i]);
+      if (rc) return rc;
+    }
+    // b_1 = F_n, b_m = sum_i alpha_{m,i} R_i / dt^{m-1}
+    std::vector<const double *> bb(st->M + 1, nullptr);
+    bb[1] = st->F;
+    for (int m = 2; m <= st->M; ++m) {
+      double *bm = st->bm[m - 1];
+      bool first = true;
+      for (int i = 1; i <= st->P; ++i) {
+        const double a = st->A[m - 1][i - 1];
+        if (a == 0.0) continue;
+        if (first) rc = launch_axpby(&c, n3, a, st->R[i - 1], 0.0, nullptr, bm);
+        else rc = launch_axpby(&c, n3, 1.0, bm, a, st->R[i - 1], bm);
+        if (rc) return rc;
+        first = false;
+      }
+      if (first) DFR_HIP(hipMemsetAsync(bm, 0, sizeof(double) * n3, c.stream));
+      rc = launch_axpby(&c, n3, 1.0 / std::pow(st->dt, (double)(m - 1)), bm, 0.0, nullptr, bm);
+      if (rc) return rc;
+      bb[m] = bm;
+    }
+    KiopsRun r;
+    rc = kiops_core(c, st->q, q32, st->dt, st->M, bb.data(), *o, st->eps, fp32, st->w, r);
+    add_stats(stats, r);
+    if (rc) return rc;
+    rc = launch_axpby(&c, n3, 1.0, st->q, 1.0, st->w, st->qs);
+    if (rc) return rc;
+  }
+  // history: (q_n, F_n) becomes entry 1; q_{n+1} becomes current
+  if (st->P > 0) {
+    double *oq = st->hq.back(), *oF = st->hF.back();
+    for (int i = st->P - 1; i > 0; --i) {
+      st->hq[i] = st->hq[i - 1];
+      st->hF[i] = st->hF[i - 1];
+    }
+    st->hq[0] = st->q;
+    st->hF[0] = st->F;
+    st->q = q_new;
+    st->qs = oq;
+    st->F = oF;
+  } else {
+    std::swap(st->q, st->qs);
+  }
+  st->nsteps++;
+  if (q_out) DFR_HIP(hipMemcpyAsync(q_out, st->q, sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
+  DFR_HIP(hipStreamSynchronize(c.stream));
+  return latched_error(c);
+}
+
+}  // extern "C"

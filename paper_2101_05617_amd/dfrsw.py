@@ -1,0 +1,253 @@
+"""Python binding of the MI355X library ``libdfrsw.so`` (C ABI in include/dfrsw.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device vectors are torch tensors (float64, contiguous, on the
+current HIP device); the library's work is enqueued on torch's current stream.
+If the shared library is missing or cannot be loaded, every entry point raises
+-- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfrsw.so")
+
+DFR_FP64 = 0
+DFR_FP32_JV = 1
+_PREC = {"fp64": DFR_FP64, "fp32_jv": DFR_FP32_JV, DFR_FP64: DFR_FP64, DFR_FP32_JV: DFR_FP32_JV}
+
+ERRORS = {-1: "DFR_E_INVAL", -2: "DFR_E_NOMEM", -3: "DFR_E_HIP", -4: "DFR_E_NONFINITE", -5: "DFR_E_DEPTH",
+          -6: "DFR_E_KIOPS"}
+
+
+class DfrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _GridDesc(ctypes.Structure):
+    _fields_ = [("ne", ctypes.c_int), ("p", ctypes.c_int), ("radius", ctypes.c_double),
+                ("omega", ctypes.c_double), ("gravity", ctypes.c_double), ("lambda0", ctypes.c_double),
+                ("phi0", ctypes.c_double), ("alpha0", ctypes.c_double), ("hB", ctypes.c_void_p)]
+
+
+class KiopsOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("m_init", ctypes.c_int), ("m_min", ctypes.c_int),
+                ("m_max", ctypes.c_int), ("iop", ctypes.c_int), ("max_attempts", ctypes.c_int)]
+
+
+class KiopsStats(ctypes.Structure):
+    _fields_ = [("n_matvec", ctypes.c_int), ("n_substeps", ctypes.c_int), ("n_rejected", ctypes.c_int),
+                ("m_last", ctypes.c_int), ("happy", ctypes.c_int), ("n_expm", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def kiops_opts(tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2, max_attempts=1000):
+    return KiopsOpts(tol, m_init, m_min, m_max, iop, max_attempts)
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+        sig = {
+            "dfr_create": (i, [ctypes.POINTER(_GridDesc), vp, ctypes.POINTER(vp)]),
+            "dfr_destroy": (i, [vp]),
+            "dfr_num_nodes": (i64, [vp]),
+            "dfr_node_frames": (i, [vp, vp, vp, vp]),
+            "dfr_sync": (i, [vp]),
+            "dfr_rhs": (i, [vp, vp, vp]),
+            "dfr_jvp_complex_step": (i, [vp, vp, vp, d, i, vp]),
+            "kiops_phi_apply": (i, [vp, vp, d, i, ctypes.POINTER(vp), ctypes.POINTER(KiopsOpts), d, i, vp,
+                                    ctypes.POINTER(KiopsStats)]),
+            "epi_create": (i, [vp, i, d, i, vp, d, i, ctypes.POINTER(vp)]),
+            "epi_step": (i, [vp, vp, ctypes.POINTER(KiopsOpts), vp, ctypes.POINTER(KiopsStats)]),
+            "epi_get_state": (i, [vp, vp]),
+            "epi_num_steps": (i64, [vp]),
+            "epi_destroy": (i, [vp]),
+            "dfr_timing_enable": (i, [vp, i]),
+            "dfr_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64)]),
+            "dfr_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
+            "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
+            "epi_num_steps", "epi_destroy", "dfr_timing_enable", "dfr_timing_read", "dfr_last_error"]
+
+
+def _check(rc):
+    if rc != 0:
+        raise DfrError(rc, lib().dfr_last_error().decode())
+
+
+def _dev(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Grid:
+    """A dfr_ctx: one rotated cubed-sphere DFR discretisation on the GPU."""
+
+    def __init__(self, ne, p, radius=1.0, omega=1.0, gravity=1.0, rotation=(0.0, np.pi / 4, 0.0), hB=None):
+        self.ne, self.p, self.ns = int(ne), int(p), int(p) + 1
+        self._hb = None if hB is None else np.ascontiguousarray(hB, dtype=np.float64)
+        desc = _GridDesc(self.ne, self.p, float(radius), float(omega), float(gravity), *map(float, rotation),
+                         None if self._hb is None else self._hb.ctypes.data_as(ctypes.c_void_p))
+        h = ctypes.c_void_p()
+        _check(lib().dfr_create(ctypes.byref(desc), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.N = int(lib().dfr_num_nodes(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dfr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def node_frames(self):
+        P, B1, B2 = (np.empty((self.N, 3)) for _ in range(3))
+        _check(lib().dfr_node_frames(self._h, *(a.ctypes.data_as(ctypes.c_void_p) for a in (P, B1, B2))))
+        return P, B1, B2
+
+    def empty(self):
+        import torch
+        return torch.empty(3 * self.N, dtype=torch.float64, device="cuda")
+
+
+# ---- entry points with the names of the C ABI ---------------------------------
+
+def dfr_sync(g: Grid):
+    _check(lib().dfr_sync(g.handle))
+
+
+def dfr_rhs(g: Grid, q, dqdt=None):
+    dqdt = g.empty() if dqdt is None else dqdt
+    _check(lib().dfr_rhs(g.handle, _dev(q), _dev(dqdt)))
+    return dqdt
+
+
+def dfr_jvp_complex_step(g: Grid, q, v, eps=1e-150, prec="fp64", jv=None):
+    jv = g.empty() if jv is None else jv
+    _check(lib().dfr_jvp_complex_step(g.handle, _dev(q), _dev(v), float(eps), _PREC[prec], _dev(jv)))
+    return jv
+
+
+def kiops_phi_apply(g: Grid, q_lin, tau_out, bs, opts=None, eps=1e-150, prec="fp64", w=None):
+    """w = sum_k tau^k phi_k(tau J(q_lin)) b_k for bs = [b_0 (or None), b_1, ...]."""
+    opts = opts or kiops_opts()
+    w = g.empty() if w is None else w
+    arr = (ctypes.c_void_p * len(bs))(*[None if b is None else _dev(b).value for b in bs])
+    st = KiopsStats()
+    _check(lib().kiops_phi_apply(g.handle, _dev(q_lin), float(tau_out), len(bs) - 1, arr, ctypes.byref(opts),
+                                 float(eps), _PREC[prec], _dev(w), ctypes.byref(st)))
+    return w, st.as_dict()
+
+
+class EpiState:
+    """An epi_state: multistep EPI integrator with its history on the GPU."""
+
+    def __init__(self, g: Grid, order, dt, q0, startup_substeps=10, eps=1e-150, prec="fp64"):
+        self.g = g
+        h = ctypes.c_void_p()
+        _check(lib().epi_create(g.handle, int(order), float(dt), int(startup_substeps), _dev(q0), float(eps),
+                                _PREC[prec], ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().epi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+KERNEL_KINDS = {"jv_arnoldi": 0, "jv": 1, "rhs": 2, "update": 3, "expm": 4, "other": 5}
+
+
+def dfr_timing_enable(g: Grid, enable=True):
+    _check(lib().dfr_timing_enable(g.handle, int(bool(enable))))
+
+
+def dfr_timing_read(g: Grid, kind):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().dfr_timing_read(g.handle, KERNEL_KINDS.get(kind, kind), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def epi_create(g: Grid, order, dt, q0, startup_substeps=10, eps=1e-150, prec="fp64"):
+    return EpiState(g, order, dt, q0, startup_substeps, eps, prec)
+
+
+def epi_step(g: Grid, st: EpiState, opts=None, q_out=None):
+    opts = opts or kiops_opts()
+    s = KiopsStats()
+    _check(lib().epi_step(g.handle, st.handle, ctypes.byref(opts), None if q_out is None else _dev(q_out),
+                          ctypes.byref(s)))
+    return s.as_dict()
+
+
+def epi_get_state(st: EpiState, q=None):
+    q = st.g.empty() if q is None else q
+    _check(lib().epi_get_state(st.handle, _dev(q)))
+    return q
+
+
+def epi_num_steps(st: EpiState):
+    return int(lib().epi_num_steps(st.handle))
+
+
+@dataclass
+class Loaded:
+    path: str
+
+
+def loaded_library():
+    lib()
+    return Loaded(LIB_PATH)

@@ -139,43 +139,59 @@ def great_circle(P, lon_c, lat_c):
     return np.arccos(np.clip(P @ c, -1.0, 1.0))
 
 
-def real_sph_harm(lmax, P):
-    """Real orthonormal spherical harmonics Y_lm, 1 <= l <= lmax, m = -l..l,
-    in (l, m) order, at unit vectors P.  Returns an array (n_lm, n_points)."""
+def _sph_harm_rows(lmax, P):
+    """Yield the real orthonormal spherical harmonics Y_lm, 1 <= l <= lmax,
+    m = -l..l, in (l, m) order, evaluated at unit vectors P (one row at a time)."""
     P = np.asarray(P)
     ct = np.clip(P[:, 2], -1.0, 1.0)
     st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
     ph = np.arctan2(P[:, 1], P[:, 0])
-    # fully normalised associated Legendre functions Pbar[l][m]
+    # fully normalised associated Legendre functions, column by column in m
     Pb = {}
-    Pb[(0, 0)] = np.full_like(ct, math.sqrt(1.0 / (4.0 * math.pi)))
-    for m in range(1, lmax + 1):
-        Pb[(m, m)] = -math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * Pb[(m - 1, m - 1)]
-    for m in range(0, lmax):
-        Pb[(m + 1, m)] = math.sqrt(2.0 * m + 3.0) * ct * Pb[(m, m)]
+    pmm = np.full_like(ct, math.sqrt(1.0 / (4.0 * math.pi)))
     for m in range(0, lmax + 1):
+        if m > 0:
+            pmm = -math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm
+        Pb[(m, m)] = pmm
+        if m + 1 <= lmax:
+            Pb[(m + 1, m)] = math.sqrt(2.0 * m + 3.0) * ct * pmm
         for l in range(m + 2, lmax + 1):
             a = math.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
             b = math.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
             Pb[(l, m)] = a * (ct * Pb[(l - 1, m)] - b * Pb[(l - 2, m)])
-    rows = []
+    cs = {m: (np.cos(m * ph), np.sin(m * ph)) for m in range(1, lmax + 1)}
     for l in range(1, lmax + 1):
         for m in range(-l, l + 1):
             if m < 0:
-                rows.append(math.sqrt(2.0) * Pb[(l, -m)] * np.sin(-m * ph))
+                yield math.sqrt(2.0) * Pb[(l, -m)] * cs[-m][1]
             elif m == 0:
-                rows.append(Pb[(l, 0)])
+                yield Pb[(l, 0)]
             else:
-                rows.append(math.sqrt(2.0) * Pb[(l, m)] * np.cos(m * ph))
-    return np.array(rows)
+                yield math.sqrt(2.0) * Pb[(l, m)] * cs[m][0]
+
+
+def n_sph_harm(lmax):
+    return (lmax + 1) ** 2 - 1
+
+
+def real_sph_harm(lmax, P):
+    """All Y_lm (1 <= l <= lmax) at P as an array (n_lm, n_points)."""
+    return np.array(list(_sph_harm_rows(lmax, P)))
+
+
+def sph_harm_sum(coef, lmax, P):
+    """sum_lm coef_lm Y_lm(P), accumulated row by row."""
+    out = np.zeros(np.asarray(P).shape[0])
+    for c, row in zip(coef, _sph_harm_rows(lmax, P)):
+        out += c * row
+    return out
 
 
 def random_field(rng, lmax, P):
     """sum of Y_lm with N(0,1) coefficients drawn in (l, m) order, scaled to
     max |field| = 1 over the given points."""
-    Y = real_sph_harm(lmax, P)
-    c = rng.standard_normal(Y.shape[0])
-    f = c @ Y
+    c = rng.standard_normal(n_sph_harm(lmax))
+    f = sph_harm_sum(c, lmax, P)
     return f / np.max(np.abs(f))
 
 
@@ -183,13 +199,11 @@ def _stream_wind(rng, lmax, P):
     """Non-divergent wind r x grad(psi) of a random stream function, scaled to
     max |V| = 1.  The tangential gradient is the 3-D gradient of the
     zero-homogeneous extension psi(x/|x|), by central differences."""
-    Y_coef = None
-    lm_rows = real_sph_harm(lmax, P).shape[0]
-    Y_coef = rng.standard_normal(lm_rows)
+    coef = rng.standard_normal(n_sph_harm(lmax))
 
     def psi(X):
         Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
-        return Y_coef @ real_sph_harm(lmax, Xn)
+        return sph_harm_sum(coef, lmax, Xn)
 
     h = 1e-5
     grad = np.zeros_like(P)
@@ -261,12 +275,7 @@ def initial_state(w: Workload, P, B1, B2):
         gh = _balanced_gh(lat, w.u0, w.gh0)
         ul = w.u0 * np.cos(lat)
         V = ul[:, None] * E
-        h = gh / GRAVITY
-        if w.h_amp > 0.0:
-            h = h + w.h_amp * w.h_scale * random_field(rng, w.h_lmax, P)
-        if w.u_amp > 0.0:
-            V = V + w.u_amp * _stream_wind(rng, w.h_lmax, P)
-        H = h
+        H = gh / GRAVITY
     elif w.kind == "jet":
         lon_c = rng.uniform(0.0, 2.0 * math.pi)
         gh = _jet_gh(lat, w.gh0)
@@ -283,6 +292,11 @@ def initial_state(w: Workload, P, B1, B2):
         hB = hb / w.h_scale
     else:
         raise ValueError(w.kind)
+    # seeded perturbations (drawn after the kind-specific draws)
+    if w.h_amp > 0.0:
+        H = H + w.h_amp * w.h_scale * random_field(rng, w.h_lmax, P)
+    if w.u_amp > 0.0:
+        V = V + w.u_amp * _stream_wind(rng, max(w.h_lmax, 1), P)
     # V in m/s -> rad/s on the unit sphere -> nondimensional (time unit 1/Omega)
     u1, u2 = wind_to_contravariant(P, B1, B2, V / a)
     Hn = H / w.h_scale
