@@ -147,10 +147,11 @@ int epi_destroy(epi_state *st);
  *   DFR_K_UPDATE      Gram-Schmidt update / normalisation kernel
  *   DFR_K_EXPM        small exponential (one workgroup)
  *   DFR_K_OTHER       vector kernels (start, combine, axpby, norms, checks)
+ *   DFR_K_FINALIZE    one-block reductions of per-block partial sums
  * dfr_timing_enable(ctx, 1) clears the totals; dfr_timing_read synchronises
  * and returns the summed duration (ms) and launch count of one kind. */
 enum { DFR_K_JV_ARNOLDI = 0, DFR_K_JV = 1, DFR_K_RHS = 2, DFR_K_UPDATE = 3, DFR_K_EXPM = 4, DFR_K_OTHER = 5,
-       DFR_K_NKINDS = 6 };
+       DFR_K_FINALIZE = 6, DFR_K_NKINDS = 7 };
 int dfr_timing_enable(dfr_ctx *ctx, int enable);
 int dfr_timing_read(dfr_ctx *ctx, int kind, double *total_ms, int64_t *launches);
 

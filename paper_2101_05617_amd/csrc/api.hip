@@ -367,8 +367,8 @@ static int alloc_workspace(Ctx &c) {
   (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device);
   (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, c.device);
   lds = std::max(lds, lds_optin) - 1024;
-  int nmax = 1;
-  while (4 * (nmax + 1) * (nmax + 1) * (int)sizeof(double) <= lds) ++nmax;
+  int nmax = 1;   // largest n (= m + 1) whose padded size fits
+  while (4 * (((nmax + 1) + 3) & ~3) * (((nmax + 1) + 3) & ~3) * (int)sizeof(double) <= lds) ++nmax;
   c.max_m = std::min(MAX_M, nmax - 1);
   if (c.max_m < 2) {
     set_error("device LDS too small for the Krylov exponential");

@@ -63,7 +63,6 @@ struct ArnoldiArgs {
   const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
   const double *vprev;    // V_{j-1} (normalised) or NULL
   double *partials;       // [gridDim][2]
-  unsigned *counter;
   struct KDev *kd;
   double tol;
 };

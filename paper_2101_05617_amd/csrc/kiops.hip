@@ -35,38 +35,35 @@ namespace dfrsw {
 
 int latched_error(Ctx &c);
 
-// ||x||_2^2 of several vectors, one after the other, into out[k] (device)
-__global__ __launch_bounds__(BLOCK) void norm2_kernel(int64_t n, const double *x, double *partials, unsigned *counter,
-                                                      double *out) {
+// ||x||_2^2: per-block partial sums, then one block sums them in a fixed order
+__global__ __launch_bounds__(BLOCK) void norm2_kernel(int64_t n, const double *x, double *partials) {
   __shared__ double red[BLOCK / 64];
-  __shared__ bool last;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) acc += x[i] * x[i];
-  // block reduction
-  {
-    double v = acc;
+  double v = acc;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
-      partials[blockIdx.x] = s;
-    }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
+    partials[blockIdx.x] = s;
   }
-  __threadfence();
+}
+
+__global__ __launch_bounds__(BLOCK) void sum_kernel(int np, const double *partials, double *out) {
+  __shared__ double red[BLOCK / 64];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < np; k += BLOCK) acc += partials[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (unsigned k = 0; k < gridDim.x; ++k) s += __builtin_nontemporal_load(partials + k);
-      *out = s;
-      *counter = 0u;
-    }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
+    *out = s;
   }
 }
 
@@ -82,8 +79,11 @@ static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
       continue;
     }
     tbegin(&c, DFR_K_OTHER);
-    hipLaunchKernelGGL(norm2_kernel, dim3((unsigned)b), dim3(BLOCK), 0, c.stream, n3, x[i], c.d_partials, c.d_counter,
-                       d_out);
+    hipLaunchKernelGGL(norm2_kernel, dim3((unsigned)b), dim3(BLOCK), 0, c.stream, n3, x[i], c.d_partials);
+    tend(&c);
+    DFR_HIP(hipGetLastError());
+    tbegin(&c, DFR_K_FINALIZE);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(BLOCK), 0, c.stream, (int)b, c.d_partials, d_out);
     tend(&c);
     DFR_HIP(hipGetLastError());
     DFR_HIP(hipMemcpyAsync(&got[i], d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -189,7 +189,6 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
       for (int k = 0; k < p; ++k) ar.W[k] = c.d_W + k * n3;
       ar.vprev = (j >= 1 && o.iop >= 2) ? V + (int64_t)(j - 1) * n3 : nullptr;
       ar.partials = c.d_partials;
-      ar.counter = c.d_counter;
       ar.kd = kd;
       ar.tol = o.tol;
       double *out = V + (int64_t)(j + 1) * n3;

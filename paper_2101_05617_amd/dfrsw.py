@@ -208,7 +208,7 @@ class EpiState:
         return self._h
 
 
-KERNEL_KINDS = {"jv_arnoldi": 0, "jv": 1, "rhs": 2, "update": 3, "expm": 4, "other": 5}
+KERNEL_KINDS = {"jv_arnoldi": 0, "jv": 1, "rhs": 2, "update": 3, "expm": 4, "other": 5, "finalize": 6}
 
 
 def dfr_timing_enable(g: Grid, enable=True):
