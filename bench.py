@@ -90,6 +90,36 @@ def cpu_baseline_leg(workload_name):
     return {"step_s": dt, "jv_s": tj, "n_matvec": st.n_matvec}
 
 
+def jv_only(w, args):
+    """Time the plain J*v kernel alone on workload w (buffers rotated past the
+    last-level cache); prints one JSON line."""
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    g = dfrsw.Grid(w.ne, w.p, *w.constants())
+    tile = dfrsw.dfr_autotune(g, args.prec)
+    P, B1, B2 = g.node_frames()
+    Q, _ = inputs.initial_state(w, P, B1, B2)
+    q = torch.from_numpy(Q).cuda()
+    N = w.n_nodes
+    nbuf = max(2, min(8, int(4e8 // (48 * N))))
+    vs = [torch.randn(3 * N, dtype=torch.float64, device="cuda") * 1e-3 for _ in range(nbuf)]
+    outs = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    eps = 1e-20 if args.prec == "fp32_jv" else 1e-150
+    t = time_jv(g, q, vs, outs, eps, args.prec, args.jv_reps)
+    # a plain device copy of exactly 256 MiB, the calibration point for the
+    # FETCH_SIZE / WRITE_SIZE counters
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    bpn = jv_bytes_per_node(args.prec)
+    print(json.dumps({"workload": w.name, "prec": args.prec, "nodes": N, "tile": tile, "us": t * 1e3,
+                      "GBs": bpn * N / (t * 1e-3) / 1e9, "frac_hbm": bpn * N / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}),
+          flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +130,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the ne=60, p=6 J*v roofline figures")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--jv-only", action="store_true",
+                    help="only time the plain complex-step J*v kernel of --workload (for profiling)")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_jv"], help="precision of --jv-only")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -118,8 +151,12 @@ def main():
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     w = inputs.WORKLOADS[args.workload]
     log(f"workload {w.name}: ne={w.ne} p={w.p} N={w.n_nodes} EPI{w.order} dt={w.dt_s}s tol={w.tol} m<={w.m_max}")
+    if args.jv_only:
+        return jv_only(w, args)
 
     g = dfrsw.Grid(w.ne, w.p, *w.constants())
+    tile = dfrsw.dfr_autotune(g, "fp64")
+    log(f"autotuned tile {tile}")
     P, B1, B2 = g.node_frames()
     Q, hB = inputs.initial_state(w, P, B1, B2)
     q0 = torch.from_numpy(Q).cuda()
@@ -183,6 +220,7 @@ def main():
                                f"EPI{w.order}, dt={w.dt_s:g}s, KIOPS tol={w.tol:g}, m<={w.m_max}, plain FP64",
                    "ne": w.ne, "p": w.p, "nodes": N, "order": w.order, "dt_s": w.dt_s,
                    "timed_steps_include_startup": timed_includes_startup},
+        "tile": tile,
         "jv_per_s": 1e3 / jv_ms,
         "jv_per_s_fp32": 1e3 / jv32_ms,
         "jv_in_step_per_s": n_jv / wall,
@@ -218,6 +256,7 @@ def main():
     if not args.no_c2:
         w2 = inputs.WORKLOADS["c2_ne60_p6_jet"]
         g2 = dfrsw.Grid(w2.ne, w2.p, *w2.constants())
+        tile2 = dfrsw.dfr_autotune(g2, "fp64")
         P2, B12, B22 = g2.node_frames()
         Q2, _ = inputs.initial_state(w2, P2, B12, B22)
         q2 = torch.from_numpy(Q2).cuda()
@@ -226,10 +265,11 @@ def main():
         v2 = [torch.randn(3 * N2, dtype=torch.float64, device="cuda") * 1e-3 for _ in range(nbuf)]
         o2 = [torch.empty(3 * N2, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
         t64 = time_jv(g2, q2, v2, o2, 1e-150, "fp64", args.jv_reps)
+        tile2_32 = dfrsw.dfr_autotune(g2, "fp32_jv")
         t32 = time_jv(g2, q2, v2, o2, 1e-20, "fp32_jv", args.jv_reps)
         log(f"ne=60 p=6 J*v: fp64 {t64 * 1e3:.1f} us, fp32 {t32 * 1e3:.1f} us")
         out["jv_ne60_p6"] = {
-            "nodes": N2,
+            "nodes": N2, "tile_fp64": tile2, "tile_fp32": tile2_32,
             "fp64": {"us": t64 * 1e3, "jv_per_s": 1e3 / t64, "GBs": 72 * N2 / (t64 * 1e-3) / 1e9,
                      "frac_hbm": 72 * N2 / (t64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "fp32_jv": {"us": t32 * 1e3, "jv_per_s": 1e3 / t32, "GBs": 60 * N2 / (t32 * 1e-3) / 1e9,

@@ -95,6 +95,18 @@ int dfr_node_frames(const dfr_ctx *ctx, double *host_P, double *host_B1, double 
 /* Wait for the context's stream; return (and clear) any latched kernel error. */
 int dfr_sync(dfr_ctx *ctx);
 
+/* Work decomposition of the DFR kernel: a workgroup takes a tile of
+ * tile_tx x tile_ty elements of one panel (both dividing ne, one thread per
+ * GL node, at most 1024 nodes).  dfr_create picks a default; dfr_set_tile
+ * overrides it (DFR_E_INVAL if not admissible); dfr_autotune times the
+ * complex-step kernel of the given precision for every admissible tile on a
+ * synthetic state and keeps the fastest (synchronises; uses the context's
+ * Krylov workspace as scratch).  Results are identical for every tile up to
+ * rounding. */
+int dfr_set_tile(dfr_ctx *ctx, int tile_tx, int tile_ty);
+int dfr_get_tile(const dfr_ctx *ctx, int *tile_tx, int *tile_ty);
+int dfr_autotune(dfr_ctx *ctx, dfr_precision prec, int *tile_tx, int *tile_ty);
+
 /* dqdt = F(q): the DFR right-hand side of the covariant shallow-water
  * equations, Eqs. (1)-(2) with the flux reconstruction of Eqs. (10)-(14),
  * Rusanov interface fluxes with the wave speeds of Eqs. (147)-(148), panel

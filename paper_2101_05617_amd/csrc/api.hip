@@ -21,7 +21,6 @@ namespace dfrsw {
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-int64_t dfr_grid_blocks(const Ctx *c);
 int set_expm_lds_limit(int n);
 
 // ---------------------------------------------------------------------------
@@ -348,9 +347,49 @@ static int setup_geometry(Ctx &c, const double *hB) {
   return DFR_OK;
 }
 
+// admissible element tiles: TX, TY divide ne, one thread per node (<= 1024),
+// dynamic LDS within the device limit, halo descriptors within the table
+static std::vector<std::pair<int, int>> tile_candidates(const Ctx &c) {
+  std::vector<std::pair<int, int>> out;
+  const int nn = c.ns * c.ns;
+  for (int tx = 1; tx <= c.ne; ++tx) {
+    if (c.ne % tx) continue;
+    for (int ty = 1; ty <= c.ne; ++ty) {
+      if (c.ne % ty) continue;
+      if (tx * ty * nn > 1024 || 2 * (tx + ty) > 128) continue;
+      if (dfr_lds_bytes(c.ns, tx, ty, false) > c.lds_limit) continue;
+      out.push_back({tx, ty});
+    }
+  }
+  return out;
+}
+
+// default tile: the largest (then squarest) tile that still gives two
+// workgroups per compute unit; on small grids, the one with most workgroups
+static void default_tile(Ctx &c) {
+  const auto cand = tile_candidates(c);
+  int best = -1;
+  long best_key = -1;
+  for (size_t k = 0; k < cand.size(); ++k) {
+    const int tx = cand[k].first, ty = cand[k].second;
+    const long nb = 6L * (c.ne / tx) * (c.ne / ty);
+    const long nel = (long)tx * ty;
+    long key;
+    if (nb >= 512) key = (1L << 40) + nel * 1000 - std::abs(tx - ty);
+    else key = nb * 1000 + nel;
+    if (key > best_key) {
+      best_key = key;
+      best = (int)k;
+    }
+  }
+  c.tile_tx = cand[best].first;
+  c.tile_ty = cand[best].second;
+}
+
 static int alloc_workspace(Ctx &c) {
   const int64_t n3 = 3 * c.n;
-  const int64_t nb = std::max<int64_t>(dfr_grid_blocks(&c), 8192);
+  // largest grid of any tile (1 x 1 tiles) or of the vector kernels
+  const int64_t nb = std::max<int64_t>(6LL * c.ne * c.ne + 8, 8192);
   DFR_HIP(hipMalloc(&c.d_partials, sizeof(double) * 2 * nb));
   DFR_HIP(hipMalloc(&c.d_counter, sizeof(unsigned)));
   DFR_HIP(hipMemset(c.d_counter, 0, sizeof(unsigned)));
@@ -367,6 +406,13 @@ static int alloc_workspace(Ctx &c) {
   (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device);
   (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, c.device);
   lds = std::max(lds, lds_optin) - 1024;
+  // the DFR kernel's static LDS (operators, halo table, reduction) stays below 4 KB
+  c.lds_limit = (size_t)lds - 4096;
+  default_tile(c);
+  {
+    const int rc = dfr_set_lds_limits(&c, c.lds_limit);
+    if (rc) return rc;
+  }
   int nmax = 1;   // largest n (= m + 1) whose padded size fits
   while (4 * (((nmax + 1) + 3) & ~3) * (((nmax + 1) + 3) & ~3) * (int)sizeof(double) <= lds) ++nmax;
   c.max_m = std::min(MAX_M, nmax - 1);
@@ -563,6 +609,77 @@ int dfr_node_frames(const dfr_ctx *h, double *P, double *B1, double *B2) {
             basis_at(c, p, P + 3 * n, B1 + 3 * n, B2 + 3 * n);
           }
   return DFR_OK;
+}
+
+int dfr_set_tile(dfr_ctx *h, int tx, int ty) {
+  if (!h) return DFR_E_INVAL;
+  Ctx &c = h->c;
+  for (const auto &t : tile_candidates(c))
+    if (t.first == tx && t.second == ty) {
+      c.tile_tx = tx;
+      c.tile_ty = ty;
+      return DFR_OK;
+    }
+  set_error("tile not admissible (TX, TY must divide ne, TX*TY*(p+1)^2 <= 1024, LDS within limit)");
+  return DFR_E_INVAL;
+}
+
+int dfr_get_tile(const dfr_ctx *h, int *tx, int *ty) {
+  if (!h || !tx || !ty) return DFR_E_INVAL;
+  *tx = h->c.tile_tx;
+  *ty = h->c.tile_ty;
+  return DFR_OK;
+}
+
+int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
+  if (!h || (prec != DFR_FP64 && prec != DFR_FP32_JV)) return DFR_E_INVAL;
+  Ctx &c = h->c;
+  const int64_t n3 = 3 * c.n;
+  // a smooth positive state and a direction in the Krylov workspace
+  double *q = c.d_V, *v = c.d_V + n3, *w = c.d_V + 2 * n3;
+  int rc = launch_fill(&c, q, v);
+  if (rc) return rc;
+  const bool fp32 = prec == DFR_FP32_JV;
+  if (fp32) {
+    rc = launch_copy_to_f32(&c, n3, q, (float *)c.d_qf32);
+    if (rc) return rc;
+  }
+  hipEvent_t e0, e1;
+  DFR_HIP(hipEventCreate(&e0));
+  DFR_HIP(hipEventCreate(&e1));
+  const int keep_tx = c.tile_tx, keep_ty = c.tile_ty;
+  float best = 1e30f;
+  int btx = keep_tx, bty = keep_ty;
+  const bool was_timing = c.timing;
+  c.timing = false;
+  for (const auto &t : tile_candidates(c)) {
+    c.tile_tx = t.first;
+    c.tile_ty = t.second;
+    const int reps = 5;
+    for (int r = 0; r < 2 + reps; ++r) {
+      if (r == 2) (void)hipEventRecord(e0, c.stream);
+      rc = launch_dfr(&c, q, (const float *)c.d_qf32, v, nullptr, fp32 ? 1e-20 : 1e-150, true, fp32, w, nullptr);
+      if (rc) break;
+    }
+    if (rc) break;
+    (void)hipEventRecord(e1, c.stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      btx = t.first;
+      bty = t.second;
+    }
+  }
+  c.timing = was_timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.tile_tx = rc ? keep_tx : btx;
+  c.tile_ty = rc ? keep_ty : bty;
+  if (tile_tx) *tile_tx = c.tile_tx;
+  if (tile_ty) *tile_ty = c.tile_ty;
+  return rc ? rc : latched_error(c);
 }
 
 int dfr_sync(dfr_ctx *h) {

@@ -108,6 +108,8 @@ struct Ctx {
   // KIOPS workspace
   int kiops_mmax = 0, kiops_p = 0;
   int max_m = MAX_M;              // Krylov cap from the LDS available to one workgroup
+  int tile_tx = 1, tile_ty = 1;   // elements per workgroup of the DFR kernel (x^1, x^2)
+  size_t lds_limit = 65536;       // LDS one workgroup may use
   double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N
   double *d_W = nullptr;          // MAX_P scaled b columns of 3N
   double *d_partials = nullptr;   // per-block partial sums
@@ -141,6 +143,11 @@ int launch_expm(Ctx *c, double tau);
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
 int launch_check_state(Ctx *c, const double *q);
+int launch_fill(Ctx *c, double *q, double *v);
+int latched_error(Ctx &c);
+size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32);
+int dfr_set_lds_limits(Ctx *c, size_t bytes);
+int64_t dfr_grid_blocks(const Ctx *c);
 
 }  // namespace dfrsw
 

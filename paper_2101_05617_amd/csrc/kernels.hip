@@ -12,6 +12,7 @@
 //   phi-combination by Krylov projection    Sec. 4, Eqs. (26), (29)
 #include "dfrsw_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace dfrsw {
@@ -163,50 +164,67 @@ __device__ __forceinline__ void side_flux1(const cx<T> Q[3], int n, T eta_1n, T 
 }
 
 // ---------------------------------------------------------------------------
-// The fused DFR kernel.  A block takes `epb` consecutive elements of one
-// element row of one panel (epb divides ne), one thread per GL node.
-//  Phase 1 (per node): metric terms from 1-D tangent tables (App. B), nodal
-//    fluxes (Eq. 136) and sources (Eq. 2) in complex arithmetic; state and
-//    fluxes staged in LDS.
-//  Phase 2a (per element, face, face point, field): own trace and neighbour
-//    trace (Eq. 7 at +-1); the east/west neighbours inside the block come from
-//    LDS, the others from global memory (L2-resident halo).
-//  Phase 2b (per element, face, face point): App. C map of the neighbour's
-//    momentum at panel edges, Rusanov common flux.
-//  Phase 3 (per node): extended-point derivative of Eq. (12) in both
-//    directions, sources, division by sqrt(g); output Re (F) or Im/eps (J v),
-//    optionally with the Arnoldi epilogue (W-columns, partial inner products).
-template <int NS, typename T>
-struct DfrSmem {
-  static constexpr int NN = NS * NS;
-  static constexpr int EPB = BLOCK / NN;
-  cx<T> F1[EPB][3][NN];
-  cx<T> F2[EPB][3][NN];
-  cx<T> Z[EPB][3][NN];
-  cx<T> Tr[EPB][4][3][NS];      // own traces; overwritten by the common fluxes
-  cx<T> Nb[EPB][4][3][NS];      // neighbour traces
-  T D[NS][NS + 2];
-  T lm[NS], lp[NS];
-  double red[BLOCK / 64];
+// The fused DFR kernel.  A block takes a tile of TX x TY elements of one panel
+// (TX, TY divide ne), one thread per GL node.
+//  A  (per node): metric terms from 1-D tangent tables (App. B), nodal fluxes
+//     (Eq. 136) and sources (Eq. 2) in complex arithmetic; state and fluxes
+//     staged in LDS.
+//  B1 (per node): the interior part of the extended-point derivative of
+//     Eq. (12) in both directions, kept in registers.
+//  B2 (per element, face, field, face point): own traces (Eq. 7 at +-1) from
+//     LDS; traces of the neighbours outside the tile from global memory.
+//  C  (per face point of the tile, each face once): App. C map of the
+//     neighbour's momentum at panel edges, Rusanov common flux.
+//  D  (per node): face terms of Eq. (12), sources, division by sqrt(g);
+//     output Re (F) or Im/eps (J v), optionally with the Arnoldi epilogue.
+// LDS regions are reused across phases: R0 = state (A..B2) then face fluxes
+// (C, D); R1 = x^1 fluxes (A, B1) then own traces (B2, C); R2 = x^2 fluxes
+// (A, B1) then halo traces (B2, C).
+constexpr int DFR_MAX_THREADS = 1024;
+constexpr int DFR_MAX_HALO = 128;   // external faces of a tile: 2 (TX + TY)
+
+struct HaloDesc {
+  int base;    // first node index of the neighbour element
+  int qface;   // the neighbour's face that touches the tile
+  int rev;     // along-edge orientation reversed
+  int edge;    // 1 on a panel edge (App. C map needed)
 };
 
+template <typename T>
+__device__ __forceinline__ cx<T> lds_cx(const T *p, int i) {
+  return {p[2 * i], p[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ void lds_cx_store(T *p, int i, cx<T> z) {
+  p[2 * i] = z.r;
+  p[2 * i + 1] = z.i;
+}
+
 template <int NS, typename T, typename TQ, bool CS>
-__global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1D ops, const int epb,
-                                                     const TQ *__restrict__ q, const double *__restrict__ v,
-                                                     const double *__restrict__ vscale, double eps,
-                                                     double *__restrict__ out, const ArnoldiArgs ar) {
-  using S = DfrSmem<NS, T>;
-  constexpr int NN = S::NN;
-  __shared__ S sm;
+__global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
+                                                               const int TY, const int r0_len, const int r1_len,
+                                                               const TQ *__restrict__ q, const double *__restrict__ v,
+                                                               const double *__restrict__ vscale, double eps,
+                                                               double *__restrict__ out, const ArnoldiArgs ar) {
+  constexpr int NN = NS * NS;
+  extern __shared__ double dyn[];
+  __shared__ T sD[NS][NS + 2];
+  __shared__ T slm[NS], slp[NS];
+  __shared__ HaloDesc hd[DFR_MAX_HALO];
+  __shared__ double red[DFR_MAX_THREADS / 64];
+  // complex values are stored as (re, im) pairs of T
+  T *R0 = reinterpret_cast<T *>(dyn);
+  T *R1 = R0 + 2 * r0_len;
+  T *R2 = R1 + 2 * r1_len;
 
   if (ar.on && ar.kd->happy) return;   // uniform: the sub-step ended in a happy breakdown
 
   const int tid = threadIdx.x;
   const int ne = g.ne;
   const int N = (int)g.n;
-  const int bpr = ne / epb;            // blocks per element row
-  const int nlog = 6 * ne * bpr;
-  const int lb = (int)logical_block(nlog);
+  const int ntx = ne / TX, nty = ne / TY;
+  const int nel = TX * TY;
+  const int lb = (int)logical_block(6 * ntx * nty);
   if (lb < 0) {                        // uniform: padding block of the XCD mapping
     if (ar.on && tid == 0) {
       ar.partials[blockIdx.x * 2 + 0] = 0.0;
@@ -214,21 +232,48 @@ __global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1
     }
     return;
   }
-  const int row = lb / bpr;            // panel * ne + element row
-  const int p = row / ne, ej = row - p * ne;
-  const int ei0 = (lb - row * bpr) * epb;
-  const int ebase = row * ne + ei0;    // first element of the block
+  const int p = lb / (ntx * nty);
+  const int trow = (lb - p * ntx * nty) / ntx;
+  const int tcol = lb - p * ntx * nty - trow * ntx;
+  const int ej0 = trow * TY, ei0 = tcol * TX;
 
-  for (int k = tid; k < NS * (NS + 2); k += BLOCK) sm.D[k / (NS + 2)][k % (NS + 2)] = (T)ops.Dt[k / (NS + 2)][k % (NS + 2)];
+  for (int k = tid; k < NS * (NS + 2); k += blockDim.x) sD[k / (NS + 2)][k % (NS + 2)] = (T)ops.Dt[k / (NS + 2)][k % (NS + 2)];
   if (tid < NS) {
-    sm.lm[tid] = (T)ops.lm[tid];
-    sm.lp[tid] = (T)ops.lp[tid];
+    slm[tid] = (T)ops.lm[tid];
+    slp[tid] = (T)ops.lp[tid];
+  }
+  // halo descriptors: [0,TY) west, [TY,2TY) east, [2TY,2TY+TX) south, then north
+  const int nhalo = 2 * (TX + TY);
+  if (tid < nhalo) {
+    int face, ei, ej;
+    if (tid < TY) { face = 0; ej = ej0 + tid; ei = ei0; }
+    else if (tid < 2 * TY) { face = 1; ej = ej0 + tid - TY; ei = ei0 + TX - 1; }
+    else if (tid < 2 * TY + TX) { face = 2; ei = ei0 + tid - 2 * TY; ej = ej0; }
+    else { face = 3; ei = ei0 + tid - 2 * TY - TX; ej = ej0 + TY - 1; }
+    int qp = p, qe = ej, qi = ei, qf, rev = 0, edge = 0;
+    if (face == 0) { if (ei > 0) { qi = ei - 1; qf = 1; } else edge = 1; }
+    else if (face == 1) { if (ei < ne - 1) { qi = ei + 1; qf = 0; } else edge = 1; }
+    else if (face == 2) { if (ej > 0) { qe = ej - 1; qf = 3; } else edge = 1; }
+    else { if (ej < ne - 1) { qe = ej + 1; qf = 2; } else edge = 1; }
+    if (edge) {
+      const int along = (face < 2) ? ej : ei;
+      qp = g.nb_q[p][face];
+      qf = g.nb_e[p][face];
+      rev = g.nb_rev[p][face];
+      const int qa = rev ? ne - 1 - along : along;
+      if (qf == 0) { qi = 0; qe = qa; }
+      else if (qf == 1) { qi = ne - 1; qe = qa; }
+      else if (qf == 2) { qe = 0; qi = qa; }
+      else { qe = ne - 1; qi = qa; }
+    }
+    hd[tid] = {((qp * ne + qe) * ne + qi) * NN, qf, rev, edge};
   }
 
   const int s = tid / NN, node = tid - s * NN, nj = node / NS, ni = node - nj * NS;
-  const bool active = s < epb;
-  const int ei = ei0 + s;
-  const int gidx = (ebase + s) * NN + node;
+  const bool active = s < nel;
+  const int sy = s / TX, sx = s - sy * TX;
+  const int ei = ei0 + sx, ej = ej0 + sy;
+  const int gidx = ((p * ne + ej) * ne + ei) * NN + node;
   const T gred = (T)g.g_red;
   const double vs = (CS && vscale) ? *vscale : 1.0;
   const double eps_vs = eps * vs;
@@ -237,7 +282,7 @@ __global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1
   T rs = T(0);
   double vtrue[3] = {0.0, 0.0, 0.0};
 
-  // ---- phase 1
+  // ---- A: state, nodal fluxes, sources
   if (active) {
     const Tan3 tx = g.tnode[ei * NS + ni], ty = g.tnode[ej * NS + nj];
     const T X = (T)tx.x, ax = (T)tx.ax, rax = (T)tx.rax;
@@ -265,7 +310,7 @@ __global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1
         qi = (T)(eps * vv);
       }
       Qz[f] = {qr, qi};
-      sm.Z[s][f][node] = Qz[f];
+      lds_cx_store(R0, (s * 3 + f) * NN + node, Qz[f]);
     }
     const cx<T> H = Qz[0], M1 = Qz[1], M2 = Qz[2];
     if (!(H.r > T(0))) atomicOr(g.err_flag, 2);
@@ -273,13 +318,13 @@ __global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1
     const cx<T> u1 = cmul(M1, rH), u2 = cmul(M2, rH);
     const cx<T> H2h = (T(0.5) * gred) * cmul(H, H);
     const cx<T> m11 = cmul(M1, u1), m12 = cmul(M1, u2), m22 = cmul(M2, u2);
-    const cx<T> f12 = m12 + e12 * H2h;
-    sm.F1[s][0][node] = sg * M1;
-    sm.F1[s][1][node] = sg * (m11 + e11 * H2h);
-    sm.F1[s][2][node] = sg * f12;
-    sm.F2[s][0][node] = sg * M2;
-    sm.F2[s][1][node] = sg * f12;
-    sm.F2[s][2][node] = sg * (m22 + e22 * H2h);
+    const cx<T> f12 = sg * (m12 + e12 * H2h);
+    lds_cx_store(R1, (s * 3 + 0) * NN + node, sg * M1);
+    lds_cx_store(R1, (s * 3 + 1) * NN + node, sg * (m11 + e11 * H2h));
+    lds_cx_store(R1, (s * 3 + 2) * NN + node, f12);
+    lds_cx_store(R2, (s * 3 + 0) * NN + node, sg * M2);
+    lds_cx_store(R2, (s * 3 + 1) * NN + node, f12);
+    lds_cx_store(R2, (s * 3 + 2) * NN + node, sg * (m22 + e22 * H2h));
     // sources per unit sqrt(g): Coriolis -2 Gamma^i_0j H u^j, metric -Gamma^i_jk H u^j u^k
     // (the h^jk Gamma^i_jk term vanishes identically on the cubed sphere, App. B)
     src1 = -(T(2) * (G101 * M1 + G102 * M2) + (G111 * m11 + (T(2) * G112) * m12));
@@ -291,136 +336,156 @@ __global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1
   }
   __syncthreads();
 
-  // ---- phase 2a: traces, task = ((f * epb + s) * 4 + face) * NS + t
-  const int ntr = 3 * epb * 4 * NS;
-  for (int task = tid; task < ntr; task += BLOCK) {
-    const int t = task % NS;
-    const int r1 = task / NS;
-    const int face = r1 & 3;
-    const int r2 = r1 >> 2;
-    const int fs = r2 % epb, f = r2 / epb;
-    const int fei = ei0 + fs;
-    // own trace along the line normal to the face
-    const T *wl = (face == 0 || face == 2) ? sm.lm : sm.lp;
-    cx<T> acc = {T(0), T(0)};
+  // ---- B1: interior part of the derivative, both directions
+  cx<T> acc[3];
+  if (active) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) acc = acc + wl[k] * sm.Z[fs][f][(face < 2) ? (t * NS + k) : (k * NS + t)];
-    sm.Tr[fs][face][f][t] = acc;
-    // neighbour trace
-    cx<T> nb = {T(0), T(0)};
-    if (face == 0 && fs > 0) {
-#pragma unroll
-      for (int k = 0; k < NS; ++k) nb = nb + sm.lp[k] * sm.Z[fs - 1][f][t * NS + k];
-    } else if (face == 1 && fs < epb - 1) {
-#pragma unroll
-      for (int k = 0; k < NS; ++k) nb = nb + sm.lm[k] * sm.Z[fs + 1][f][t * NS + k];
-    } else {
-      int q_p = p, q_ej = ej, q_ei = fei, q_face, q_t = t;
-      bool edge = false;
-      if (face == 0) { if (fei > 0) { q_ei = fei - 1; q_face = 1; } else edge = true; }
-      else if (face == 1) { if (fei < ne - 1) { q_ei = fei + 1; q_face = 0; } else edge = true; }
-      else if (face == 2) { if (ej > 0) { q_ej = ej - 1; q_face = 3; } else edge = true; }
-      else { if (ej < ne - 1) { q_ej = ej + 1; q_face = 2; } else edge = true; }
-      if (edge) {
-        const int along = (face < 2) ? ej : fei;
-        q_p = g.nb_q[p][face];
-        q_face = g.nb_e[p][face];
-        const int rev = g.nb_rev[p][face];
-        const int qa = rev ? ne - 1 - along : along;
-        q_t = rev ? NS - 1 - t : t;
-        if (q_face == 0) { q_ei = 0; q_ej = qa; }
-        else if (q_face == 1) { q_ei = ne - 1; q_ej = qa; }
-        else if (q_face == 2) { q_ej = 0; q_ei = qa; }
-        else { q_ej = ne - 1; q_ei = qa; }
-      }
-      const T *wq = (q_face == 0 || q_face == 2) ? sm.lm : sm.lp;
-      const int first = f * N + ((q_p * ne + q_ej) * ne + q_ei) * NN + ((q_face < 2) ? q_t * NS : q_t);
-      const int stride = (q_face < 2) ? 1 : NS;
+    for (int f = 0; f < 3; ++f) {
+      const int b = (s * 3 + f) * NN;
+      cx<T> d = {T(0), T(0)};
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const int id = first + k * stride;
-        T zi = T(0);
-        if (CS) zi = (T)(eps_vs * v[id]);
-        nb = nb + wq[k] * cx<T>{(T)q[id], zi};
+        d = d + sD[ni][k + 1] * lds_cx(R1, b + nj * NS + k);
+        d = d + sD[nj][k + 1] * lds_cx(R2, b + k * NS + ni);
       }
+      acc[f] = d;
     }
-    sm.Nb[fs][face][f][t] = nb;
   }
   __syncthreads();
 
-  // ---- phase 2b: common fluxes, task = (s * 4 + face) * NS + t
-  const int nfl = epb * 4 * NS;
-  for (int task = tid; task < nfl; task += BLOCK) {
+  // ---- B2: own traces (into R1) and halo traces (into R2)
+  // own: task = ((s * 4 + face) * 3 + f) * NS + t ; stored at the same index
+  for (int task = tid; task < nel * 12 * NS; task += blockDim.x) {
     const int t = task % NS;
-    const int r1 = task / NS;
-    const int face = r1 & 3, fs = r1 >> 2;
-    const int fei = ei0 + fs;
-    cx<T> own[3], nb[3];
+    const int r = task / NS;
+    const int f = r % 3;
+    const int r2 = r / 3;
+    const int face = r2 & 3, es = r2 >> 2;
+    const T *w = (face == 0 || face == 2) ? slm : slp;
+    const int b = (es * 3 + f) * NN + ((face < 2) ? t * NS : t);
+    const int st = (face < 2) ? 1 : NS;
+    cx<T> a = {T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < NS; ++k) a = a + w[k] * lds_cx(R0, b + k * st);
+    lds_cx_store(R1, task, a);
+  }
+  // halo: task = (h * 3 + f) * NS + t
+  for (int task = tid; task < nhalo * 3 * NS; task += blockDim.x) {
+    const int t = task % NS;
+    const int r = task / NS;
+    const int f = r % 3, h = r / 3;
+    const HaloDesc d = hd[h];
+    const int qt = d.rev ? NS - 1 - t : t;
+    const T *w = (d.qface == 0 || d.qface == 2) ? slm : slp;
+    const int first = f * N + d.base + ((d.qface < 2) ? qt * NS : qt);
+    const int st = (d.qface < 2) ? 1 : NS;
+    cx<T> a = {T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int id = first + k * st;
+      T zi = T(0);
+      if (CS) zi = (T)(eps_vs * v[id]);
+      a = a + w[k] * cx<T>{(T)q[id], zi};
+    }
+    lds_cx_store(R2, task, a);
+  }
+  __syncthreads();
+
+  // ---- C: common fluxes, each face of the tile once, into R0
+  // vertical faces (x^1 normal): (fx, sy, t), fx = 0..TX ; then horizontal (fy, sx, t)
+  const int nvert = (TX + 1) * TY * NS;
+  const int nflux = nvert + (TY + 1) * TX * NS;
+  for (int task = tid; task < nflux; task += blockDim.x) {
+    const bool vert = task < nvert;
+    const int tk = vert ? task : task - nvert;
+    const int t = tk % NS;
+    const int r = tk / NS;
+    int n, lo_el, hi_el, lo_h, hi_h, ex, ey, fxy;
+    if (vert) {
+      n = 0;
+      const int fy_ = r % TY;   // element row in the tile
+      fxy = r / TY;             // face column 0..TX
+      lo_el = (fxy > 0) ? fy_ * TX + fxy - 1 : -1;
+      hi_el = (fxy < TX) ? fy_ * TX + fxy : -1;
+      lo_h = fy_;               // west halo
+      hi_h = TY + fy_;          // east halo
+      ex = ei0 + fxy;           // edge index along x^1
+      ey = ej0 + fy_;
+    } else {
+      n = 1;
+      const int fx_ = r % TX;
+      fxy = r / TX;             // face row 0..TY
+      lo_el = (fxy > 0) ? (fxy - 1) * TX + fx_ : -1;
+      hi_el = (fxy < TY) ? fxy * TX + fx_ : -1;
+      lo_h = 2 * TY + fx_;      // south halo
+      hi_h = 2 * TY + TX + fx_; // north halo
+      ex = ei0 + fx_;
+      ey = ej0 + fxy;
+    }
+    cx<T> QL[3], QR[3];
+    int hq = -1;   // halo side read (for the App. C map)
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      own[f] = sm.Tr[fs][face][f][t];
-      nb[f] = sm.Nb[fs][face][f][t];
+      // own traces of the low element on its high face (E or N), of the high
+      // element on its low face (W or S)
+      if (lo_el >= 0) QL[f] = lds_cx(R1, ((lo_el * 4 + (n == 0 ? 1 : 3)) * 3 + f) * NS + t);
+      else { QL[f] = lds_cx(R2, (lo_h * 3 + f) * NS + t); hq = lo_h; }
+      if (hi_el >= 0) QR[f] = lds_cx(R1, ((hi_el * 4 + (n == 0 ? 0 : 2)) * 3 + f) * NS + t);
+      else { QR[f] = lds_cx(R2, (hi_h * 3 + f) * NS + t); hq = hi_h; }
     }
-    const bool edge = (face == 0 && fei == 0) || (face == 1 && fei == ne - 1) || (face == 2 && ej == 0) ||
-                      (face == 3 && ej == ne - 1);
-    if (edge) {
-      const int along = (face < 2) ? ej : fei;
+    if (hq >= 0 && hd[hq].edge) {
+      // App. C: neighbour components -> this panel's basis
+      const int face = (hq < TY) ? 0 : (hq < 2 * TY) ? 1 : (hq < 2 * TY + TX) ? 2 : 3;
+      const int along = (face < 2) ? ey : ex;
       const double *M = g.xform + (((p * 4 + face) * ne + along) * NS + t) * 4;
       const T m00 = (T)M[0], m01 = (T)M[1], m10 = (T)M[2], m11 = (T)M[3];
-      const cx<T> a1 = m00 * nb[1] + m01 * nb[2];
-      const cx<T> a2 = m10 * nb[1] + m11 * nb[2];
-      nb[1] = a1;
-      nb[2] = a2;
+      cx<T> *Qn = (lo_el < 0) ? QL : QR;
+      const cx<T> a1 = m00 * Qn[1] + m01 * Qn[2];
+      const cx<T> a2 = m10 * Qn[1] + m11 * Qn[2];
+      Qn[1] = a1;
+      Qn[2] = a2;
     }
     // metric at the face point
     T X, Y, ax, ay, rax, ray;
-    if (face < 2) {
-      const double xe = g.tedge[fei + (face == 1)];
-      const Tan3 ty = g.tnode[ej * NS + t];
-      X = (T)xe; ax = T(1) + X * X; rax = frcp(ax);
+    if (n == 0) {
+      X = (T)g.tedge[ex]; ax = T(1) + X * X; rax = frcp(ax);
+      const Tan3 ty = g.tnode[ey * NS + t];
       Y = (T)ty.x; ay = (T)ty.ax; ray = (T)ty.rax;
     } else {
-      const double ye = g.tedge[ej + (face == 3)];
-      const Tan3 tx = g.tnode[fei * NS + t];
+      const Tan3 tx = g.tnode[ex * NS + t];
       X = (T)tx.x; ax = (T)tx.ax; rax = (T)tx.rax;
-      Y = (T)ye; ay = T(1) + Y * Y; ray = frcp(ay);
+      Y = (T)g.tedge[ey]; ay = T(1) + Y * Y; ray = frcp(ay);
     }
     const T d2 = ax + Y * Y;
     const T rd = frsqrt(d2);
     const T sg = ax * ay * rd * rd * rd;
-    const int n = (face < 2) ? 0 : 1;
     const T e11 = d2 * rax, e22 = d2 * ray, e12 = X * Y * e11 * ray;
     const T eta1n = n == 0 ? e11 : e12, eta2n = n == 0 ? e12 : e22, etann = n == 0 ? e11 : e22;
-    const bool own_low = (face == 1 || face == 3);
     cx<T> fL[3], fR[3], cL, cR;
-    const cx<T> *QL = own_low ? own : nb;
-    const cx<T> *QR = own_low ? nb : own;
     side_flux1(QL, n, eta1n, eta2n, etann, gred, fL, cL);
     side_flux1(QR, n, eta1n, eta2n, etann, gred, fR, cR);
     const cx<T> lam = (cL.r >= cR.r) ? cL : cR;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const cx<T> F = T(0.5) * (fL[f] + fR[f]) - T(0.5) * cmul(lam, QR[f] - QL[f]);
-      sm.Tr[fs][face][f][t] = sg * F;
+      lds_cx_store(R0, task * 3 + f, sg * F);
     }
   }
   __syncthreads();
 
-  // ---- phase 3: derivative of the continuous flux polynomial (Eqs. 12, 14)
+  // ---- D: face terms, sources, output
   double w[3] = {0.0, 0.0, 0.0};
   if (active) {
     const T scale = -(T)g.two_over_delta * rs;
     const T invE = CS ? (T)(1.0 / eps) : T(1);
+    const int iW = ((sx * TY + sy) * NS + nj) * 3, iE = (((sx + 1) * TY + sy) * NS + nj) * 3;
+    const int iS = nvert * 3 + ((sy * TX + sx) * NS + ni) * 3, iN = nvert * 3 + (((sy + 1) * TX + sx) * NS + ni) * 3;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      cx<T> d1 = sm.D[ni][0] * sm.Tr[s][0][f][nj] + sm.D[ni][NS + 1] * sm.Tr[s][1][f][nj];
-      cx<T> d2 = sm.D[nj][0] * sm.Tr[s][2][f][ni] + sm.D[nj][NS + 1] * sm.Tr[s][3][f][ni];
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        d1 = d1 + sm.D[ni][k + 1] * sm.F1[s][f][nj * NS + k];
-        d2 = d2 + sm.D[nj][k + 1] * sm.F2[s][f][k * NS + ni];
-      }
-      cx<T> r = scale * (d1 + d2);
+      cx<T> d = acc[f];
+      d = d + sD[ni][0] * lds_cx(R0, iW + f) + sD[ni][NS + 1] * lds_cx(R0, iE + f);
+      d = d + sD[nj][0] * lds_cx(R0, iS + f) + sD[nj][NS + 1] * lds_cx(R0, iN + f);
+      cx<T> r = scale * d;
       if (f == 1) r = r + src1;
       if (f == 2) r = r + src2;
       w[f] = CS ? (double)(r.i * invE) : (double)r.r;
@@ -439,15 +504,15 @@ __global__ __launch_bounds__(BLOCK) void dfr_kernel(const GridArgs g, const Ops1
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int id = f * N + gidx;
-      double acc = w[f];
-      for (int k = 0; k < ar.p; ++k) acc += ar.W[k][id] * c[k];
-      out[id] = acc;
-      d0 += acc * vtrue[f];
-      if (ar.vprev) d1 += acc * ar.vprev[id];
+      double a = w[f];
+      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * c[k];
+      out[id] = a;
+      d0 += a * vtrue[f];
+      if (ar.vprev) d1 += a * ar.vprev[id];
     }
   }
-  const double b0 = block_sum(d0, sm.red);
-  const double b1 = block_sum(d1, sm.red);
+  const double b0 = block_sum(d0, red);
+  const double b1 = block_sum(d1, red);
   if (tid == 0) {
     ar.partials[blockIdx.x * 2 + 0] = b0;
     ar.partials[blockIdx.x * 2 + 1] = b1;
@@ -715,6 +780,16 @@ __global__ __launch_bounds__(BLOCK) void to_f32_kernel(int64_t n, const double *
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) y[i] = (float)x[i];
 }
 
+// a positive smooth state (H = 1 + 0.1 sin, small momenta) and a direction,
+// used only to time kernels
+__global__ __launch_bounds__(BLOCK) void fill_kernel(int64_t n, double *q, double *v) {
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * BLOCK) {
+    const double x = (double)(i % n) * 1e-3;
+    q[i] = (i < n) ? 1.0 + 0.1 * sin(x) : 0.05 * cos(x + (double)(i / n));
+    v[i] = 1e-3 * sin(3.0 * x + 1.0);
+  }
+}
+
 __global__ __launch_bounds__(BLOCK) void check_state_kernel(int64_t n, const double *q, int *err) {
   int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * BLOCK) {
@@ -734,29 +809,65 @@ static inline int grid_for(int64_t n) {
   return (int)b;
 }
 
-// elements per block: the largest divisor of ne that fits BLOCK threads
-int dfr_epb(const Ctx *c) {
-  const int cap = BLOCK / (c->ns * c->ns);
-  int e = cap < c->ne ? cap : c->ne;
-  while (c->ne % e) --e;
-  return e;
+// LDS regions of the tiled kernel, in complex values: R0, R1, R2
+static void dfr_regions(int ns, int tx, int ty, int &r0, int &r1, int &r2) {
+  const int nn = ns * ns, nel = tx * ty, nhalo = 2 * (tx + ty);
+  const int nflux = ((tx + 1) * ty + (ty + 1) * tx) * ns;
+  r0 = std::max(nel * 3 * nn, nflux * 3);
+  r1 = std::max(nel * 3 * nn, nel * 12 * ns);
+  r2 = std::max(nel * 3 * nn, nhalo * 3 * ns);
+}
+
+size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32) {
+  int r0, r1, r2;
+  dfr_regions(ns, tx, ty, r0, r1, r2);
+  return (size_t)(r0 + r1 + r2) * 2 * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 int64_t dfr_grid_blocks(const Ctx *c) {
-  const int64_t nlog = 6LL * c->ne * (c->ne / dfr_epb(c));
+  const int64_t nlog = 6LL * (c->ne / c->tile_tx) * (c->ne / c->tile_ty);
   return ((nlog + 7) / 8) * 8;
 }
 
 template <int NS, typename T, typename TQ, bool CS>
 static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale, double eps, double *out,
                       const ArnoldiArgs &ar) {
-  const int epb = dfr_epb(c);
+  const int tx = c->tile_tx, ty = c->tile_ty;
+  int r0, r1, r2;
+  dfr_regions(NS, tx, ty, r0, r1, r2);
+  const size_t lds = (size_t)(r0 + r1 + r2) * 2 * sizeof(T);
+  const int threads = ((tx * ty * NS * NS + 63) / 64) * 64;
   const int64_t nb = dfr_grid_blocks(c);
   tbegin(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV));
-  hipLaunchKernelGGL((dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(BLOCK), 0, c->stream, c->ga, c->ops, epb,
-                     q, v, vscale, eps, out, ar);
+  hipLaunchKernelGGL((dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(threads), lds, c->stream, c->ga, c->ops,
+                     tx, ty, r0, r1, q, v, vscale, eps, out, ar);
   tend(c);
   if (ar.on) launch_dots_finalize(c, (int)nb, ar);
+}
+
+template <int NS>
+static int set_lds_attr(size_t bytes) {
+  DFR_HIP(hipFuncSetAttribute((const void *)dfr_kernel<NS, double, double, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  DFR_HIP(hipFuncSetAttribute((const void *)dfr_kernel<NS, double, double, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  DFR_HIP(hipFuncSetAttribute((const void *)dfr_kernel<NS, float, float, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return DFR_OK;
+}
+
+// allow the dynamic LDS of every tile the context may use
+int dfr_set_lds_limits(Ctx *c, size_t bytes) {
+  switch (c->ns) {
+    case 2: return set_lds_attr<2>(bytes);
+    case 3: return set_lds_attr<3>(bytes);
+    case 4: return set_lds_attr<4>(bytes);
+    case 5: return set_lds_attr<5>(bytes);
+    case 6: return set_lds_attr<6>(bytes);
+    case 7: return set_lds_attr<7>(bytes);
+    case 8: return set_lds_attr<8>(bytes);
+    default: set_error("unsupported number of GL points"); return DFR_E_INVAL;
+  }
 }
 
 template <typename T, typename TQ, bool CS>
@@ -864,6 +975,12 @@ int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y) {
   tbegin(c, DFR_K_OTHER);
   hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, c->stream, n, x, y);
   tend(c);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_fill(Ctx *c, double *q, double *v) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(3 * c->n)), dim3(BLOCK), 0, c->stream, c->n, q, v);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

@@ -80,6 +80,9 @@ def lib():
             "epi_get_state": (i, [vp, vp]),
             "epi_num_steps": (i64, [vp]),
             "epi_destroy": (i, [vp]),
+            "dfr_set_tile": (i, [vp, i, i]),
+            "dfr_get_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "dfr_autotune": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_timing_enable": (i, [vp, i]),
             "dfr_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64)]),
             "dfr_last_error": (ctypes.c_char_p, []),
@@ -95,7 +98,8 @@ def lib():
 def exported_symbols():
     return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
-            "epi_num_steps", "epi_destroy", "dfr_timing_enable", "dfr_timing_read", "dfr_last_error"]
+            "epi_num_steps", "epi_destroy", "dfr_set_tile", "dfr_get_tile", "dfr_autotune", "dfr_timing_enable",
+            "dfr_timing_read", "dfr_last_error"]
 
 
 def _check(rc):
@@ -209,6 +213,22 @@ class EpiState:
 
 
 KERNEL_KINDS = {"jv_arnoldi": 0, "jv": 1, "rhs": 2, "update": 3, "expm": 4, "other": 5, "finalize": 6}
+
+
+def dfr_set_tile(g: Grid, tx, ty):
+    _check(lib().dfr_set_tile(g.handle, int(tx), int(ty)))
+
+
+def dfr_get_tile(g: Grid):
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    _check(lib().dfr_get_tile(g.handle, ctypes.byref(tx), ctypes.byref(ty)))
+    return tx.value, ty.value
+
+
+def dfr_autotune(g: Grid, prec="fp64"):
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    _check(lib().dfr_autotune(g.handle, _PREC[prec], ctypes.byref(tx), ctypes.byref(ty)))
+    return tx.value, ty.value
 
 
 def dfr_timing_enable(g: Grid, enable=True):

@@ -255,3 +255,33 @@ def test_c1_full_size_epi5_parity():
     # sub-steps to bound the oracle's run time)
     errs = _epi_compare(C1, 4, 2)
     assert max(errs) < 1e-11
+
+
+@pytest.mark.parametrize("ne,p", [(6, 3), (4, 6), (2, 2)])
+def test_every_tile_shape_gives_the_same_result(ne, p):
+    # the workgroup tile (TX x TY elements) changes only the decomposition
+    w = small(C0, ne, p, u_amp=2.0)
+    G, D, Q = pair(w)
+    from paper_2101_05617_amd import dfrsw
+    V = inputs.random_direction(3 * G.N, 77)
+    ref_f, ref_j = G.rhs(Q), G.jvp(Q, V)
+    q, v = to_dev(Q), to_dev(V)
+    nn = (p + 1) ** 2
+    tried = 0
+    for tx in range(1, ne + 1):
+        for ty in range(1, ne + 1):
+            if ne % tx or ne % ty or tx * ty * nn > 1024:
+                continue
+            dfrsw.dfr_set_tile(D, tx, ty)
+            assert dfrsw.dfr_get_tile(D) == (tx, ty)
+            ef = rel_fields(to_host(dfrsw.dfr_rhs(D, q)), ref_f, G.N)
+            ej = rel_fields(to_host(dfrsw.dfr_jvp_complex_step(D, q, v)), ref_j, G.N)
+            record(f"tile_ne{ne}_p{p}_{tx}x{ty}", max(ef, ej))
+            assert ef < rhs_bar(G, Q) and ej < 1e-12, (tx, ty, ef, ej)
+            tried += 1
+    assert tried >= 3
+    with pytest.raises(dfrsw.DfrError):
+        dfrsw.dfr_set_tile(D, ne + 1, 1)
+    tx, ty = dfrsw.dfr_autotune(D, "fp64")
+    assert ne % tx == 0 and ne % ty == 0
+    assert rel_fields(to_host(dfrsw.dfr_jvp_complex_step(D, q, v)), ref_j, G.N) < 1e-12
