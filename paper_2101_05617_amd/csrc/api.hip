@@ -391,6 +391,7 @@ static int alloc_workspace(Ctx &c) {
   // largest grid of any tile (1 x 1 tiles) or of the vector kernels
   const int64_t nb = std::max<int64_t>(6LL * c.ne * c.ne + 8, 8192);
   DFR_HIP(hipMalloc(&c.d_partials, sizeof(double) * 2 * nb));
+  DFR_HIP(hipMalloc(&c.d_partials2, sizeof(double) * 2 * nb));
   DFR_HIP(hipMalloc(&c.d_counter, sizeof(unsigned)));
   DFR_HIP(hipMemset(c.d_counter, 0, sizeof(unsigned)));
   DFR_HIP(hipMalloc(&c.d_kd, sizeof(KDev)));
@@ -406,8 +407,8 @@ static int alloc_workspace(Ctx &c) {
   (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device);
   (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, c.device);
   lds = std::max(lds, lds_optin) - 1024;
-  // the DFR kernel's static LDS (operators, halo table, reduction) stays below 4 KB
-  c.lds_limit = (size_t)lds - 4096;
+  // the DFR kernel's static LDS (operators, halo table, reduction) stays below 8 KB
+  c.lds_limit = (size_t)lds - 8192;
   default_tile(c);
   {
     const int rc = dfr_set_lds_limits(&c, c.lds_limit);
@@ -432,6 +433,7 @@ static void free_ctx(Ctx &c) {
   (void)hipFree(c.d_orog);
   (void)hipFree(c.d_err);
   (void)hipFree(c.d_partials);
+  (void)hipFree(c.d_partials2);
   (void)hipFree(c.d_counter);
   (void)hipFree(c.d_kd);
   (void)hipFree(c.d_expm_scratch);

@@ -55,25 +55,34 @@ struct GridArgs {
   int *err_flag;          // latched kernel error (vector atomics only)
 };
 
-// Optional Arnoldi epilogue of the J*v kernel (KIOPS iteration).
+// Optional Arnoldi prologue/epilogue of the J*v kernel (one KIOPS iteration).
+// The prologue finalises the previous kernel's reduction (partial sums `pin`)
+// in a fixed order, identically in every workgroup: the norm of the vector
+// built by the previous update (or of the start vector), hence sigma_j and
+// the bottom block b_j; workgroup 0 records them in KDev.
 struct ArnoldiArgs {
   int on;                 // 0: plain J*v
   int j;                  // index of the basis vector being multiplied
   int p;                  // number of W columns
+  int start;              // 1: v_j is the sub-step's start vector
   const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
-  const double *vprev;    // V_{j-1} (normalised) or NULL
-  double *partials;       // [gridDim][2]
+  const double *vprev;    // V_{j-1} (normalised) or NULL (iop = 1)
+  const double *pin;      // partial sums of the previous kernel, one per workgroup
+  int np_in;
+  double *pout;           // this kernel's partial inner products, two per workgroup
   struct KDev *kd;
   double tol;
+  double ybot[MAX_P];     // mu y(t) of the start vector (start only)
 };
 
 // Device-side KIOPS state (one per context).
 struct KDev {
   double H[(MAX_M + 2) * (MAX_M + 2)];     // Hessenberg, row-major, ld = MAX_M + 2
   double sigma[MAX_M + 2];                 // scale of the stored (unnormalised) top vectors
-  double bot[(MAX_M + 2) * MAX_P];         // bottom blocks (true values)
+  double bot[(MAX_M + 2) * MAX_P];         // bottom blocks (normalised)
+  double botu[(MAX_M + 2) * MAX_P];        // bottom blocks before normalisation
+  double wn2[MAX_M + 2];                   // squared norms of botu
   double beta;
-  double wnorm2_bot;
   double E0[MAX_M + 2];                    // first column of the small exponential
   double err;                              // error estimate of the last exponential
   double hlast;                            // h_{J,J-1}
@@ -112,7 +121,8 @@ struct Ctx {
   size_t lds_limit = 65536;       // LDS one workgroup may use
   double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N
   double *d_W = nullptr;          // MAX_P scaled b columns of 3N
-  double *d_partials = nullptr;   // per-block partial sums
+  double *d_partials = nullptr;   // per-block partial sums (J*v inner products)
+  double *d_partials2 = nullptr;  // per-block partial sums (norms)
   unsigned *d_counter = nullptr;
   KDev *d_kd = nullptr;
   double *d_expm_scratch = nullptr;
@@ -135,11 +145,12 @@ void tend(Ctx *c);
 // kernels.hip
 int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const double *vscale,
                double eps, bool complex_step, bool fp32, double *out, const ArnoldiArgs *ar);
-int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out);
-int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, double tol);
-int launch_start(Ctx *c, const double *x, double *v0, int p, const double *ybot);
+int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out);
+int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, const double *pin, int np_in,
+                  double *pout, int *np_out);
+int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out);
 int launch_combine(Ctx *c, double *x);
-int launch_expm(Ctx *c, double tau);
+int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol);
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
 int launch_check_state(Ctx *c, const double *q);

@@ -17,8 +17,6 @@
 
 namespace dfrsw {
 
-int launch_dots_finalize(Ctx *c, int np, const ArnoldiArgs &ar);
-
 // ---------------------------------------------------------------------------
 // complex arithmetic on (re, im) pairs: the complex step evaluates F on
 // z = q + i eps v; products keep the eps^2 terms (exact complex arithmetic)
@@ -67,49 +65,72 @@ __device__ __forceinline__ int64_t logical_block(int64_t nlogical) {
   return lb < nlogical ? lb : -1;
 }
 
-// sum of partials[k*stride + off], k < np, in a fixed order; valid in thread 0
-__device__ double reduce_partials(const double *partials, int np, int stride, int off, double *red) {
-  double s = 0.0;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) s += partials[(int64_t)k * stride + off];
-  return block_sum(s, red);
+// Sum of pin[k*stride + off], k < np, in an order that does not depend on the
+// workgroup size: 256 virtual lanes take every 256th value, then a fixed
+// binary tree.  Every workgroup of every kernel gets the identical value.
+// red: 256 doubles of LDS.  Call from all threads of the workgroup.
+__device__ double reduce_fixed(const double *pin, int np, int stride, int off, double *red) {
+  __syncthreads();
+  for (int l = threadIdx.x; l < 256; l += blockDim.x) {
+    double s = 0.0;
+    for (int k = l; k < np; k += 256) s += pin[(int64_t)k * stride + off];
+    red[l] = s;
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    for (int l = threadIdx.x; l < h; l += blockDim.x) red[l] += red[l + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
 }
 
-// ---------------------------------------------------------------------------
-// Arnoldi finalisation after w = A~ v_j has been formed and its inner products
-// with the last two top vectors reduced: classical Gram-Schmidt coefficients
-// h_{j,j}, h_{j-1,j} (incomplete orthogonalisation, iop = 2) including the
-// bottom blocks, and the bottom block of the new vector.
-__device__ void arnoldi_dot_finalize(const ArnoldiArgs &ar, int np, double *red) {
+// Arnoldi prologue: finalise the norm of the vector v_j (start vector, or the
+// vector built by the previous update), giving sigma_j = 1/||.|| for the
+// stored top block and the normalised bottom block b_j.  Returns false (in
+// every workgroup) on a happy breakdown.  Workgroup 0 records the values.
+__device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig, double bj[MAX_P]) {
   KDev *kd = ar.kd;
   const int j = ar.j, p = ar.p;
-  const double d0 = reduce_partials(ar.partials, np, 2, 0, red);
-  const double d1 = reduce_partials(ar.partials, np, 2, 1, red);
-  if (threadIdx.x == 0) {
-    const double *bj = kd->bot + j * MAX_P;
-    double wb[MAX_P];
-    for (int k = 0; k < p; ++k) wb[k] = (k + 1 < p) ? bj[k + 1] : 0.0;   // K v_j^bot (upper shift)
-    double hjj = d0, hpj = d1;
-    for (int k = 0; k < p; ++k) hjj += bj[k] * wb[k];
-    const int ld = MAX_M + 2;
-    kd->H[j * ld + j] = hjj;
-    const bool two = (j >= 1) && (ar.vprev != nullptr);   // iop = 2
-    if (two) {
-      const double *bp = kd->bot + (j - 1) * MAX_P;
-      for (int k = 0; k < p; ++k) hpj += bp[k] * wb[k];
-      kd->H[(j - 1) * ld + j] = hpj;
-    } else {
-      hpj = 0.0;
+  const double s = reduce_fixed(ar.pin, ar.np_in, 1, 0, red);
+  const int ld = MAX_M + 2;
+  const bool w0 = blockIdx.x == 0;
+  if (ar.start) {
+    double s2 = s;
+    for (int k = 0; k < p; ++k) s2 += ar.ybot[k] * ar.ybot[k];
+    const double beta = sqrt(s2);
+    sig = 1.0 / beta;
+    for (int k = 0; k < p; ++k) bj[k] = ar.ybot[k] / beta;
+    if (w0) {
+      for (int k = threadIdx.x; k < ld * ld; k += blockDim.x) kd->H[k] = 0.0;
+      if (threadIdx.x == 0) {
+        kd->beta = beta;
+        kd->sigma[0] = sig;
+        for (int k = 0; k < p; ++k) kd->bot[k] = bj[k];
+        kd->happy = 0;
+        kd->J = 0;
+      }
     }
-    double nb2 = 0.0;
-    double *bn = kd->bot + (j + 1) * MAX_P;
-    for (int k = 0; k < p; ++k) {
-      double v = wb[k] - hjj * bj[k];
-      if (two) v -= hpj * kd->bot[(j - 1) * MAX_P + k];
-      bn[k] = v;
-      nb2 += v * v;
-    }
-    kd->wnorm2_bot = nb2;
+    return true;
   }
+  const double nrm = sqrt(s + kd->wn2[j]);
+  if (nrm < ar.tol) {
+    if (w0 && threadIdx.x == 0) {
+      kd->happy = 1;
+      kd->J = j;
+    }
+    return false;
+  }
+  sig = 1.0 / nrm;
+  for (int k = 0; k < p; ++k) bj[k] = kd->botu[j * MAX_P + k] / nrm;
+  if (w0 && threadIdx.x == 0) {
+    kd->H[j * ld + (j - 1)] = nrm;
+    kd->sigma[j] = sig;
+    for (int k = 0; k < p; ++k) kd->bot[j * MAX_P + k] = bj[k];
+    kd->J = j;
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -211,7 +232,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   __shared__ T sD[NS][NS + 2];
   __shared__ T slm[NS], slp[NS];
   __shared__ HaloDesc hd[DFR_MAX_HALO];
-  __shared__ double red[DFR_MAX_THREADS / 64];
+  __shared__ double red[256];
   // complex values are stored as (re, im) pairs of T
   T *R0 = reinterpret_cast<T *>(dyn);
   T *R1 = R0 + 2 * r0_len;
@@ -227,10 +248,17 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   const int lb = (int)logical_block(6 * ntx * nty);
   if (lb < 0) {                        // uniform: padding block of the XCD mapping
     if (ar.on && tid == 0) {
-      ar.partials[blockIdx.x * 2 + 0] = 0.0;
-      ar.partials[blockIdx.x * 2 + 1] = 0.0;
+      ar.pout[blockIdx.x * 2 + 0] = 0.0;
+      ar.pout[blockIdx.x * 2 + 1] = 0.0;
     }
     return;
+  }
+  double vs = 1.0;
+  double bj[MAX_P];
+  if (ar.on) {
+    if (!arnoldi_prologue(ar, red, vs, bj)) return;   // uniform
+  } else if (CS && vscale) {
+    vs = *vscale;
   }
   const int p = lb / (ntx * nty);
   const int trow = (lb - p * ntx * nty) / ntx;
@@ -275,7 +303,6 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   const int ei = ei0 + sx, ej = ej0 + sy;
   const int gidx = ((p * ne + ej) * ne + ei) * NN + node;
   const T gred = (T)g.g_red;
-  const double vs = (CS && vscale) ? *vscale : 1.0;
   const double eps_vs = eps * vs;
 
   cx<T> src1 = {T(0), T(0)}, src2 = {T(0), T(0)};
@@ -500,12 +527,11 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   // ---- Arnoldi epilogue: w += sum_k W_k c_k ; partial <v_j, w>, <v_{j-1}, w>
   double d0 = 0.0, d1 = 0.0;
   if (active) {
-    const double *c = ar.kd->bot + ar.j * MAX_P;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int id = f * N + gidx;
       double a = w[f];
-      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * c[k];
+      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * bj[k];
       out[id] = a;
       d0 += a * vtrue[f];
       if (ar.vprev) d1 += a * ar.vprev[id];
@@ -514,89 +540,82 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   const double b0 = block_sum(d0, red);
   const double b1 = block_sum(d1, red);
   if (tid == 0) {
-    ar.partials[blockIdx.x * 2 + 0] = b0;
-    ar.partials[blockIdx.x * 2 + 1] = b1;
+    ar.pout[blockIdx.x * 2 + 0] = b0;
+    ar.pout[blockIdx.x * 2 + 1] = b1;
   }
-}
-
-// one block: reduce the J v kernel's partial inner products (fixed order)
-__global__ __launch_bounds__(BLOCK) void arnoldi_dots_finalize_kernel(int np, const ArnoldiArgs ar) {
-  __shared__ double red[BLOCK / 64];
-  if (ar.kd->happy) return;
-  arnoldi_dot_finalize(ar, np, red);
 }
 
 // first Arnoldi step of a sub-step whose top block is identically zero:
-// w = W c (no J v), same epilogue
+// w = W b_0 (no J v); both partial inner products vanish
 __global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, double *out) {
+  __shared__ double red[256];
   if (ar.kd->happy) return;
-  const double *c = ar.kd->bot + ar.j * MAX_P;
+  double sig, bj[MAX_P];
+  if (!arnoldi_prologue(ar, red, sig, bj)) return;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
     double acc = 0.0;
-    for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * c[k];
+    for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * bj[k];
     out[i] = acc;
   }
-  // the top block of v_j is zero, so both inner products vanish
   if (threadIdx.x == 0) {
-    ar.partials[blockIdx.x * 2 + 0] = 0.0;
-    ar.partials[blockIdx.x * 2 + 1] = 0.0;
+    ar.pout[blockIdx.x * 2 + 0] = 0.0;
+    ar.pout[blockIdx.x * 2 + 1] = 0.0;
   }
 }
 
-// Gram-Schmidt update and normalisation:
-//   w <- w - h_jj sigma_j v~_j - h_{j-1,j} v_{j-1};  v_j <- sigma_j v~_j (stored normalised)
-//   h_{j+1,j} = ||w|| (top and bottom), sigma_{j+1} = 1/h_{j+1,j}; happy breakdown if < tol
-__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, double *w, double *vj,
-                                                               const double *vprev, double *partials, KDev *kd) {
-  __shared__ double red[BLOCK / 64];
+// Gram-Schmidt step.  Prologue: the inner products h_{j,j}, h_{j-1,j} (top
+// partials of the J v kernel plus the bottom blocks; classical Gram-Schmidt
+// over the last two vectors) and the new bottom block, recorded by workgroup
+// 0.  Body: w <- w - h_jj sigma_j v~_j - h_{j-1,j} v_{j-1}; v_j <- sigma_j v~_j
+// (stored normalised); partial ||w||^2 per workgroup.
+__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, double *w, double *vj,
+                                                               const double *vprev, const double *pin, int np_in,
+                                                               double *pout, KDev *kd) {
+  __shared__ double red[256];
   if (kd->happy) return;
+  const double d0 = reduce_fixed(pin, np_in, 2, 0, red);
+  const double d1 = reduce_fixed(pin, np_in, 2, 1, red);
   const int ld = MAX_M + 2;
-  const double hjj = kd->H[j * ld + j];
-  const double hpj = (j >= 1 && vprev) ? kd->H[(j - 1) * ld + j] : 0.0;
+  const bool two = (j >= 1) && (vprev != nullptr);
+  const double *bj = kd->bot + j * MAX_P;
+  const double *bp = kd->bot + (j - (j >= 1 ? 1 : 0)) * MAX_P;
+  double wb[MAX_P];
+  for (int k = 0; k < p; ++k) wb[k] = (k + 1 < p) ? bj[k + 1] : 0.0;   // K b_j (upper shift)
+  double hjj = d0, hpj = d1;
+  for (int k = 0; k < p; ++k) hjj += bj[k] * wb[k];
+  if (two) {
+    for (int k = 0; k < p; ++k) hpj += bp[k] * wb[k];
+  } else {
+    hpj = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    kd->H[j * ld + j] = hjj;
+    if (two) kd->H[(j - 1) * ld + j] = hpj;
+    double nb2 = 0.0;
+    for (int k = 0; k < p; ++k) {
+      double v = wb[k] - hjj * bj[k];
+      if (two) v -= hpj * bp[k];
+      kd->botu[(j + 1) * MAX_P + k] = v;
+      nb2 += v * v;
+    }
+    kd->wn2[j + 1] = nb2;
+  }
   const double sj = kd->sigma[j];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
     const double vv = sj * vj[i];
     double x = w[i] - hjj * vv;
-    if (vprev) x -= hpj * vprev[i];
+    if (two) x -= hpj * vprev[i];
     w[i] = x;
     vj[i] = vv;
     acc += x * x;
   }
   const double b = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x * 2] = b;
+  if (threadIdx.x == 0) pout[blockIdx.x] = b;
 }
 
-// one block: h_{j+1,j} = ||w|| (top and bottom blocks), sigma_{j+1} = 1/h_{j+1,j},
-// normalised bottom block; happy breakdown if the norm is below tol
-__global__ __launch_bounds__(BLOCK) void arnoldi_norm_finalize_kernel(int np, int j, int p, const double *partials,
-                                                                      KDev *kd, double tol) {
-  __shared__ double red[BLOCK / 64];
-  if (kd->happy) return;
-  const double s = reduce_partials(partials, np, 2, 0, red);
-  if (threadIdx.x == 0) {
-    const int ld = MAX_M + 2;
-    const double nrm = sqrt(s + kd->wnorm2_bot);
-    kd->sigma[j] = 1.0;
-    kd->J = j + 1;
-    if (nrm < tol) {
-      kd->happy = 1;
-    } else {
-      kd->H[(j + 1) * ld + j] = nrm;
-      kd->sigma[j + 1] = 1.0 / nrm;
-      double *bn = kd->bot + (j + 1) * MAX_P;
-      for (int k = 0; k < p; ++k) bn[k] /= nrm;
-    }
-  }
-}
-
-struct Ybot {
-  double y[MAX_P];
-};
-
-// start of a sub-step: v~_0 = x (copied), partial ||x||^2
-__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, double *v0,
-                                                              double *partials) {
+// start of a sub-step: v~_0 = x (copied), partial ||x||^2 per workgroup
+__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, double *v0, double *pout) {
   __shared__ double red[BLOCK / 64];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
@@ -605,27 +624,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const 
     acc += xv * xv;
   }
   const double b = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x * 2] = b;
-}
-
-// one block: beta = ||[x; mu y(t)]||, sigma_0 = 1/beta, bottom block mu y(t)/beta,
-// Hessenberg cleared
-__global__ __launch_bounds__(BLOCK) void arnoldi_start_finalize_kernel(int np, int p, const Ybot yb,
-                                                                       const double *partials, KDev *kd) {
-  __shared__ double red[BLOCK / 64];
-  const double s = reduce_partials(partials, np, 2, 0, red);
-  const int ld = MAX_M + 2;
-  for (int k = threadIdx.x; k < ld * ld; k += BLOCK) kd->H[k] = 0.0;
-  if (threadIdx.x == 0) {
-    double s2 = s;
-    for (int k = 0; k < p; ++k) s2 += yb.y[k] * yb.y[k];
-    const double beta = sqrt(s2);
-    kd->beta = beta;
-    kd->sigma[0] = 1.0 / beta;
-    for (int k = 0; k < p; ++k) kd->bot[k] = yb.y[k] / beta;
-    kd->happy = 0;
-    kd->J = 0;
-  }
+  if (threadIdx.x == 0) pout[blockIdx.x] = b;
 }
 
 // accepted sub-step: x = beta * sum_{k<J} v_k E[k][0]
@@ -675,10 +674,23 @@ __device__ void lds_matmul(const double *A, const double *B, double *C, int ld) 
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res) {
+__global__ __launch_bounds__(BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
+                                                     int np_in, double tol) {
   extern __shared__ double lds[];
-  __shared__ double red[BLOCK / 64];
+  __shared__ double red[256];
   __shared__ double cnorm;
+  // finalise the norm of the last vector built (unless a happy breakdown
+  // already ended the sweep): h_{jfin, jfin-1}, or a happy breakdown
+  if (!kd->happy) {
+    const double s = reduce_fixed(pin, np_in, 1, 0, red);
+    if (threadIdx.x == 0) {
+      const double nrm = sqrt(s + kd->wn2[jfin]);
+      if (nrm < tol) kd->happy = 1;
+      else kd->H[jfin * (MAX_M + 2) + (jfin - 1)] = nrm;
+      kd->J = jfin;
+    }
+    __syncthreads();
+  }
   const int J = kd->J;
   const int n = J + 1;
   const int ld = (n + 3) & ~3;          // padded to whole 4 x 4 tiles (zero padding)
@@ -842,7 +854,6 @@ static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale
   hipLaunchKernelGGL((dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(threads), lds, c->stream, c->ga, c->ops,
                      tx, ty, r0, r1, q, v, vscale, eps, out, ar);
   tend(c);
-  if (ar.on) launch_dots_finalize(c, (int)nb, ar);
 }
 
 template <int NS>
@@ -896,51 +907,45 @@ int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const
   return dispatch_ns<double, double, true>(c, q, v, vscale, eps, out, a);
 }
 
-int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out) {
-  const int64_t n3 = 3 * c->n;
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(arnoldi_first_kernel, dim3(grid_for(n3)), dim3(BLOCK), 0, c->stream, n3, ar, out);
-  tend(c);
-  DFR_HIP(hipGetLastError());
-  return launch_dots_finalize(c, grid_for(n3), ar);
+static inline int grid_reduce(int64_t n) {
+  // vector kernels whose partial sums are consumed by the next kernel use at
+  // most 1024 workgroups (grid-stride loops)
+  const int g = grid_for(n);
+  return g < 1024 ? g : 1024;
 }
 
-int launch_dots_finalize(Ctx *c, int np, const ArnoldiArgs &ar) {
-  tbegin(c, DFR_K_FINALIZE);
-  hipLaunchKernelGGL(arnoldi_dots_finalize_kernel, dim3(1), dim3(BLOCK), 0, c->stream, np, ar);
+int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out) {
+  const int64_t n3 = 3 * c->n;
+  const int nb = grid_reduce(n3);
+  tbegin(c, DFR_K_OTHER);
+  hipLaunchKernelGGL(arnoldi_first_kernel, dim3(nb), dim3(BLOCK), 0, c->stream, n3, ar, out);
   tend(c);
   DFR_HIP(hipGetLastError());
+  *np_out = nb;
   return DFR_OK;
 }
 
-int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, double tol) {
+int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, const double *pin, int np_in,
+                  double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
+  const int nb = grid_reduce(n3);
   tbegin(c, DFR_K_UPDATE);
-  hipLaunchKernelGGL(arnoldi_update_kernel, dim3(grid_for(n3)), dim3(BLOCK), 0, c->stream, n3, j, w, vj, vprev,
-                     c->d_partials, c->d_kd);
+  hipLaunchKernelGGL(arnoldi_update_kernel, dim3(nb), dim3(BLOCK), 0, c->stream, n3, j, c->kiops_p, w, vj, vprev, pin,
+                     np_in, pout, c->d_kd);
   tend(c);
   DFR_HIP(hipGetLastError());
-  tbegin(c, DFR_K_FINALIZE);
-  hipLaunchKernelGGL(arnoldi_norm_finalize_kernel, dim3(1), dim3(BLOCK), 0, c->stream, grid_for(n3), j, c->kiops_p,
-                     c->d_partials, c->d_kd, tol);
-  tend(c);
-  DFR_HIP(hipGetLastError());
+  *np_out = nb;
   return DFR_OK;
 }
 
-int launch_start(Ctx *c, const double *x, double *v0, int p, const double *ybot) {
+int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
-  Ybot yb{};
-  for (int k = 0; k < p; ++k) yb.y[k] = ybot[k];
+  const int nb = grid_reduce(n3);
   tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(arnoldi_start_kernel, dim3(grid_for(n3)), dim3(BLOCK), 0, c->stream, n3, x, v0, c->d_partials);
+  hipLaunchKernelGGL(arnoldi_start_kernel, dim3(nb), dim3(BLOCK), 0, c->stream, n3, x, v0, pout);
   tend(c);
   DFR_HIP(hipGetLastError());
-  tbegin(c, DFR_K_FINALIZE);
-  hipLaunchKernelGGL(arnoldi_start_finalize_kernel, dim3(1), dim3(BLOCK), 0, c->stream, grid_for(n3), p, yb,
-                     c->d_partials, c->d_kd);
-  tend(c);
-  DFR_HIP(hipGetLastError());
+  *np_out = nb;
   return DFR_OK;
 }
 
@@ -953,11 +958,12 @@ int launch_combine(Ctx *c, double *x) {
   return DFR_OK;
 }
 
-int launch_expm(Ctx *c, double tau) {
+int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol) {
   const int n = ((c->kiops_mmax + 1) + 3) & ~3;
   const size_t lds = (size_t)4 * n * n * sizeof(double);
   tbegin(c, DFR_K_EXPM);
-  hipLaunchKernelGGL(expm_kernel, dim3(1), dim3(BLOCK), lds, c->stream, c->d_kd, tau, (KHost *)c->d_expm_scratch);
+  hipLaunchKernelGGL(expm_kernel, dim3(1), dim3(BLOCK), lds, c->stream, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin,
+                     pin, np_in, tol);
   tend(c);
   DFR_HIP(hipGetLastError());
   return DFR_OK;

@@ -163,6 +163,10 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
   double *V = c.d_V;
   KDev *kd = c.d_kd;
 
+  // partial-sum buffers: A = inner products of the J v kernels, B = norms
+  double *pA = c.d_partials, *pB = c.d_partials2;
+  int npA = 0, npB = 0;
+  double ybot[MAX_P] = {0.0};
   while (t < tau_out) {
     if (++attempts > o.max_attempts) {
       set_error("kiops: no convergence within max_attempts");
@@ -171,14 +175,13 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
     const int j_sweep = j;
     bool skipped = false;
     if (j == 0) {
-      double y[MAX_P];
       for (int k = 0; k < p; ++k) {
         const int pw = p - 1 - k;
         double f = 1.0;
         for (int i = 2; i <= pw; ++i) f *= i;
-        y[k] = mu * std::pow(t, (double)pw) / f;
+        ybot[k] = mu * std::pow(t, (double)pw) / f;
       }
-      rc = launch_start(&c, w, V, p, y);
+      rc = launch_start(&c, w, V, pB, &npB);
       if (rc) return rc;
     }
     while (j < m) {
@@ -186,24 +189,31 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
       ar.on = 1;
       ar.j = j;
       ar.p = p;
-      for (int k = 0; k < p; ++k) ar.W[k] = c.d_W + k * n3;
+      ar.start = (j == 0);
+      for (int k = 0; k < p; ++k) {
+        ar.W[k] = c.d_W + k * n3;
+        ar.ybot[k] = ybot[k];
+      }
       ar.vprev = (j >= 1 && o.iop >= 2) ? V + (int64_t)(j - 1) * n3 : nullptr;
-      ar.partials = c.d_partials;
+      ar.pin = pB;
+      ar.np_in = npB;
+      ar.pout = pA;
       ar.kd = kd;
       ar.tol = o.tol;
       double *out = V + (int64_t)(j + 1) * n3;
       if (j == 0 && t == 0.0 && b0_absent) {
-        rc = launch_arnoldi_first(&c, ar, out);
+        rc = launch_arnoldi_first(&c, ar, out, &npA);
         skipped = true;
       } else {
-        rc = launch_dfr(&c, q, q32, V + (int64_t)j * n3, &kd->sigma[j], eps, true, fp32, out, &ar);
+        rc = launch_dfr(&c, q, q32, V + (int64_t)j * n3, nullptr, eps, true, fp32, out, &ar);
+        npA = (int)dfr_grid_blocks(&c);
       }
       if (rc) return rc;
-      rc = launch_update(&c, j, out, V + (int64_t)j * n3, ar.vprev, o.tol);
+      rc = launch_update(&c, j, out, V + (int64_t)j * n3, ar.vprev, pA, npA, pB, &npB);
       if (rc) return rc;
       ++j;
     }
-    rc = launch_expm(&c, tau);
+    rc = launch_expm(&c, tau, j, pB, npB, o.tol);
     if (rc) return rc;
     DFR_HIP(hipMemcpyAsync(c.h_res, c.d_expm_scratch, sizeof(KHost), hipMemcpyDeviceToHost, c.stream));
     DFR_HIP(hipStreamSynchronize(c.stream));
