@@ -187,7 +187,7 @@ def main():
     kernel_ms_total = sum(v[0] for v in kern.values())
 
     N = w.n_nodes
-    M = w.order - 2 if w.order > 2 else 1      # phi-columns of the combination
+    M = {2: 1, 3: 2, 4: 3, 5: 4, 6: 4}[w.order]   # phi-columns b_1..b_M of the EPI combination
     ms_jva, n_jva = kern["jv_arnoldi"]
     avg_jva_ms = ms_jva / max(n_jva, 1)
     bytes_jva = arnoldi_jv_bytes_per_node(M) * N

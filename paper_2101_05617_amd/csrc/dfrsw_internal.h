@@ -15,6 +15,7 @@ constexpr int MAX_NS = 8;        // p <= 7
 constexpr int MAX_M = 64;        // Krylov dimension cap
 constexpr int MAX_P = 8;         // phi-functions in one combination
 constexpr int BLOCK = 256;       // threads per block of the DFR and vector kernels
+constexpr int EXPM_BLOCK = 512;  // one workgroup of the small exponential: 17 x 17 4x4 tiles at m = 64
 
 void set_error(const std::string &msg);
 

@@ -66,9 +66,10 @@ __device__ __forceinline__ int64_t logical_block(int64_t nlogical) {
 }
 
 // Sum of pin[k*stride + off], k < np, in an order that does not depend on the
-// workgroup size: 256 virtual lanes take every 256th value, then a fixed
-// binary tree.  Every workgroup of every kernel gets the identical value.
-// red: 256 doubles of LDS.  Call from all threads of the workgroup.
+// workgroup size: 256 virtual lanes take every 256th value; the first wave
+// (always 64 lanes) adds them in a fixed pattern and a fixed butterfly.  Every
+// workgroup of every kernel gets the identical value.  red: 256 doubles of
+// LDS.  Call from all threads of the workgroup; valid in every thread.
 __device__ double reduce_fixed(const double *pin, int np, int stride, int off, double *red) {
   __syncthreads();
   for (int l = threadIdx.x; l < 256; l += blockDim.x) {
@@ -77,10 +78,14 @@ __device__ double reduce_fixed(const double *pin, int np, int stride, int off, d
     red[l] = s;
   }
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    for (int l = threadIdx.x; l < h; l += blockDim.x) red[l] += red[l + h];
-    __syncthreads();
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double v = (red[l] + red[l + 64]) + (red[l + 128] + red[l + 192]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (l == 0) red[0] = v;
   }
+  __syncthreads();
   const double r = red[0];
   __syncthreads();
   return r;
@@ -647,7 +652,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, cons
 // C = A B for n x n row-major matrices in LDS with leading dimension ld
 // (ld = n rounded up to a multiple of 4, padding rows/columns zero): each
 // thread accumulates a 4 x 4 tile in registers, so every LDS value read feeds
-// four FMAs.
+// four FMAs; the k loop is unrolled for independent loads in flight.
 __device__ void lds_matmul(const double *A, const double *B, double *C, int ld) {
   const int nt = ld / 4;
   for (int tile = threadIdx.x; tile < nt * nt; tile += blockDim.x) {
@@ -657,15 +662,20 @@ __device__ void lds_matmul(const double *A, const double *B, double *C, int ld) 
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    const double *a0p = A + r0 * ld, *a1p = a0p + ld, *a2p = a1p + ld, *a3p = a2p + ld;
+#pragma unroll 4
     for (int k = 0; k < ld; ++k) {
-      const double a0 = A[(r0 + 0) * ld + k], a1 = A[(r0 + 1) * ld + k];
-      const double a2 = A[(r0 + 2) * ld + k], a3 = A[(r0 + 3) * ld + k];
-      const double b0 = B[k * ld + c0 + 0], b1 = B[k * ld + c0 + 1];
-      const double b2 = B[k * ld + c0 + 2], b3 = B[k * ld + c0 + 3];
-      acc[0][0] += a0 * b0; acc[0][1] += a0 * b1; acc[0][2] += a0 * b2; acc[0][3] += a0 * b3;
-      acc[1][0] += a1 * b0; acc[1][1] += a1 * b1; acc[1][2] += a1 * b2; acc[1][3] += a1 * b3;
-      acc[2][0] += a2 * b0; acc[2][1] += a2 * b1; acc[2][2] += a2 * b2; acc[2][3] += a2 * b3;
-      acc[3][0] += a3 * b0; acc[3][1] += a3 * b1; acc[3][2] += a3 * b2; acc[3][3] += a3 * b3;
+      const double a0 = a0p[k], a1 = a1p[k], a2 = a2p[k], a3 = a3p[k];
+      const double *bp = B + k * ld + c0;
+      const double b0 = bp[0], b1 = bp[1], b2 = bp[2], b3 = bp[3];
+      acc[0][0] = fma(a0, b0, acc[0][0]); acc[0][1] = fma(a0, b1, acc[0][1]);
+      acc[0][2] = fma(a0, b2, acc[0][2]); acc[0][3] = fma(a0, b3, acc[0][3]);
+      acc[1][0] = fma(a1, b0, acc[1][0]); acc[1][1] = fma(a1, b1, acc[1][1]);
+      acc[1][2] = fma(a1, b2, acc[1][2]); acc[1][3] = fma(a1, b3, acc[1][3]);
+      acc[2][0] = fma(a2, b0, acc[2][0]); acc[2][1] = fma(a2, b1, acc[2][1]);
+      acc[2][2] = fma(a2, b2, acc[2][2]); acc[2][3] = fma(a2, b3, acc[2][3]);
+      acc[3][0] = fma(a3, b0, acc[3][0]); acc[3][1] = fma(a3, b1, acc[3][1]);
+      acc[3][2] = fma(a3, b2, acc[3][2]); acc[3][3] = fma(a3, b3, acc[3][3]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -674,7 +684,14 @@ __device__ void lds_matmul(const double *A, const double *B, double *C, int ld) 
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
+// Taylor coefficients 1/k!, k = 0..18, and a zero for k = 19 (degree 18)
+__constant__ double kInvFact[20] = {
+    1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0,
+    1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0,
+    1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0, 1.0 / 355687428096000.0,
+    1.0 / 6402373705728000.0, 0.0};
+
+__global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
                                                      int np_in, double tol) {
   extern __shared__ double lds[];
   __shared__ double red[256];
@@ -705,11 +722,15 @@ __global__ __launch_bounds__(BLOCK) void expm_kernel(KDev *kd, double tau, KHost
     A[idx] = v;
   }
   __syncthreads();
-  // 1-norm (max column sum)
+  // 1-norm (max column sum): the column sums of H_aug are those of tau*H_J
+  // plus tau in column J; four threads per column
   double cm = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int idx = threadIdx.x; idx < 4 * n; idx += blockDim.x) {
+    const int j = idx >> 2, part = idx & 3;
     double cs = 0.0;
-    for (int i = 0; i < n; ++i) cs += fabs(A[i * ld + j]);
+    for (int i = part; i < n; i += 4) cs += fabs(A[i * ld + j]);
+    cs += __shfl_xor(cs, 1, 64);
+    cs += __shfl_xor(cs, 2, 64);
     cm = fmax(cm, cs);
   }
   {
@@ -734,15 +755,10 @@ __global__ __launch_bounds__(BLOCK) void expm_kernel(KDev *kd, double tau, KHost
   }
   lds_matmul(A, A, A2, ld);
   __syncthreads();
-  // c_k = 1/k!, k = 0..19 (c_19 = 0 keeps the degree at 18)
-  double c[20];
-  c[0] = 1.0;
-  for (int k = 1; k < 19; ++k) c[k] = c[k - 1] / k;
-  c[19] = 0.0;
   // P = c18 I + c19 A  (padding stays zero: only the leading n x n block is set)
   for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
     const int i = idx / ld, j = idx - i * ld;
-    P[idx] = ((i == j && i < n) ? c[18] : 0.0) + c[19] * A[idx];
+    P[idx] = ((i == j && i < n) ? kInvFact[18] : 0.0) + kInvFact[19] * A[idx];
   }
   __syncthreads();
   for (int k = 8; k >= 0; --k) {
@@ -750,7 +766,7 @@ __global__ __launch_bounds__(BLOCK) void expm_kernel(KDev *kd, double tau, KHost
     __syncthreads();
     for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
       const int i = idx / ld, j = idx - i * ld;
-      P[idx] = Q[idx] + ((i == j && i < n) ? c[2 * k] : 0.0) + c[2 * k + 1] * A[idx];
+      P[idx] = Q[idx] + ((i == j && i < n) ? kInvFact[2 * k] : 0.0) + kInvFact[2 * k + 1] * A[idx];
     }
     __syncthreads();
   }
@@ -962,7 +978,7 @@ int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, doub
   const int n = ((c->kiops_mmax + 1) + 3) & ~3;
   const size_t lds = (size_t)4 * n * n * sizeof(double);
   tbegin(c, DFR_K_EXPM);
-  hipLaunchKernelGGL(expm_kernel, dim3(1), dim3(BLOCK), lds, c->stream, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin,
+  hipLaunchKernelGGL(expm_kernel, dim3(1), dim3(EXPM_BLOCK), lds, c->stream, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin,
                      pin, np_in, tol);
   tend(c);
   DFR_HIP(hipGetLastError());
