@@ -348,7 +348,7 @@ static int setup_geometry(Ctx &c, const double *hB) {
 }
 
 // admissible element tiles: TX, TY divide ne, one thread per node (<= 1024),
-// dynamic LDS within the device limit, halo descriptors within the table
+// dynamic LDS within the device limit
 static std::vector<std::pair<int, int>> tile_candidates(const Ctx &c) {
   std::vector<std::pair<int, int>> out;
   const int nn = c.ns * c.ns;
@@ -356,7 +356,7 @@ static std::vector<std::pair<int, int>> tile_candidates(const Ctx &c) {
     if (c.ne % tx) continue;
     for (int ty = 1; ty <= c.ne; ++ty) {
       if (c.ne % ty) continue;
-      if (tx * ty * nn > 1024 || 2 * (tx + ty) > 128) continue;
+      if (tx * ty * nn > 1024) continue;
       if (dfr_lds_bytes(c.ns, tx, ty, false) > c.lds_limit) continue;
       out.push_back({tx, ty});
     }

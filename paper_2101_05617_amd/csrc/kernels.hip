@@ -19,7 +19,7 @@ namespace dfrsw {
 
 // ---------------------------------------------------------------------------
 // complex arithmetic on (re, im) pairs: the complex step evaluates F on
-// z = q + i eps v; products keep the eps^2 terms (exact complex arithmetic)
+// z = q + i eps v, whose imaginary parts are O(eps |v|)
 template <typename T>
 struct cx {
   T r, i;
@@ -32,9 +32,13 @@ template <typename T>
 __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.r, -a.i}; }
 template <typename T>
 __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+// product without the Im*Im term: it is below half an ulp of Re*Re whenever
+// both imaginary parts are below 2^-27 (FP64) / 2^-12 (FP32) of the real
+// parts, so the result equals that of exact complex arithmetic in floating
+// point (the same condition as crcp1 / csqrt1 below)
 template <typename T>
-__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+__device__ __forceinline__ cx<T> cmul1(cx<T> a, cx<T> b) {
+  return {a.r * b.r, fma(a.r, b.i, a.i * b.r)};
 }
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -173,75 +177,93 @@ __device__ __forceinline__ cx<T> csqrt1(cx<T> z) {
 }
 
 // physical flux through an x^n = const face per unit sqrt(g)/a^2, and the
-// Rusanov wave speed |u^n| + sqrt(h^nn g H), for Q = (H, H u^1, H u^2)
+// Rusanov wave speed |u^n| + sqrt(h^nn g H), for Q = (H, H u^1, H u^2); the
+// state is taken by value and the normal momentum Mn = H u^n passed in (no
+// indexed arrays: they would live in scratch memory)
 template <typename T>
-__device__ __forceinline__ void side_flux1(const cx<T> Q[3], int n, T eta_1n, T eta_2n, T eta_nn, T gred,
-                                           cx<T> f[3], cx<T> &c) {
-  const cx<T> rH = crcp1(Q[0]);
-  const cx<T> Mn = (n == 0) ? Q[1] : Q[2];
-  const cx<T> un = cmul(Mn, rH);
-  const cx<T> H2h = (T(0.5) * gred) * cmul(Q[0], Q[0]);
-  f[0] = Mn;
-  f[1] = cmul(Q[1], un) + eta_1n * H2h;
-  f[2] = cmul(Q[2], un) + eta_2n * H2h;
+__device__ __forceinline__ void side_flux1(cx<T> H, cx<T> M1, cx<T> M2, cx<T> Mn, T eta_1n, T eta_2n, T eta_nn,
+                                           T gred, cx<T> &f0, cx<T> &f1, cx<T> &f2, cx<T> &c) {
+  const cx<T> rH = crcp1(H);
+  const cx<T> un = cmul1(Mn, rH);
+  const cx<T> H2h = (T(0.5) * gred) * cmul1(H, H);
+  f0 = Mn;
+  f1 = cmul1(M1, un) + eta_1n * H2h;
+  f2 = cmul1(M2, un) + eta_2n * H2h;
   // |u^n| with the branch of the real evaluation: sign(Re H u^n), H > 0
   const cx<T> au = (Mn.r >= T(0)) ? un : -un;
-  c = au + csqrt1((eta_nn * gred) * Q[0]);
+  c = au + csqrt1((eta_nn * gred) * H);
 }
 
 // ---------------------------------------------------------------------------
 // The fused DFR kernel.  A block takes a tile of TX x TY elements of one panel
 // (TX, TY divide ne), one thread per GL node.
+//
+// The discrete operator is linear in the fluxes once they are formed: the
+// derivative of Eq. (12), the extrapolation of Eq. (7) and the face terms.  Of
+// the complex evaluation only one part is kept through these stages, the
+// "linear lane": Im for the complex-step product (its result is Im F / eps),
+// Re for F itself.  The states extrapolated to the faces keep both parts,
+// since the Rusanov flux is nonlinear in them.
 //  A  (per node): metric terms from 1-D tangent tables (App. B), nodal fluxes
-//     (Eq. 136) and sources (Eq. 2) in complex arithmetic; state and fluxes
-//     staged in LDS.
-//  B1 (per node): the interior part of the extended-point derivative of
-//     Eq. (12) in both directions, kept in registers.
-//  B2 (per element, face, field, face point): own traces (Eq. 7 at +-1) from
-//     LDS; traces of the neighbours outside the tile from global memory.
+//     (Eq. 136, linear lane) and sources (Eq. 2, linear lane); the state (both
+//     parts) to LDS.  Then, per face point of the tile's neighbours, the
+//     neighbour's state extrapolated to the shared face, from global memory.
+//  B  (per node): interior part of the extended-point derivative of Eq. (12)
+//     in both directions, in registers; (per element row / column) the own
+//     states extrapolated to both faces of the row / column.
 //  C  (per face point of the tile, each face once): App. C map of the
 //     neighbour's momentum at panel edges, Rusanov common flux.
 //  D  (per node): face terms of Eq. (12), sources, division by sqrt(g);
-//     output Re (F) or Im/eps (J v), optionally with the Arnoldi epilogue.
-// LDS regions are reused across phases: R0 = state (A..B2) then face fluxes
-// (C, D); R1 = x^1 fluxes (A, B1) then own traces (B2, C); R2 = x^2 fluxes
-// (A, B1) then halo traces (B2, C).
+//     output, optionally with the Arnoldi epilogue.
 constexpr int DFR_MAX_THREADS = 1024;
-constexpr int DFR_MAX_HALO = 128;   // external faces of a tile: 2 (TX + TY)
 
-struct HaloDesc {
-  int base;    // first node index of the neighbour element
-  int qface;   // the neighbour's face that touches the tile
-  int rev;     // along-edge orientation reversed
-  int edge;    // 1 on a panel edge (App. C map needed)
+// one face of the tile, set up once per workgroup
+struct FaceDesc {
+  int lo, hi;   // trace slots of the two sides: own el*4+face, or 4*nel + halo
+  int xf;       // App. C table offset ((panel*4 + halo face)*ne + along)*NS, or -1
+  int info;     // bit 0: normal direction (0: x^1, 1: x^2); bit 1: map the lo side, bit 2: the hi side
+  int eedge;    // face line index in the edge-tangent table
+  int enode;    // element index along the face in the node-tangent table
 };
 
-template <typename T>
-__device__ __forceinline__ cx<T> lds_cx(const T *p, int i) {
-  return {p[2 * i], p[2 * i + 1]};
+// LDS layout of the tiled kernel, in values of the compute type T:
+// state [nel][3][NN][L], fluxes [nel][5][NN] (reused for the common fluxes
+// [nface*NS][3]), traces [4 nel + nhalo][3][NS][L], face table.
+struct DfrLds {
+  int state, flux, trace, faces, total;
+};
+__host__ __device__ inline DfrLds dfr_lds_layout(int ns, int tx, int ty, int lanes, int tsize) {
+  const int nn = ns * ns, nel = tx * ty, nhalo = 2 * (tx + ty);
+  const int nface = (tx + 1) * ty + (ty + 1) * tx;
+  DfrLds l;
+  l.state = 0;
+  l.flux = nel * 3 * nn * lanes;
+  const int nflux = std::max(nel * 5 * nn, nface * ns * 3);
+  l.trace = l.flux + nflux;
+  l.faces = l.trace + (4 * nel + nhalo) * 3 * ns * lanes;
+  const int fvals = (nface * (int)sizeof(FaceDesc) + tsize - 1) / tsize;
+  l.total = l.faces + fvals;
+  return l;
 }
-template <typename T>
-__device__ __forceinline__ void lds_cx_store(T *p, int i, cx<T> z) {
-  p[2 * i] = z.r;
-  p[2 * i + 1] = z.i;
+
+template <typename T, bool CS>
+__device__ __forceinline__ T lin(cx<T> z) {
+  if constexpr (CS) return z.i;
+  else return z.r;
 }
 
 template <int NS, typename T, typename TQ, bool CS>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
-                                                               const int TY, const int r0_len, const int r1_len,
-                                                               const TQ *__restrict__ q, const double *__restrict__ v,
+                                                               const int TY, const TQ *__restrict__ q,
+                                                               const double *__restrict__ v,
                                                                const double *__restrict__ vscale, double eps,
                                                                double *__restrict__ out, const ArnoldiArgs ar) {
   constexpr int NN = NS * NS;
+  constexpr int L = CS ? 2 : 1;   // parts kept of a state value
   extern __shared__ double dyn[];
   __shared__ T sD[NS][NS + 2];
   __shared__ T slm[NS], slp[NS];
-  __shared__ HaloDesc hd[DFR_MAX_HALO];
   __shared__ double red[256];
-  // complex values are stored as (re, im) pairs of T
-  T *R0 = reinterpret_cast<T *>(dyn);
-  T *R1 = R0 + 2 * r0_len;
-  T *R2 = R1 + 2 * r1_len;
 
   if (ar.on && ar.kd->happy) return;   // uniform: the sub-step ended in a happy breakdown
 
@@ -250,6 +272,15 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   const int N = (int)g.n;
   const int ntx = ne / TX, nty = ne / TY;
   const int nel = TX * TY;
+  const int nhalo = 2 * (TX + TY);
+  const int nvf = (TX + 1) * TY;
+  const int nface = nvf + (TY + 1) * TX;
+  const DfrLds lay = dfr_lds_layout(NS, TX, TY, L, (int)sizeof(T));
+  T *S = reinterpret_cast<T *>(dyn) + lay.state;
+  T *Fl = reinterpret_cast<T *>(dyn) + lay.flux;
+  T *TR = reinterpret_cast<T *>(dyn) + lay.trace;
+  FaceDesc *FD = reinterpret_cast<FaceDesc *>(reinterpret_cast<T *>(dyn) + lay.faces);
+
   const int lb = (int)logical_block(6 * ntx * nty);
   if (lb < 0) {                        // uniform: padding block of the XCD mapping
     if (ar.on && tid == 0) {
@@ -259,9 +290,15 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     return;
   }
   double vs = 1.0;
-  double bj[MAX_P];
+  __shared__ double sbj[MAX_P];   // normalised bottom block b_j (read by the epilogue)
   if (ar.on) {
+    double bj[MAX_P];
     if (!arnoldi_prologue(ar, red, vs, bj)) return;   // uniform
+    if (tid == 0) {
+#pragma unroll
+      for (int k = 0; k < MAX_P; ++k)
+        if (k < ar.p) sbj[k] = bj[k];
+    }
   } else if (CS && vscale) {
     vs = *vscale;
   }
@@ -275,31 +312,35 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     slm[tid] = (T)ops.lm[tid];
     slp[tid] = (T)ops.lp[tid];
   }
-  // halo descriptors: [0,TY) west, [TY,2TY) east, [2TY,2TY+TX) south, then north
-  const int nhalo = 2 * (TX + TY);
-  if (tid < nhalo) {
-    int face, ei, ej;
-    if (tid < TY) { face = 0; ej = ej0 + tid; ei = ei0; }
-    else if (tid < 2 * TY) { face = 1; ej = ej0 + tid - TY; ei = ei0 + TX - 1; }
-    else if (tid < 2 * TY + TX) { face = 2; ei = ei0 + tid - 2 * TY; ej = ej0; }
-    else { face = 3; ei = ei0 + tid - 2 * TY - TX; ej = ej0 + TY - 1; }
-    int qp = p, qe = ej, qi = ei, qf, rev = 0, edge = 0;
-    if (face == 0) { if (ei > 0) { qi = ei - 1; qf = 1; } else edge = 1; }
-    else if (face == 1) { if (ei < ne - 1) { qi = ei + 1; qf = 0; } else edge = 1; }
-    else if (face == 2) { if (ej > 0) { qe = ej - 1; qf = 3; } else edge = 1; }
-    else { if (ej < ne - 1) { qe = ej + 1; qf = 2; } else edge = 1; }
-    if (edge) {
-      const int along = (face < 2) ? ej : ei;
-      qp = g.nb_q[p][face];
-      qf = g.nb_e[p][face];
-      rev = g.nb_rev[p][face];
-      const int qa = rev ? ne - 1 - along : along;
-      if (qf == 0) { qi = 0; qe = qa; }
-      else if (qf == 1) { qi = ne - 1; qe = qa; }
-      else if (qf == 2) { qe = 0; qi = qa; }
-      else { qe = ne - 1; qi = qa; }
+  // face table: vertical faces (x^1 normal) id = fx*TY + row, fx = 0..TX;
+  // then horizontal faces id = nvf + fy*TX + col, fy = 0..TY.  Halo slots:
+  // [0,TY) west, [TY,2TY) east, [2TY,2TY+TX) south, then north.
+  for (int id = tid; id < nface; id += blockDim.x) {
+    FaceDesc d;
+    const int h0 = 4 * nel;
+    if (id < nvf) {
+      const int fx = id / TY, row = id - fx * TY;
+      d.lo = fx > 0 ? (row * TX + fx - 1) * 4 + 1 : h0 + row;
+      d.hi = fx < TX ? (row * TX + fx) * 4 + 0 : h0 + TY + row;
+      d.eedge = ei0 + fx;
+      d.enode = ej0 + row;
+      d.info = 0;
+      d.xf = -1;
+      if (fx == 0 && ei0 == 0) { d.info |= 2; d.xf = ((p * 4 + 0) * ne + ej0 + row) * NS; }
+      if (fx == TX && ei0 + TX == ne) { d.info |= 4; d.xf = ((p * 4 + 1) * ne + ej0 + row) * NS; }
+    } else {
+      const int k = id - nvf;
+      const int fy = k / TX, col = k - fy * TX;
+      d.lo = fy > 0 ? ((fy - 1) * TX + col) * 4 + 3 : h0 + 2 * TY + col;
+      d.hi = fy < TY ? (fy * TX + col) * 4 + 2 : h0 + 2 * TY + TX + col;
+      d.eedge = ej0 + fy;
+      d.enode = ei0 + col;
+      d.info = 1;
+      d.xf = -1;
+      if (fy == 0 && ej0 == 0) { d.info |= 2; d.xf = ((p * 4 + 2) * ne + ei0 + col) * NS; }
+      if (fy == TY && ej0 + TY == ne) { d.info |= 4; d.xf = ((p * 4 + 3) * ne + ei0 + col) * NS; }
     }
-    hd[tid] = {((qp * ne + qe) * ne + qi) * NN, qf, rev, edge};
+    FD[id] = d;
   }
 
   const int s = tid / NN, node = tid - s * NN, nj = node / NS, ni = node - nj * NS;
@@ -310,7 +351,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   const T gred = (T)g.g_red;
   const double eps_vs = eps * vs;
 
-  cx<T> src1 = {T(0), T(0)}, src2 = {T(0), T(0)};
+  T src1 = T(0), src2 = T(0);
   T rs = T(0);
   double vtrue[3] = {0.0, 0.0, 0.0};
 
@@ -336,172 +377,185 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     for (int f = 0; f < 3; ++f) {
       const T qr = (T)q[f * N + gidx];
       T qi = T(0);
-      if (CS) {
+      if constexpr (CS) {
         const double vv = vs * v[f * N + gidx];
         vtrue[f] = vv;
         qi = (T)(eps * vv);
       }
       Qz[f] = {qr, qi};
-      lds_cx_store(R0, (s * 3 + f) * NN + node, Qz[f]);
+      T *sp = S + ((s * 3 + f) * NN + node) * L;
+      sp[0] = qr;
+      if constexpr (CS) sp[1] = qi;
     }
     const cx<T> H = Qz[0], M1 = Qz[1], M2 = Qz[2];
     if (!(H.r > T(0))) atomicOr(g.err_flag, 2);
     const cx<T> rH = crcp1(H);
-    const cx<T> u1 = cmul(M1, rH), u2 = cmul(M2, rH);
-    const cx<T> H2h = (T(0.5) * gred) * cmul(H, H);
-    const cx<T> m11 = cmul(M1, u1), m12 = cmul(M1, u2), m22 = cmul(M2, u2);
-    const cx<T> f12 = sg * (m12 + e12 * H2h);
-    lds_cx_store(R1, (s * 3 + 0) * NN + node, sg * M1);
-    lds_cx_store(R1, (s * 3 + 1) * NN + node, sg * (m11 + e11 * H2h));
-    lds_cx_store(R1, (s * 3 + 2) * NN + node, f12);
-    lds_cx_store(R2, (s * 3 + 0) * NN + node, sg * M2);
-    lds_cx_store(R2, (s * 3 + 1) * NN + node, f12);
-    lds_cx_store(R2, (s * 3 + 2) * NN + node, sg * (m22 + e22 * H2h));
+    const cx<T> u1 = cmul1(M1, rH), u2 = cmul1(M2, rH);
+    const T H2h = lin<T, CS>((T(0.5) * gred) * cmul1(H, H));
+    const T m11 = lin<T, CS>(cmul1(M1, u1)), m12 = lin<T, CS>(cmul1(M1, u2)), m22 = lin<T, CS>(cmul1(M2, u2));
+    const T l1 = lin<T, CS>(M1), l2 = lin<T, CS>(M2), lH = lin<T, CS>(H);
+    T *fp = Fl + s * 5 * NN + node;
+    fp[0 * NN] = sg * l1;                      // x^1 flux of H
+    fp[1 * NN] = sg * (m11 + e11 * H2h);       // x^1 flux of H u^1
+    fp[2 * NN] = sg * (m12 + e12 * H2h);       // x^1 flux of H u^2 = x^2 flux of H u^1
+    fp[3 * NN] = sg * l2;                      // x^2 flux of H
+    fp[4 * NN] = sg * (m22 + e22 * H2h);       // x^2 flux of H u^2
     // sources per unit sqrt(g): Coriolis -2 Gamma^i_0j H u^j, metric -Gamma^i_jk H u^j u^k
     // (the h^jk Gamma^i_jk term vanishes identically on the cubed sphere, App. B)
-    src1 = -(T(2) * (G101 * M1 + G102 * M2) + (G111 * m11 + (T(2) * G112) * m12));
-    src2 = -(T(2) * (G201 * M1 + G202 * M2) + ((T(2) * G212) * m12 + G222 * m22));
+    src1 = -(T(2) * (G101 * l1 + G102 * l2) + (G111 * m11 + (T(2) * G112) * m12));
+    src2 = -(T(2) * (G201 * l1 + G202 * l2) + ((T(2) * G212) * m12 + G222 * m22));
     if (g.orog) {
-      src1 = src1 - (T)g.orog[gidx] * H;
-      src2 = src2 - (T)g.orog[N + gidx] * H;
+      src1 -= (T)g.orog[gidx] * lH;
+      src2 -= (T)g.orog[N + gidx] * lH;
     }
   }
-  __syncthreads();
-
-  // ---- B1: interior part of the derivative, both directions
-  cx<T> acc[3];
-  if (active) {
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const int b = (s * 3 + f) * NN;
-      cx<T> d = {T(0), T(0)};
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        d = d + sD[ni][k + 1] * lds_cx(R1, b + nj * NS + k);
-        d = d + sD[nj][k + 1] * lds_cx(R2, b + k * NS + ni);
-      }
-      acc[f] = d;
-    }
-  }
-  __syncthreads();
-
-  // ---- B2: own traces (into R1) and halo traces (into R2)
-  // own: task = ((s * 4 + face) * 3 + f) * NS + t ; stored at the same index
-  for (int task = tid; task < nel * 12 * NS; task += blockDim.x) {
-    const int t = task % NS;
-    const int r = task / NS;
-    const int f = r % 3;
-    const int r2 = r / 3;
-    const int face = r2 & 3, es = r2 >> 2;
-    const T *w = (face == 0 || face == 2) ? slm : slp;
-    const int b = (es * 3 + f) * NN + ((face < 2) ? t * NS : t);
-    const int st = (face < 2) ? 1 : NS;
-    cx<T> a = {T(0), T(0)};
-#pragma unroll
-    for (int k = 0; k < NS; ++k) a = a + w[k] * lds_cx(R0, b + k * st);
-    lds_cx_store(R1, task, a);
-  }
-  // halo: task = (h * 3 + f) * NS + t
+  // neighbour states extrapolated to the faces shared with the tile:
+  // task = (h * 3 + f) * NS + t
   for (int task = tid; task < nhalo * 3 * NS; task += blockDim.x) {
     const int t = task % NS;
     const int r = task / NS;
     const int f = r % 3, h = r / 3;
-    const HaloDesc d = hd[h];
-    const int qt = d.rev ? NS - 1 - t : t;
-    const T *w = (d.qface == 0 || d.qface == 2) ? slm : slp;
-    const int first = f * N + d.base + ((d.qface < 2) ? qt * NS : qt);
-    const int st = (d.qface < 2) ? 1 : NS;
-    cx<T> a = {T(0), T(0)};
+    int face, ai;
+    if (h < TY) { face = 0; ai = h; }
+    else if (h < 2 * TY) { face = 1; ai = h - TY; }
+    else if (h < 2 * TY + TX) { face = 2; ai = h - 2 * TY; }
+    else { face = 3; ai = h - 2 * TY - TX; }
+    int qp = p, qe, qi, qf, rev = 0;
+    if (face == 0) { qe = ej0 + ai; qi = ei0 - 1; qf = 1; }
+    else if (face == 1) { qe = ej0 + ai; qi = ei0 + TX; qf = 0; }
+    else if (face == 2) { qi = ei0 + ai; qe = ej0 - 1; qf = 3; }
+    else { qi = ei0 + ai; qe = ej0 + TY; qf = 2; }
+    if (qi < 0 || qi >= ne || qe < 0 || qe >= ne) {   // across a panel edge
+      const int along = (face < 2) ? ej0 + ai : ei0 + ai;
+      qp = g.nb_q[p][face];
+      qf = g.nb_e[p][face];
+      rev = g.nb_rev[p][face];
+      const int qa = rev ? ne - 1 - along : along;
+      if (qf == 0) { qi = 0; qe = qa; }
+      else if (qf == 1) { qi = ne - 1; qe = qa; }
+      else if (qf == 2) { qe = 0; qi = qa; }
+      else { qe = ne - 1; qi = qa; }
+    }
+    const int qt = rev ? NS - 1 - t : t;
+    const bool wlo = (qf == 0 || qf == 2);
+    const int first = f * N + ((qp * ne + qe) * ne + qi) * NN + ((qf < 2) ? qt * NS : qt);
+    const int st = (qf < 2) ? 1 : NS;
+    // (the LDS copies of the weights are not yet visible here)
+    T ar_ = T(0), ai_ = T(0);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const int id = first + k * st;
-      T zi = T(0);
-      if (CS) zi = (T)(eps_vs * v[id]);
-      a = a + w[k] * cx<T>{(T)q[id], zi};
+      const T wk = wlo ? (T)ops.lm[k] : (T)ops.lp[k];
+      ar_ += wk * (T)q[id];
+      if constexpr (CS) ai_ += wk * (T)(eps_vs * v[id]);
     }
-    lds_cx_store(R2, task, a);
+    T *tp = TR + (((4 * nel + h) * 3 + f) * NS + t) * L;
+    tp[0] = ar_;
+    if constexpr (CS) tp[1] = ai_;
   }
   __syncthreads();
 
-  // ---- C: common fluxes, each face of the tile once, into R0
-  // vertical faces (x^1 normal): (fx, sy, t), fx = 0..TX ; then horizontal (fy, sx, t)
-  const int nvert = (TX + 1) * TY * NS;
-  const int nflux = nvert + (TY + 1) * TX * NS;
-  for (int task = tid; task < nflux; task += blockDim.x) {
-    const bool vert = task < nvert;
-    const int tk = vert ? task : task - nvert;
-    const int t = tk % NS;
-    const int r = tk / NS;
-    int n, lo_el, hi_el, lo_h, hi_h, ex, ey, fxy;
-    if (vert) {
-      n = 0;
-      const int fy_ = r % TY;   // element row in the tile
-      fxy = r / TY;             // face column 0..TX
-      lo_el = (fxy > 0) ? fy_ * TX + fxy - 1 : -1;
-      hi_el = (fxy < TX) ? fy_ * TX + fxy : -1;
-      lo_h = fy_;               // west halo
-      hi_h = TY + fy_;          // east halo
-      ex = ei0 + fxy;           // edge index along x^1
-      ey = ej0 + fy_;
-    } else {
-      n = 1;
-      const int fx_ = r % TX;
-      fxy = r / TX;             // face row 0..TY
-      lo_el = (fxy > 0) ? (fxy - 1) * TX + fx_ : -1;
-      hi_el = (fxy < TY) ? fxy * TX + fx_ : -1;
-      lo_h = 2 * TY + fx_;      // south halo
-      hi_h = 2 * TY + TX + fx_; // north halo
-      ex = ei0 + fx_;
-      ey = ej0 + fxy;
-    }
-    cx<T> QL[3], QR[3];
-    int hq = -1;   // halo side read (for the App. C map)
+  // ---- B: interior part of the derivative (linear lane), both directions
+  T acc[3] = {T(0), T(0), T(0)};
+  if (active) {
+    const T *fp = Fl + s * 5 * NN;
+    T d0 = T(0), d1 = T(0), d2 = T(0);
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      // own traces of the low element on its high face (E or N), of the high
-      // element on its low face (W or S)
-      if (lo_el >= 0) QL[f] = lds_cx(R1, ((lo_el * 4 + (n == 0 ? 1 : 3)) * 3 + f) * NS + t);
-      else { QL[f] = lds_cx(R2, (lo_h * 3 + f) * NS + t); hq = lo_h; }
-      if (hi_el >= 0) QR[f] = lds_cx(R1, ((hi_el * 4 + (n == 0 ? 0 : 2)) * 3 + f) * NS + t);
-      else { QR[f] = lds_cx(R2, (hi_h * 3 + f) * NS + t); hq = hi_h; }
+    for (int k = 0; k < NS; ++k) {
+      const T cxk = sD[ni][k + 1], cyk = sD[nj][k + 1];
+      const int ix = nj * NS + k, iy = k * NS + ni;
+      d0 += cxk * fp[0 * NN + ix] + cyk * fp[3 * NN + iy];
+      d1 += cxk * fp[1 * NN + ix] + cyk * fp[2 * NN + iy];
+      d2 += cxk * fp[2 * NN + ix] + cyk * fp[4 * NN + iy];
     }
-    if (hq >= 0 && hd[hq].edge) {
-      // App. C: neighbour components -> this panel's basis
-      const int face = (hq < TY) ? 0 : (hq < 2 * TY) ? 1 : (hq < 2 * TY + TX) ? 2 : 3;
-      const int along = (face < 2) ? ey : ex;
-      const double *M = g.xform + (((p * 4 + face) * ne + along) * NS + t) * 4;
+    acc[0] = d0;
+    acc[1] = d1;
+    acc[2] = d2;
+  }
+  // own states extrapolated to both faces of each row (dir 0: W, E) and
+  // column (dir 1: S, N): task = ((es * 2 + dir) * 3 + f) * NS + t
+  for (int task = tid; task < nel * 6 * NS; task += blockDim.x) {
+    const int t = task % NS;
+    const int r = task / NS;
+    const int f = r % 3;
+    const int r2 = r / 3;
+    const int dir = r2 & 1, es = r2 >> 1;
+    const T *sp = S + ((es * 3 + f) * NN + (dir == 0 ? t * NS : t)) * L;
+    const int st = (dir == 0 ? 1 : NS) * L;
+    T lr = T(0), li = T(0), hr = T(0), hi = T(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T zr = sp[k * st];
+      lr += slm[k] * zr;
+      hr += slp[k] * zr;
+      if constexpr (CS) {
+        const T zi = sp[k * st + 1];
+        li += slm[k] * zi;
+        hi += slp[k] * zi;
+      }
+    }
+    T *lo = TR + (((es * 4 + 2 * dir) * 3 + f) * NS + t) * L;
+    T *up = TR + (((es * 4 + 2 * dir + 1) * 3 + f) * NS + t) * L;
+    lo[0] = lr;
+    up[0] = hr;
+    if constexpr (CS) {
+      lo[1] = li;
+      up[1] = hi;
+    }
+  }
+  __syncthreads();
+
+  // ---- C: common fluxes, each face point of the tile once (linear lane) ->
+  // Fl[(face * NS + t) * 3 + f]
+  for (int task = tid; task < nface * NS; task += blockDim.x) {
+    const int fid = task / NS, t = task - fid * NS;
+    const FaceDesc d = FD[fid];
+    const int n = d.info & 1;
+    auto ld_tr = [&](int slot, int f) -> cx<T> {
+      const T *a = TR + ((slot * 3 + f) * NS + t) * L;
+      return {a[0], CS ? a[L - 1] : T(0)};
+    };
+    const cx<T> HL = ld_tr(d.lo, 0), HR = ld_tr(d.hi, 0);
+    cx<T> L1 = ld_tr(d.lo, 1), L2 = ld_tr(d.lo, 2), R1 = ld_tr(d.hi, 1), R2 = ld_tr(d.hi, 2);
+    if (d.xf >= 0) {
+      // App. C: the neighbour's components -> this panel's basis
+      const double *M = g.xform + (int64_t)(d.xf + t) * 4;
       const T m00 = (T)M[0], m01 = (T)M[1], m10 = (T)M[2], m11 = (T)M[3];
-      cx<T> *Qn = (lo_el < 0) ? QL : QR;
-      const cx<T> a1 = m00 * Qn[1] + m01 * Qn[2];
-      const cx<T> a2 = m10 * Qn[1] + m11 * Qn[2];
-      Qn[1] = a1;
-      Qn[2] = a2;
+      if (d.info & 2) {
+        const cx<T> a1 = m00 * L1 + m01 * L2, a2 = m10 * L1 + m11 * L2;
+        L1 = a1;
+        L2 = a2;
+      } else {
+        const cx<T> a1 = m00 * R1 + m01 * R2, a2 = m10 * R1 + m11 * R2;
+        R1 = a1;
+        R2 = a2;
+      }
     }
     // metric at the face point
     T X, Y, ax, ay, rax, ray;
     if (n == 0) {
-      X = (T)g.tedge[ex]; ax = T(1) + X * X; rax = frcp(ax);
-      const Tan3 ty = g.tnode[ey * NS + t];
+      X = (T)g.tedge[d.eedge]; ax = T(1) + X * X; rax = frcp(ax);
+      const Tan3 ty = g.tnode[d.enode * NS + t];
       Y = (T)ty.x; ay = (T)ty.ax; ray = (T)ty.rax;
     } else {
-      const Tan3 tx = g.tnode[ex * NS + t];
+      const Tan3 tx = g.tnode[d.enode * NS + t];
       X = (T)tx.x; ax = (T)tx.ax; rax = (T)tx.rax;
-      Y = (T)g.tedge[ey]; ay = T(1) + Y * Y; ray = frcp(ay);
+      Y = (T)g.tedge[d.eedge]; ay = T(1) + Y * Y; ray = frcp(ay);
     }
     const T d2 = ax + Y * Y;
     const T rd = frsqrt(d2);
     const T sg = ax * ay * rd * rd * rd;
     const T e11 = d2 * rax, e22 = d2 * ray, e12 = X * Y * e11 * ray;
     const T eta1n = n == 0 ? e11 : e12, eta2n = n == 0 ? e12 : e22, etann = n == 0 ? e11 : e22;
-    cx<T> fL[3], fR[3], cL, cR;
-    side_flux1(QL, n, eta1n, eta2n, etann, gred, fL, cL);
-    side_flux1(QR, n, eta1n, eta2n, etann, gred, fR, cR);
+    cx<T> fL0, fL1, fL2, fR0, fR1, fR2, cL, cR;
+    side_flux1(HL, L1, L2, n == 0 ? L1 : L2, eta1n, eta2n, etann, gred, fL0, fL1, fL2, cL);
+    side_flux1(HR, R1, R2, n == 0 ? R1 : R2, eta1n, eta2n, etann, gred, fR0, fR1, fR2, cR);
     const cx<T> lam = (cL.r >= cR.r) ? cL : cR;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const cx<T> F = T(0.5) * (fL[f] + fR[f]) - T(0.5) * cmul(lam, QR[f] - QL[f]);
-      lds_cx_store(R0, task * 3 + f, sg * F);
-    }
+    const T hs = T(0.5) * sg;
+    T *cf = Fl + task * 3;
+    cf[0] = hs * lin<T, CS>((fL0 + fR0) - cmul1(lam, HR - HL));
+    cf[1] = hs * lin<T, CS>((fL1 + fR1) - cmul1(lam, R1 - L1));
+    cf[2] = hs * lin<T, CS>((fL2 + fR2) - cmul1(lam, R2 - L2));
   }
   __syncthreads();
 
@@ -511,16 +565,15 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     const T scale = -(T)g.two_over_delta * rs;
     const T invE = CS ? (T)(1.0 / eps) : T(1);
     const int iW = ((sx * TY + sy) * NS + nj) * 3, iE = (((sx + 1) * TY + sy) * NS + nj) * 3;
-    const int iS = nvert * 3 + ((sy * TX + sx) * NS + ni) * 3, iN = nvert * 3 + (((sy + 1) * TX + sx) * NS + ni) * 3;
+    const int iS = ((nvf + sy * TX + sx) * NS + ni) * 3, iN = ((nvf + (sy + 1) * TX + sx) * NS + ni) * 3;
+    const T cw = sD[ni][0], ce = sD[ni][NS + 1], cs = sD[nj][0], cn = sD[nj][NS + 1];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      cx<T> d = acc[f];
-      d = d + sD[ni][0] * lds_cx(R0, iW + f) + sD[ni][NS + 1] * lds_cx(R0, iE + f);
-      d = d + sD[nj][0] * lds_cx(R0, iS + f) + sD[nj][NS + 1] * lds_cx(R0, iN + f);
-      cx<T> r = scale * d;
-      if (f == 1) r = r + src1;
-      if (f == 2) r = r + src2;
-      w[f] = CS ? (double)(r.i * invE) : (double)r.r;
+      T d = acc[f] + cw * Fl[iW + f] + ce * Fl[iE + f] + cs * Fl[iS + f] + cn * Fl[iN + f];
+      T r = scale * d;
+      if (f == 1) r += src1;
+      if (f == 2) r += src2;
+      w[f] = (double)(r * invE);
     }
     if (!ar.on) {
 #pragma unroll
@@ -536,7 +589,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     for (int f = 0; f < 3; ++f) {
       const int id = f * N + gidx;
       double a = w[f];
-      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * bj[k];
+      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * sbj[k];
       out[id] = a;
       d0 += a * vtrue[f];
       if (ar.vprev) d1 += a * ar.vprev[id];
@@ -837,19 +890,10 @@ static inline int grid_for(int64_t n) {
   return (int)b;
 }
 
-// LDS regions of the tiled kernel, in complex values: R0, R1, R2
-static void dfr_regions(int ns, int tx, int ty, int &r0, int &r1, int &r2) {
-  const int nn = ns * ns, nel = tx * ty, nhalo = 2 * (tx + ty);
-  const int nflux = ((tx + 1) * ty + (ty + 1) * tx) * ns;
-  r0 = std::max(nel * 3 * nn, nflux * 3);
-  r1 = std::max(nel * 3 * nn, nel * 12 * ns);
-  r2 = std::max(nel * 3 * nn, nhalo * 3 * ns);
-}
-
+// dynamic LDS of the tiled kernel (complex-step form, the largest)
 size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32) {
-  int r0, r1, r2;
-  dfr_regions(ns, tx, ty, r0, r1, r2);
-  return (size_t)(r0 + r1 + r2) * 2 * (fp32 ? sizeof(float) : sizeof(double));
+  const int ts = fp32 ? (int)sizeof(float) : (int)sizeof(double);
+  return (size_t)dfr_lds_layout(ns, tx, ty, 2, ts).total * ts;
 }
 
 int64_t dfr_grid_blocks(const Ctx *c) {
@@ -861,14 +905,12 @@ template <int NS, typename T, typename TQ, bool CS>
 static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale, double eps, double *out,
                       const ArnoldiArgs &ar) {
   const int tx = c->tile_tx, ty = c->tile_ty;
-  int r0, r1, r2;
-  dfr_regions(NS, tx, ty, r0, r1, r2);
-  const size_t lds = (size_t)(r0 + r1 + r2) * 2 * sizeof(T);
+  const size_t lds = (size_t)dfr_lds_layout(NS, tx, ty, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T);
   const int threads = ((tx * ty * NS * NS + 63) / 64) * 64;
   const int64_t nb = dfr_grid_blocks(c);
   tbegin(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV));
   hipLaunchKernelGGL((dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(threads), lds, c->stream, c->ga, c->ops,
-                     tx, ty, r0, r1, q, v, vscale, eps, out, ar);
+                     tx, ty, q, v, vscale, eps, out, ar);
   tend(c);
 }
 
