@@ -444,24 +444,24 @@ static void free_ctx(Ctx &c) {
   (void)hipFree(c.d_tmp);
 }
 
-void tbegin(Ctx *c, int kind) {
-  if (!c->timing) return;
+bool timing_slot(Ctx *c, int kind, hipEvent_t *start, hipEvent_t *stop) {
+  if (!c->timing) return false;
   if (c->evused == c->evpool.size()) {
     Ctx::EvPair e{};
     if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
       c->timing = false;
-      return;
+      return false;
     }
     c->evpool.push_back(e);
   }
   Ctx::EvPair &e = c->evpool[c->evused];
   e.kind = kind;
-  (void)hipEventRecord(e.a, c->stream);
+  *start = e.a;
+  *stop = e.b;
+  return true;
 }
 
-void tend(Ctx *c) {
-  if (!c->timing) return;
-  (void)hipEventRecord(c->evpool[c->evused].b, c->stream);
+void timing_done(Ctx *c) {
   c->evused++;
   // fold finished pairs back periodically so the pool stays small
   if (c->evused >= 4096) {

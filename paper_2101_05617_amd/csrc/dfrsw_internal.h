@@ -1,6 +1,7 @@
 // Internal declarations of the MI355X DFR shallow-water library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -139,9 +140,23 @@ struct Ctx {
   int64_t t_n[DFR_K_NKINDS] = {0};
 };
 
-// event bracket around one launch (no-op unless timing is enabled)
-void tbegin(Ctx *c, int kind);
-void tend(Ctx *c);
+// Per-kernel timing: when enabled, a launch takes a start/stop event pair
+// that the runtime stamps at the kernel's own dispatch and completion
+// (hipExtLaunchKernelGGL), so no marker packets are added to the stream.
+bool timing_slot(Ctx *c, int kind, hipEvent_t *start, hipEvent_t *stop);
+void timing_done(Ctx *c);
+
+template <typename... KArgs, typename... Args>
+inline void dfr_launch(Ctx *c, int kind, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem,
+                       Args... args) {
+  hipEvent_t e0, e1;
+  if (timing_slot(c, kind, &e0, &e1)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, c->stream, e0, e1, 0, args...);
+    timing_done(c);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, c->stream, args...);
+  }
+}
 
 // kernels.hip
 int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const double *vscale,

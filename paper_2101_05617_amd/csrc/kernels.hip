@@ -60,6 +60,28 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;   // valid in thread 0
 }
 
+// block-wide sums of two values in a fixed order; valid in thread 0
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wv] = a;
+    red[2 * wv + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      sa += red[2 * k];
+      sb += red[2 * k + 1];
+    }
+    a = sa;
+    b = sb;
+  }
+}
+
 // XCD-aware logical block: consecutive logical blocks land on the same XCD
 // (the dispatcher places block b on XCD b % 8), so neighbouring elements
 // share an L2.
@@ -95,14 +117,15 @@ __device__ double reduce_fixed(const double *pin, int np, int stride, int off, d
   return r;
 }
 
-// Arnoldi prologue: finalise the norm of the vector v_j (start vector, or the
-// vector built by the previous update), giving sigma_j = 1/||.|| for the
-// stored top block and the normalised bottom block b_j.  Returns false (in
-// every workgroup) on a happy breakdown.  Workgroup 0 records the values.
-__device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig, double bj[MAX_P]) {
+// Arnoldi prologue, given the finished sum s of the partial squared norms:
+// the norm of the vector v_j (start vector, or the vector built by the
+// previous update), sigma_j = 1/||.|| for the stored top block and the
+// normalised bottom block b_j.  Returns false on a happy breakdown.  In
+// workgroup 0 the threads lane < nthr record the values (lane 0 the scalars).
+__device__ bool arnoldi_finish(const ArnoldiArgs &ar, double s, int lane, int nthr, double &sig,
+                               double bj[MAX_P]) {
   KDev *kd = ar.kd;
   const int j = ar.j, p = ar.p;
-  const double s = reduce_fixed(ar.pin, ar.np_in, 1, 0, red);
   const int ld = MAX_M + 2;
   const bool w0 = blockIdx.x == 0;
   if (ar.start) {
@@ -112,8 +135,8 @@ __device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig
     sig = 1.0 / beta;
     for (int k = 0; k < p; ++k) bj[k] = ar.ybot[k] / beta;
     if (w0) {
-      for (int k = threadIdx.x; k < ld * ld; k += blockDim.x) kd->H[k] = 0.0;
-      if (threadIdx.x == 0) {
+      for (int k = lane; k < ld * ld; k += nthr) kd->H[k] = 0.0;
+      if (lane == 0) {
         kd->beta = beta;
         kd->sigma[0] = sig;
         for (int k = 0; k < p; ++k) kd->bot[k] = bj[k];
@@ -125,7 +148,7 @@ __device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig
   }
   const double nrm = sqrt(s + kd->wn2[j]);
   if (nrm < ar.tol) {
-    if (w0 && threadIdx.x == 0) {
+    if (w0 && lane == 0) {
       kd->happy = 1;
       kd->J = j;
     }
@@ -133,13 +156,19 @@ __device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig
   }
   sig = 1.0 / nrm;
   for (int k = 0; k < p; ++k) bj[k] = kd->botu[j * MAX_P + k] / nrm;
-  if (w0 && threadIdx.x == 0) {
+  if (w0 && lane == 0) {
     kd->H[j * ld + (j - 1)] = nrm;
     kd->sigma[j] = sig;
     for (int k = 0; k < p; ++k) kd->bot[j * MAX_P + k] = bj[k];
     kd->J = j;
   }
   return true;
+}
+
+// the prologue with its reduction, all threads of the workgroup taking part
+__device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig, double bj[MAX_P]) {
+  const double s = reduce_fixed(ar.pin, ar.np_in, 1, 0, red);
+  return arnoldi_finish(ar, s, threadIdx.x, blockDim.x, sig, bj);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,8 +294,6 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   __shared__ T slm[NS], slp[NS];
   __shared__ double red[256];
 
-  if (ar.on && ar.kd->happy) return;   // uniform: the sub-step ended in a happy breakdown
-
   const int tid = threadIdx.x;
   const int ne = g.ne;
   const int N = (int)g.n;
@@ -289,19 +316,26 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     }
     return;
   }
-  double vs = 1.0;
+  // The direction enters unscaled: J (sigma v) = sigma J v, the scale sigma
+  // (vscale, or the Arnoldi sigma_j) multiplies the result.  In Arnoldi mode
+  // the loads of the previous kernel's partial sums are issued here and the
+  // reduction finished after phase A, off the critical path (blockDim >= 256,
+  // np_in <= 1024: one virtual lane of reduce_fixed per thread tid < 256,
+  // summed in the same order).
   __shared__ double sbj[MAX_P];   // normalised bottom block b_j (read by the epilogue)
+  __shared__ double ssig;         // sigma_j
+  __shared__ int shappy;          // happy breakdown found by this kernel's prologue
+  int happy0 = 0;
+  double pv[4] = {0.0, 0.0, 0.0, 0.0};
   if (ar.on) {
-    double bj[MAX_P];
-    if (!arnoldi_prologue(ar, red, vs, bj)) return;   // uniform
-    if (tid == 0) {
+    happy0 = ar.kd->happy;
+    if (tid < 256) {
 #pragma unroll
-      for (int k = 0; k < MAX_P; ++k)
-        if (k < ar.p) sbj[k] = bj[k];
+      for (int k = 0; k < 4; ++k)
+        if (tid + 256 * k < ar.np_in) pv[k] = ar.pin[tid + 256 * k];
     }
-  } else if (CS && vscale) {
-    vs = *vscale;
   }
+  const double vs_in = (!ar.on && CS && vscale) ? *vscale : 1.0;
   const int p = lb / (ntx * nty);
   const int trow = (lb - p * ntx * nty) / ntx;
   const int tcol = lb - p * ntx * nty - trow * ntx;
@@ -349,7 +383,6 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   const int ei = ei0 + sx, ej = ej0 + sy;
   const int gidx = ((p * ne + ej) * ne + ei) * NN + node;
   const T gred = (T)g.g_red;
-  const double eps_vs = eps * vs;
 
   T src1 = T(0), src2 = T(0);
   T rs = T(0);
@@ -378,7 +411,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
       const T qr = (T)q[f * N + gidx];
       T qi = T(0);
       if constexpr (CS) {
-        const double vv = vs * v[f * N + gidx];
+        const double vv = v[f * N + gidx];
         vtrue[f] = vv;
         qi = (T)(eps * vv);
       }
@@ -447,13 +480,33 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
       const int id = first + k * st;
       const T wk = wlo ? (T)ops.lm[k] : (T)ops.lp[k];
       ar_ += wk * (T)q[id];
-      if constexpr (CS) ai_ += wk * (T)(eps_vs * v[id]);
+      if constexpr (CS) ai_ += wk * (T)(eps * v[id]);
     }
     T *tp = TR + (((4 * nel + h) * 3 + f) * NS + t) * L;
     tp[0] = ar_;
     if constexpr (CS) tp[1] = ai_;
   }
+  if (ar.on) {
+    if (happy0) return;   // uniform: the sub-step ended in a happy breakdown
+    if (tid < 256) red[tid] = ((pv[0] + pv[1]) + pv[2]) + pv[3];
+  }
   __syncthreads();
+  if (ar.on && tid < 64) {
+    // finish the reduction (the fixed butterfly of reduce_fixed) and the
+    // prologue in the first wave; the results are read after two barriers
+    double x = (red[tid] + red[tid + 64]) + (red[tid + 128] + red[tid + 192]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    double sg_, bj[MAX_P];
+    const bool ok = arnoldi_finish(ar, x, tid, 64, sg_, bj);
+    if (tid == 0) {
+      shappy = ok ? 0 : 1;
+      ssig = sg_;
+#pragma unroll
+      for (int k = 0; k < MAX_P; ++k)
+        if (k < ar.p) sbj[k] = bj[k];
+    }
+  }
 
   // ---- B: interior part of the derivative (linear lane), both directions
   T acc[3] = {T(0), T(0), T(0)};
@@ -504,6 +557,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     }
   }
   __syncthreads();
+
+  if (ar.on && shappy) return;   // uniform: happy breakdown found above
 
   // ---- C: common fluxes, each face point of the tile once (linear lane) ->
   // Fl[(face * NS + t) * 3 + f]
@@ -561,6 +616,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 
   // ---- D: face terms, sources, output
   double w[3] = {0.0, 0.0, 0.0};
+  const double vs = ar.on ? ssig : vs_in;
   if (active) {
     const T scale = -(T)g.two_over_delta * rs;
     const T invE = CS ? (T)(1.0 / eps) : T(1);
@@ -573,7 +629,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
       T r = scale * d;
       if (f == 1) r += src1;
       if (f == 2) r += src2;
-      w[f] = (double)(r * invE);
+      w[f] = CS ? (double)(r * invE) * vs : (double)r;
     }
     if (!ar.on) {
 #pragma unroll
@@ -591,15 +647,14 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
       double a = w[f];
       for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * sbj[k];
       out[id] = a;
-      d0 += a * vtrue[f];
+      d0 += a * (vs * vtrue[f]);
       if (ar.vprev) d1 += a * ar.vprev[id];
     }
   }
-  const double b0 = block_sum(d0, red);
-  const double b1 = block_sum(d1, red);
+  block_sum2(d0, d1, red);
   if (tid == 0) {
-    ar.pout[blockIdx.x * 2 + 0] = b0;
-    ar.pout[blockIdx.x * 2 + 1] = b1;
+    ar.pout[blockIdx.x * 2 + 0] = d0;
+    ar.pout[blockIdx.x * 2 + 1] = d1;
   }
 }
 
@@ -906,12 +961,9 @@ static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale
                       const ArnoldiArgs &ar) {
   const int tx = c->tile_tx, ty = c->tile_ty;
   const size_t lds = (size_t)dfr_lds_layout(NS, tx, ty, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T);
-  const int threads = ((tx * ty * NS * NS + 63) / 64) * 64;
+  const int threads = std::max(256, ((tx * ty * NS * NS + 63) / 64) * 64);
   const int64_t nb = dfr_grid_blocks(c);
-  tbegin(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV));
-  hipLaunchKernelGGL((dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(threads), lds, c->stream, c->ga, c->ops,
-                     tx, ty, q, v, vscale, eps, out, ar);
-  tend(c);
+  dfr_launch(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV), (dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
 }
 
 template <int NS>
@@ -975,9 +1027,7 @@ static inline int grid_reduce(int64_t n) {
 int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(arnoldi_first_kernel, dim3(nb), dim3(BLOCK), 0, c->stream, n3, ar, out);
-  tend(c);
+  dfr_launch(c, DFR_K_OTHER, arnoldi_first_kernel, dim3(nb), dim3(BLOCK), 0, n3, ar, out);
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
@@ -987,10 +1037,7 @@ int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, con
                   double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);
-  tbegin(c, DFR_K_UPDATE);
-  hipLaunchKernelGGL(arnoldi_update_kernel, dim3(nb), dim3(BLOCK), 0, c->stream, n3, j, c->kiops_p, w, vj, vprev, pin,
-                     np_in, pout, c->d_kd);
-  tend(c);
+  dfr_launch(c, DFR_K_UPDATE, arnoldi_update_kernel, dim3(nb), dim3(BLOCK), 0, n3, j, c->kiops_p, w, vj, vprev, pin, np_in, pout, c->d_kd);
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
@@ -999,9 +1046,7 @@ int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, con
 int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(arnoldi_start_kernel, dim3(nb), dim3(BLOCK), 0, c->stream, n3, x, v0, pout);
-  tend(c);
+  dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel, dim3(nb), dim3(BLOCK), 0, n3, x, v0, pout);
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
@@ -1009,9 +1054,7 @@ int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out)
 
 int launch_combine(Ctx *c, double *x) {
   const int64_t n3 = 3 * c->n;
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(arnoldi_combine_kernel, dim3(grid_for(n3)), dim3(BLOCK), 0, c->stream, n3, c->d_V, n3, c->d_kd, x);
-  tend(c);
+  dfr_launch(c, DFR_K_OTHER, arnoldi_combine_kernel, dim3(grid_for(n3)), dim3(BLOCK), 0, n3, c->d_V, n3, c->d_kd, x);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
@@ -1019,26 +1062,19 @@ int launch_combine(Ctx *c, double *x) {
 int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol) {
   const int n = ((c->kiops_mmax + 1) + 3) & ~3;
   const size_t lds = (size_t)4 * n * n * sizeof(double);
-  tbegin(c, DFR_K_EXPM);
-  hipLaunchKernelGGL(expm_kernel, dim3(1), dim3(EXPM_BLOCK), lds, c->stream, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin,
-                     pin, np_in, tol);
-  tend(c);
+  dfr_launch(c, DFR_K_EXPM, expm_kernel, dim3(1), dim3(EXPM_BLOCK), lds, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin, pin, np_in, tol);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
 
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out) {
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, c->stream, n, a, x, b, y, out);
-  tend(c);
+  dfr_launch(c, DFR_K_OTHER, axpby_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, n, a, x, b, y, out);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
 
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y) {
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, c->stream, n, x, y);
-  tend(c);
+  dfr_launch(c, DFR_K_OTHER, to_f32_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, n, x, y);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
@@ -1050,9 +1086,7 @@ int launch_fill(Ctx *c, double *q, double *v) {
 }
 
 int launch_check_state(Ctx *c, const double *q) {
-  tbegin(c, DFR_K_OTHER);
-  hipLaunchKernelGGL(check_state_kernel, dim3(grid_for(3 * c->n)), dim3(BLOCK), 0, c->stream, c->n, q, c->d_err);
-  tend(c);
+  dfr_launch(c, DFR_K_OTHER, check_state_kernel, dim3(grid_for(3 * c->n)), dim3(BLOCK), 0, c->n, q, c->d_err);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

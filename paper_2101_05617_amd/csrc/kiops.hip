@@ -78,13 +78,9 @@ static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
       got[i] = 0.0;
       continue;
     }
-    tbegin(&c, DFR_K_OTHER);
-    hipLaunchKernelGGL(norm2_kernel, dim3((unsigned)b), dim3(BLOCK), 0, c.stream, n3, x[i], c.d_partials);
-    tend(&c);
+    dfr_launch(&c, DFR_K_OTHER, norm2_kernel, dim3((unsigned)b), dim3(BLOCK), 0, n3, x[i], c.d_partials);
     DFR_HIP(hipGetLastError());
-    tbegin(&c, DFR_K_FINALIZE);
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(BLOCK), 0, c.stream, (int)b, c.d_partials, d_out);
-    tend(&c);
+    dfr_launch(&c, DFR_K_FINALIZE, sum_kernel, dim3(1), dim3(BLOCK), 0, (int)b, c.d_partials, d_out);
     DFR_HIP(hipGetLastError());
     DFR_HIP(hipMemcpyAsync(&got[i], d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
     DFR_HIP(hipStreamSynchronize(c.stream));
