@@ -21,7 +21,8 @@ namespace dfrsw {
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-int set_expm_lds_limit(int n);
+int set_expm_lds_limit(int m);
+size_t expm_lds_bytes(int m);
 
 // ---------------------------------------------------------------------------
 // Gauss-Legendre points and weights (roots of P_ns), symmetric by construction
@@ -402,7 +403,7 @@ static int alloc_workspace(Ctx &c) {
   DFR_HIP(hipMalloc(&c.d_W, sizeof(double) * MAX_P * n3));
   DFR_HIP(hipMalloc(&c.d_qf32, sizeof(float) * n3));
   DFR_HIP(hipMalloc(&c.d_tmp, sizeof(double) * n3));
-  // the small exponential keeps four (m+1)^2 FP64 matrices in LDS
+  // the small exponential keeps four padded m x m FP64 matrices in LDS
   int lds = 0, lds_optin = 0;
   (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c.device);
   (void)hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, c.device);
@@ -414,14 +415,13 @@ static int alloc_workspace(Ctx &c) {
     const int rc = dfr_set_lds_limits(&c, c.lds_limit);
     if (rc) return rc;
   }
-  int nmax = 1;   // largest n (= m + 1) whose padded size fits
-  while (4 * (((nmax + 1) + 3) & ~3) * (((nmax + 1) + 3) & ~3) * (int)sizeof(double) <= lds) ++nmax;
-  c.max_m = std::min(MAX_M, nmax - 1);
-  if (c.max_m < 2) {
+  c.max_m = MAX_M;   // largest Krylov dimension whose exponential fits in LDS
+  while (c.max_m > 2 && expm_lds_bytes(c.max_m) > (size_t)lds) --c.max_m;
+  if (expm_lds_bytes(c.max_m) > (size_t)lds) {
     set_error("device LDS too small for the Krylov exponential");
     return DFR_E_INVAL;
   }
-  int rc = set_expm_lds_limit(c.max_m + 1);
+  int rc = set_expm_lds_limit(c.max_m);
   if (rc) return rc;
   return DFR_OK;
 }

@@ -757,40 +757,17 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, cons
 // workgroup: scaling to ||.||_1 <= 1, Taylor polynomial of degree 18 in
 // Paterson-Stockmeyer form (blocks of A^2), then repeated squaring.  The
 // truncation error for ||A||_1 <= 1 is below sum_{k>=19} 1/k! < 1e-17.
-// C = A B for n x n row-major matrices in LDS with leading dimension ld
-// (ld = n rounded up to a multiple of 4, padding rows/columns zero): each
-// thread accumulates a 4 x 4 tile in registers, so every LDS value read feeds
-// four FMAs; the k loop is unrolled for independent loads in flight.
-__device__ void lds_matmul(const double *A, const double *B, double *C, int ld) {
-  const int nt = ld / 4;
-  for (int tile = threadIdx.x; tile < nt * nt; tile += blockDim.x) {
-    const int r0 = (tile / nt) * 4, c0 = (tile % nt) * 4;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    const double *a0p = A + r0 * ld, *a1p = a0p + ld, *a2p = a1p + ld, *a3p = a2p + ld;
-#pragma unroll 4
-    for (int k = 0; k < ld; ++k) {
-      const double a0 = a0p[k], a1 = a1p[k], a2 = a2p[k], a3 = a3p[k];
-      const double *bp = B + k * ld + c0;
-      const double b0 = bp[0], b1 = bp[1], b2 = bp[2], b3 = bp[3];
-      acc[0][0] = fma(a0, b0, acc[0][0]); acc[0][1] = fma(a0, b1, acc[0][1]);
-      acc[0][2] = fma(a0, b2, acc[0][2]); acc[0][3] = fma(a0, b3, acc[0][3]);
-      acc[1][0] = fma(a1, b0, acc[1][0]); acc[1][1] = fma(a1, b1, acc[1][1]);
-      acc[1][2] = fma(a1, b2, acc[1][2]); acc[1][3] = fma(a1, b3, acc[1][3]);
-      acc[2][0] = fma(a2, b0, acc[2][0]); acc[2][1] = fma(a2, b1, acc[2][1]);
-      acc[2][2] = fma(a2, b2, acc[2][2]); acc[2][3] = fma(a2, b3, acc[2][3]);
-      acc[3][0] = fma(a3, b0, acc[3][0]); acc[3][1] = fma(a3, b1, acc[3][1]);
-      acc[3][2] = fma(a3, b2, acc[3][2]); acc[3][3] = fma(a3, b3, acc[3][3]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) C[(r0 + i) * ld + c0 + j] = acc[i][j];
-  }
-}
+// ---------------------------------------------------------------------------
+// The small exponential of the Krylov step: E = exp(tau H_aug) with
+// H_aug = [[H_J, e_1], [0, 0]] ((J+1) x (J+1)); only E[:J, 0] (the sub-step
+// result) and E[J-1, J] (the error estimate) are needed.  With A = tau H_J
+// and c = tau e_1, every polynomial in tau H_aug has the form
+// [[p(A), q(A) c], [0, p(0)]]: the J x J block is carried as a matrix (on the
+// matrix cores, FP64 MFMA 16x16x4) and the last column as a vector.
+// Method: scaling and squaring with the degree-18 Taylor polynomial,
+// 1-norm of the scaled matrix <= 1, Paterson-Stockmeyer in A^2.
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Taylor coefficients 1/k!, k = 0..18, and a zero for k = 19 (degree 18)
 __constant__ double kInvFact[20] = {
@@ -799,11 +776,59 @@ __constant__ double kInvFact[20] = {
     1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0, 1.0 / 355687428096000.0,
     1.0 / 6402373705728000.0, 0.0};
 
+// C = X Y for P x P matrices (P = 16 nt) in LDS with leading dimension ld,
+// then C[r][c] = epi(r, c, value).  FP64 MFMA 16x16x4: lane l supplies
+// X[i][k] and Y[k][j] with i = j = l % 16, k = l / 16, and receives
+// D[4 q + l / 16][l % 16] in its q-th accumulator.  Wave w takes the 16x16
+// output tiles w, w + nwaves, ...; two accumulators per tile split the k sum.
+template <typename Epi>
+__device__ void mfma_matmul(const double *X, const double *Y, double *C, int nt, int ld, Epi epi) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int P = 16 * nt;
+  for (int tile = wv; tile < nt * nt; tile += nw) {
+    const int ti = tile / nt, tj = tile - ti * nt;
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const double *xa = X + (ti * 16 + li) * ld + lk;
+    const double *yb = Y + lk * ld + tj * 16 + li;
+    for (int k0 = 0; k0 < P; k0 += 8) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0], yb[k0 * ld], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k0 + 4], yb[(k0 + 4) * ld], acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = ti * 16 + 4 * q + lk, col = tj * 16 + li;
+      C[row * ld + col] = epi(row, col, acc0[q] + acc1[q]);
+    }
+  }
+}
+
+// y[i * ys] = epi(i, sum_k X[i][k] x[k * xs]), i < P: eight lanes per row
+template <typename Epi>
+__device__ void lds_matvec(const double *X, int ld, const double *x, int xs, double *y, int ys, int P, Epi epi) {
+  for (int t = threadIdx.x; t < 8 * P; t += blockDim.x) {
+    const int i = t >> 3, part = t & 7;
+    double s = 0.0;
+    for (int k = part; k < P; k += 8) s = fma(X[i * ld + k], x[k * xs], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    if (part == 0) y[i * ys] = epi(i, s);
+  }
+}
+
+__host__ __device__ inline int expm_pad(int m) { return 16 * ((m + 15) / 16); }
+size_t expm_lds_bytes(int m) {
+  const int P = expm_pad(m);
+  return (size_t)4 * P * (P + 1) * sizeof(double);
+}
+
 __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
-                                                     int np_in, double tol) {
+                                                          int np_in, double tol) {
   extern __shared__ double lds[];
   __shared__ double red[256];
   __shared__ double cnorm;
+  __shared__ double vec[5][MAX_M];   // pc (two buffers), A c, scratch column
   // finalise the norm of the last vector built (unless a happy breakdown
   // already ended the sweep): h_{jfin, jfin-1}, or a happy breakdown
   if (!kd->happy) {
@@ -816,27 +841,23 @@ __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, 
     }
     __syncthreads();
   }
+  const int tid = threadIdx.x;
   const int J = kd->J;
-  const int n = J + 1;
-  const int ld = (n + 3) & ~3;          // padded to whole 4 x 4 tiles (zero padding)
-  const int nn = ld * ld;
-  double *A = lds, *A2 = lds + nn, *P = lds + 2 * nn, *Q = lds + 3 * nn;
+  const int nt = (J + 15) / 16, P = 16 * nt, ld = P + 1;   // odd stride: LDS banks
+  const int nn = P * ld;
+  double *A = lds, *A2 = lds + nn, *Pm = lds + 2 * nn, *Qm = lds + 3 * nn;
   const int hld = MAX_M + 2;
-  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
-    const int i = idx / ld, j = idx - i * ld;
-    double v = 0.0;
-    if (i < J && j < J) v = tau * kd->H[i * hld + j];
-    if (i == 0 && j == J) v = tau;
-    A[idx] = v;
+  for (int idx = tid; idx < P * P; idx += blockDim.x) {
+    const int i = idx / P, j = idx - i * P;
+    A[i * ld + j] = (i < J && j < J) ? tau * kd->H[i * hld + j] : 0.0;
   }
   __syncthreads();
-  // 1-norm (max column sum): the column sums of H_aug are those of tau*H_J
-  // plus tau in column J; four threads per column
-  double cm = 0.0;
-  for (int idx = threadIdx.x; idx < 4 * n; idx += blockDim.x) {
+  // 1-norm of tau H_aug: the column sums of A, and |tau| for the last column
+  double cm = (tid == 0) ? fabs(tau) : 0.0;
+  for (int idx = tid; idx < 4 * P; idx += blockDim.x) {
     const int j = idx >> 2, part = idx & 3;
     double cs = 0.0;
-    for (int i = part; i < n; i += 4) cs += fabs(A[i * ld + j]);
+    for (int i = part; i < P; i += 4) cs += fabs(A[i * ld + j]);
     cs += __shfl_xor(cs, 1, 64);
     cs += __shfl_xor(cs, 2, 64);
     cm = fmax(cm, cs);
@@ -845,9 +866,9 @@ __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, 
     double v = cm;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       double m = 0.0;
       for (int k = 0; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, red[k]);
       cnorm = m;
@@ -856,38 +877,63 @@ __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, 
   }
   int sq = 0;
   if (cnorm > 1.0) sq = (int)ceil(log2(cnorm));
+  const double sc = ldexp(1.0, -sq);
+  const double c0 = tau * sc;   // the scaled last column is c0 e_1
   if (sq > 0) {
-    const double sc = ldexp(1.0, -sq);
-    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) A[idx] *= sc;
-    __syncthreads();
-  }
-  lds_matmul(A, A, A2, ld);
-  __syncthreads();
-  // P = c18 I + c19 A  (padding stays zero: only the leading n x n block is set)
-  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
-    const int i = idx / ld, j = idx - i * ld;
-    P[idx] = ((i == j && i < n) ? kInvFact[18] : 0.0) + kInvFact[19] * A[idx];
-  }
-  __syncthreads();
-  for (int k = 8; k >= 0; --k) {
-    lds_matmul(A2, P, Q, ld);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
-      const int i = idx / ld, j = idx - i * ld;
-      P[idx] = Q[idx] + ((i == j && i < n) ? kInvFact[2 * k] : 0.0) + kInvFact[2 * k + 1] * A[idx];
+    for (int idx = tid; idx < P * P; idx += blockDim.x) {
+      const int i = idx / P, j = idx - i * P;
+      A[i * ld + j] *= sc;
     }
     __syncthreads();
   }
-  for (int r = 0; r < sq; ++r) {
-    lds_matmul(P, P, Q, ld);
-    __syncthreads();
-    double *t = P;
-    P = Q;
-    Q = t;
+  double *pc = vec[0], *pcn = vec[1], *Ac = vec[2];
+  mfma_matmul(A, A, A2, nt, ld, [](int, int, double v) { return v; });
+  if (tid < P) Ac[tid] = c0 * A[tid * ld];
+  __syncthreads();
+  // Paterson-Stockmeyer in A^2, from the top: P = c18 I + c19 A gives, after
+  // one step, P = c18 A^2 + c16 I + c17 A; the last column of the running
+  // polynomial (q(A) c) and its corner entry pz run alongside
+  for (int idx = tid; idx < P * P; idx += blockDim.x) {
+    const int i = idx / P, j = idx - i * P;
+    Pm[i * ld + j] = kInvFact[18] * A2[i * ld + j] + ((i == j && i < J) ? kInvFact[16] : 0.0) +
+                     kInvFact[17] * A[i * ld + j];
   }
-  for (int k = threadIdx.x; k < J; k += blockDim.x) kd->E0[k] = P[k * ld];
-  if (threadIdx.x == 0) {
-    const double eJ = P[(J - 1) * ld + J];
+  if (tid < P) pc[tid] = kInvFact[18] * Ac[tid] + ((tid == 0) ? kInvFact[17] * c0 : 0.0);
+  double pz = kInvFact[16];
+  __syncthreads();
+  for (int k = 7; k >= 0; --k) {
+    const double ca = kInvFact[2 * k], cb = kInvFact[2 * k + 1];
+    // last column: q_new(A) c = A^2 (q(A) c) + pz A c + cb c
+    const double pzo = pz;
+    lds_matvec(A2, ld, pc, 1, pcn, 1, P, [&](int i, double v) { return v + pzo * Ac[i] + ((i == 0) ? cb * c0 : 0.0); });
+    if (k > 0 || sq > 0) {
+      mfma_matmul(A2, Pm, Qm, nt, ld, [&](int r, int c, double v) {
+        return v + ((r == c && r < J) ? ca : 0.0) + cb * A[r * ld + c];
+      });
+    } else {
+      // no squaring follows: only the first column is needed
+      lds_matvec(A2, ld, Pm, ld, Qm, ld, P, [&](int i, double v) { return v + ((i == 0) ? ca : 0.0) + cb * A[i * ld]; });
+    }
+    pz = ca;
+    __syncthreads();
+    double *t = Pm; Pm = Qm; Qm = t;
+    t = pc; pc = pcn; pcn = t;
+  }
+  // squarings: [[P, pc], [0, pz]]^2 = [[P^2, P pc + pz pc], [0, pz^2]]
+  for (int r = 1; r <= sq; ++r) {
+    const double pzo = pz;
+    const double *pco = pc;
+    lds_matvec(Pm, ld, pc, 1, pcn, 1, P, [&](int i, double v) { return v + pzo * pco[i]; });
+    if (r < sq) mfma_matmul(Pm, Pm, Qm, nt, ld, [](int, int, double v) { return v; });
+    else lds_matvec(Pm, ld, Pm, ld, Qm, ld, P, [](int, double v) { return v; });
+    pz = pzo * pzo;
+    __syncthreads();
+    double *t = Pm; Pm = Qm; Qm = t;
+    t = pc; pc = pcn; pcn = t;
+  }
+  for (int k = tid; k < J; k += blockDim.x) kd->E0[k] = Pm[k * ld];
+  if (tid == 0) {
+    const double eJ = pc[J - 1];
     const double hl = kd->happy ? 0.0 : kd->H[J * hld + (J - 1)];
     kd->eJ = eJ;
     kd->hlast = hl;
@@ -1060,8 +1106,7 @@ int launch_combine(Ctx *c, double *x) {
 }
 
 int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol) {
-  const int n = ((c->kiops_mmax + 1) + 3) & ~3;
-  const size_t lds = (size_t)4 * n * n * sizeof(double);
+  const size_t lds = expm_lds_bytes(c->kiops_mmax);
   dfr_launch(c, DFR_K_EXPM, expm_kernel, dim3(1), dim3(EXPM_BLOCK), lds, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin, pin, np_in, tol);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
@@ -1091,9 +1136,8 @@ int launch_check_state(Ctx *c, const double *q) {
   return DFR_OK;
 }
 
-int set_expm_lds_limit(int n) {
-  n = (n + 3) & ~3;
-  const size_t lds = (size_t)4 * n * n * sizeof(double);
+int set_expm_lds_limit(int m) {
+  const size_t lds = expm_lds_bytes(m);
   DFR_HIP(hipFuncSetAttribute((const void *)expm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return DFR_OK;
 }
