@@ -156,7 +156,8 @@ def main():
 
     g = dfrsw.Grid(w.ne, w.p, *w.constants())
     tile = dfrsw.dfr_autotune(g, "fp64")
-    log(f"autotuned tile {tile}")
+    tile_kr = dfrsw.dfr_get_krylov_tile(g)
+    log(f"autotuned tiles: plain {tile}, Krylov form {tile_kr}")
     P, B1, B2 = g.node_frames()
     Q, hB = inputs.initial_state(w, P, B1, B2)
     q0 = torch.from_numpy(Q).cuda()
@@ -232,6 +233,7 @@ def main():
                    "ne": w.ne, "p": w.p, "nodes": N, "order": w.order, "dt_s": w.dt_s,
                    "timed_steps_include_startup": timed_includes_startup},
         "tile": tile,
+        "tile_krylov": tile_kr,
         "jv_per_s": 1e3 / jv_ms,
         "jv_per_s_fp32": 1e3 / jv32_ms,
         "jv_in_step_per_s": n_jv / wall,

@@ -69,7 +69,7 @@ typedef struct {
   double tol;        /* relative tolerance of the phi-combination */
   int m_init;        /* initial Krylov dimension */
   int m_min, m_max;  /* bounds of the Krylov dimension (m_max <= 64) */
-  int iop;           /* incomplete orthogonalisation length (>= 1) */
+  int iop;           /* incomplete orthogonalisation length: 1 or 2 */
   int max_attempts;  /* cap on sub-step attempts before DFR_E_KIOPS */
 } kiops_opts;
 
@@ -97,14 +97,18 @@ int dfr_sync(dfr_ctx *ctx);
 
 /* Work decomposition of the DFR kernel: a workgroup takes a tile of
  * tile_tx x tile_ty elements of one panel (both dividing ne, one thread per
- * GL node, at most 1024 nodes).  dfr_create picks a default; dfr_set_tile
- * overrides it (DFR_E_INVAL if not admissible); dfr_autotune times the
- * complex-step kernel of the given precision for every admissible tile on a
- * synthetic state and keeps the fastest (synchronises; uses the context's
- * Krylov workspace as scratch).  Results are identical for every tile up to
- * rounding. */
+ * GL node, at most 1024 nodes).  The products inside kiops_phi_apply (with
+ * the fused Arnoldi steps) have a tile of their own.  dfr_create picks a
+ * default for both; dfr_set_tile sets both (DFR_E_INVAL if not admissible);
+ * dfr_autotune times the complex-step kernel of the given precision, plain
+ * and in its Krylov form, for every admissible tile on a synthetic state and
+ * keeps the fastest of each (synchronises; uses the context's Krylov
+ * workspace as scratch) and returns the plain one.  dfr_get_tile returns the
+ * tile of dfr_rhs / dfr_jvp_complex_step, dfr_get_krylov_tile the other.
+ * Results are identical for every tile up to rounding. */
 int dfr_set_tile(dfr_ctx *ctx, int tile_tx, int tile_ty);
 int dfr_get_tile(const dfr_ctx *ctx, int *tile_tx, int *tile_ty);
+int dfr_get_krylov_tile(const dfr_ctx *ctx, int *tile_tx, int *tile_ty);
 int dfr_autotune(dfr_ctx *ctx, dfr_precision prec, int *tile_tx, int *tile_ty);
 
 /* dqdt = F(q): the DFR right-hand side of the covariant shallow-water

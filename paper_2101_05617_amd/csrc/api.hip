@@ -383,8 +383,8 @@ static void default_tile(Ctx &c) {
       best = (int)k;
     }
   }
-  c.tile_tx = cand[best].first;
-  c.tile_ty = cand[best].second;
+  c.tile_tx = c.ar_tx = cand[best].first;
+  c.tile_ty = c.ar_ty = cand[best].second;
 }
 
 static int alloc_workspace(Ctx &c) {
@@ -510,6 +510,26 @@ int latched_error(Ctx &c) {
 
 }  // namespace dfrsw
 
+namespace dfrsw {
+// mean duration (ms) of `reps` launches after two untimed ones
+template <typename F>
+static int time_launches(Ctx &c, hipEvent_t e0, hipEvent_t e1, int reps, F launch, float *ms) {
+  int rc = DFR_OK;
+  for (int r = 0; r < 2 + reps && !rc; ++r) {
+    if (r == 2) (void)hipEventRecord(e0, c.stream);
+    rc = launch();
+  }
+  if (rc) return rc;
+  (void)hipEventRecord(e1, c.stream);
+  (void)hipEventSynchronize(e1);
+  *ms = 0.f;
+  (void)hipEventElapsedTime(ms, e0, e1);
+  *ms /= reps;
+  return DFR_OK;
+}
+
+}  // namespace dfrsw
+
 using namespace dfrsw;
 
 extern "C" {
@@ -618,8 +638,8 @@ int dfr_set_tile(dfr_ctx *h, int tx, int ty) {
   Ctx &c = h->c;
   for (const auto &t : tile_candidates(c))
     if (t.first == tx && t.second == ty) {
-      c.tile_tx = tx;
-      c.tile_ty = ty;
+      c.tile_tx = c.ar_tx = tx;
+      c.tile_ty = c.ar_ty = ty;
       return DFR_OK;
     }
   set_error("tile not admissible (TX, TY must divide ne, TX*TY*(p+1)^2 <= 1024, LDS within limit)");
@@ -630,6 +650,13 @@ int dfr_get_tile(const dfr_ctx *h, int *tx, int *ty) {
   if (!h || !tx || !ty) return DFR_E_INVAL;
   *tx = h->c.tile_tx;
   *ty = h->c.tile_ty;
+  return DFR_OK;
+}
+
+int dfr_get_krylov_tile(const dfr_ctx *h, int *tx, int *ty) {
+  if (!h || !tx || !ty) return DFR_E_INVAL;
+  *tx = h->c.ar_tx;
+  *ty = h->c.ar_ty;
   return DFR_OK;
 }
 
@@ -646,39 +673,62 @@ int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
     rc = launch_copy_to_f32(&c, n3, q, (float *)c.d_qf32);
     if (rc) return rc;
   }
+  const double eps = fp32 ? 1e-20 : 1e-150;
+  // the Krylov form: start of a sweep with four b-columns and a previous
+  // vector (the KIOPS state is re-initialised by every sweep)
+  ArnoldiArgs ar{};
+  ar.on = 1;
+  ar.j = 0;
+  ar.p = std::min(4, MAX_P);
+  ar.start = 1;
+  for (int k = 0; k < ar.p; ++k) ar.W[k] = v;
+  ar.vprev = q;
+  ar.pin = q;
+  ar.np_in = 1;
+  ar.pout = c.d_partials;
+  ar.kd = c.d_kd;
+  ar.tol = 0.0;
+  ar.ybot[0] = 1.0;
+  DFR_HIP(hipMemsetAsync(&c.d_kd->happy, 0, sizeof(int), c.stream));
   hipEvent_t e0, e1;
   DFR_HIP(hipEventCreate(&e0));
   DFR_HIP(hipEventCreate(&e1));
-  const int keep_tx = c.tile_tx, keep_ty = c.tile_ty;
-  float best = 1e30f;
-  int btx = keep_tx, bty = keep_ty;
+  const int keep[4] = {c.tile_tx, c.tile_ty, c.ar_tx, c.ar_ty};
+  float best = 1e30f, best_ar = 1e30f;
+  int bt[4] = {keep[0], keep[1], keep[2], keep[3]};
   const bool was_timing = c.timing;
   c.timing = false;
   for (const auto &t : tile_candidates(c)) {
-    c.tile_tx = t.first;
-    c.tile_ty = t.second;
-    const int reps = 5;
-    for (int r = 0; r < 2 + reps; ++r) {
-      if (r == 2) (void)hipEventRecord(e0, c.stream);
-      rc = launch_dfr(&c, q, (const float *)c.d_qf32, v, nullptr, fp32 ? 1e-20 : 1e-150, true, fp32, w, nullptr);
-      if (rc) break;
-    }
-    if (rc) break;
-    (void)hipEventRecord(e1, c.stream);
-    (void)hipEventSynchronize(e1);
+    c.tile_tx = c.ar_tx = t.first;
+    c.tile_ty = c.ar_ty = t.second;
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
+    rc = time_launches(c, e0, e1, 5, [&] {
+      return launch_dfr(&c, q, (const float *)c.d_qf32, v, nullptr, eps, true, fp32, w, nullptr);
+    }, &ms);
+    if (rc) break;
     if (ms < best) {
       best = ms;
-      btx = t.first;
-      bty = t.second;
+      bt[0] = t.first;
+      bt[1] = t.second;
+    }
+    rc = time_launches(c, e0, e1, 5, [&] {
+      return launch_dfr(&c, q, (const float *)c.d_qf32, v, nullptr, eps, true, fp32, w, &ar);
+    }, &ms);
+    if (rc) break;
+    if (ms < best_ar) {
+      best_ar = ms;
+      bt[2] = t.first;
+      bt[3] = t.second;
     }
   }
   c.timing = was_timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c.tile_tx = rc ? keep_tx : btx;
-  c.tile_ty = rc ? keep_ty : bty;
+  const int *use = rc ? keep : bt;
+  c.tile_tx = use[0];
+  c.tile_ty = use[1];
+  c.ar_tx = use[2];
+  c.ar_ty = use[3];
   if (tile_tx) *tile_tx = c.tile_tx;
   if (tile_ty) *tile_ty = c.tile_ty;
   return rc ? rc : latched_error(c);

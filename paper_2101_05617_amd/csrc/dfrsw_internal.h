@@ -120,6 +120,7 @@ struct Ctx {
   int kiops_mmax = 0, kiops_p = 0;
   int max_m = MAX_M;              // Krylov cap from the LDS available to one workgroup
   int tile_tx = 1, tile_ty = 1;   // elements per workgroup of the DFR kernel (x^1, x^2)
+  int ar_tx = 1, ar_ty = 1;       // the same for the J*v kernel with the Arnoldi prologue/epilogue
   size_t lds_limit = 65536;       // LDS one workgroup may use
   double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N
   double *d_W = nullptr;          // MAX_P scaled b columns of 3N
@@ -162,7 +163,7 @@ inline void dfr_launch(Ctx *c, int kind, void (*kernel)(KArgs...), dim3 grid, di
 int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const double *vscale,
                double eps, bool complex_step, bool fp32, double *out, const ArnoldiArgs *ar);
 int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out);
-int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, const double *pin, int np_in,
+int launch_update(Ctx *c, int j, double *w, const double *vj, const double *vprev, const double *pin, int np_in,
                   double *pout, int *np_out);
 int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out);
 int launch_combine(Ctx *c, double *x);
@@ -174,7 +175,7 @@ int launch_fill(Ctx *c, double *q, double *v);
 int latched_error(Ctx &c);
 size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32);
 int dfr_set_lds_limits(Ctx *c, size_t bytes);
-int64_t dfr_grid_blocks(const Ctx *c);
+int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi);
 
 }  // namespace dfrsw
 

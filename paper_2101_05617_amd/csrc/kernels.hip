@@ -117,6 +117,40 @@ __device__ double reduce_fixed(const double *pin, int np, int stride, int off, d
   return r;
 }
 
+// reduce_fixed of the two interleaved sets pin[2k] and pin[2k+1] in one
+// pass (the same order, hence the same values).  red: 512 doubles of LDS.
+__device__ void reduce_fixed2(const double *pin, int np, double *red, double &s0, double &s1) {
+  __syncthreads();
+  for (int l = threadIdx.x; l < 256; l += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int k = l; k < np; k += 256) {
+      a += pin[2 * (int64_t)k];
+      b += pin[2 * (int64_t)k + 1];
+    }
+    red[l] = a;
+    red[256 + l] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double x = (red[l] + red[l + 64]) + (red[l + 128] + red[l + 192]);
+    double y = (red[256 + l] + red[256 + l + 64]) + (red[256 + l + 128] + red[256 + l + 192]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      x += __shfl_xor(x, o, 64);
+      y += __shfl_xor(y, o, 64);
+    }
+    if (l == 0) {
+      red[0] = x;
+      red[256] = y;
+    }
+  }
+  __syncthreads();
+  s0 = red[0];
+  s1 = red[256];
+  __syncthreads();
+}
+
 // Arnoldi prologue, given the finished sum s of the partial squared norms:
 // the norm of the vector v_j (start vector, or the vector built by the
 // previous update), sigma_j = 1/||.|| for the stored top block and the
@@ -281,7 +315,7 @@ __device__ __forceinline__ T lin(cx<T> z) {
   else return z.r;
 }
 
-template <int NS, typename T, typename TQ, bool CS>
+template <int NS, typename T, typename TQ, bool CS, bool AR>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
                                                                const int TY, const TQ *__restrict__ q,
                                                                const double *__restrict__ v,
@@ -310,7 +344,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 
   const int lb = (int)logical_block(6 * ntx * nty);
   if (lb < 0) {                        // uniform: padding block of the XCD mapping
-    if (ar.on && tid == 0) {
+    if (AR && tid == 0) {
       ar.pout[blockIdx.x * 2 + 0] = 0.0;
       ar.pout[blockIdx.x * 2 + 1] = 0.0;
     }
@@ -322,12 +356,11 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   // reduction finished after phase A, off the critical path (blockDim >= 256,
   // np_in <= 1024: one virtual lane of reduce_fixed per thread tid < 256,
   // summed in the same order).
-  __shared__ double sbj[MAX_P];   // normalised bottom block b_j (read by the epilogue)
   __shared__ double ssig;         // sigma_j
   __shared__ int shappy;          // happy breakdown found by this kernel's prologue
   int happy0 = 0;
   double pv[4] = {0.0, 0.0, 0.0, 0.0};
-  if (ar.on) {
+  if constexpr (AR) {
     happy0 = ar.kd->happy;
     if (tid < 256) {
 #pragma unroll
@@ -335,7 +368,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
         if (tid + 256 * k < ar.np_in) pv[k] = ar.pin[tid + 256 * k];
     }
   }
-  const double vs_in = (!ar.on && CS && vscale) ? *vscale : 1.0;
+  const double vs_in = (!AR && CS && vscale) ? *vscale : 1.0;
   const int p = lb / (ntx * nty);
   const int trow = (lb - p * ntx * nty) / ntx;
   const int tcol = lb - p * ntx * nty - trow * ntx;
@@ -387,6 +420,23 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   T src1 = T(0), src2 = T(0);
   T rs = T(0);
   double vtrue[3] = {0.0, 0.0, 0.0};
+  // Arnoldi: the b-column combination of the augmented operator and the
+  // previous basis vector are read here, in flight during the computation.
+  // With the unnormalised bottom block u_j (the start vector's mu y, or the
+  // one left by the previous update), w_j = sigma_j (J v~_j + W u_j).
+  double wb[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
+  if (AR && active) {
+    const double *ub = ar.kd->botu + ar.j * MAX_P;
+    const double sp = ar.vprev ? ar.kd->sigma[ar.j - 1] : 0.0;   // v_{j-1} = sigma_{j-1} v~_{j-1}
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int id = f * N + gidx;
+      double a = 0.0;
+      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
+      wb[f] = a;
+      if (ar.vprev) vp[f] = sp * ar.vprev[id];
+    }
+  }
 
   // ---- A: state, nodal fluxes, sources
   if (active) {
@@ -486,12 +536,12 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     tp[0] = ar_;
     if constexpr (CS) tp[1] = ai_;
   }
-  if (ar.on) {
+  if constexpr (AR) {
     if (happy0) return;   // uniform: the sub-step ended in a happy breakdown
     if (tid < 256) red[tid] = ((pv[0] + pv[1]) + pv[2]) + pv[3];
   }
   __syncthreads();
-  if (ar.on && tid < 64) {
+  if (AR && tid < 64) {
     // finish the reduction (the fixed butterfly of reduce_fixed) and the
     // prologue in the first wave; the results are read after two barriers
     double x = (red[tid] + red[tid + 64]) + (red[tid + 128] + red[tid + 192]);
@@ -502,9 +552,6 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
     if (tid == 0) {
       shappy = ok ? 0 : 1;
       ssig = sg_;
-#pragma unroll
-      for (int k = 0; k < MAX_P; ++k)
-        if (k < ar.p) sbj[k] = bj[k];
     }
   }
 
@@ -558,7 +605,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   }
   __syncthreads();
 
-  if (ar.on && shappy) return;   // uniform: happy breakdown found above
+  if (AR && shappy) return;   // uniform: happy breakdown found above
 
   // ---- C: common fluxes, each face point of the tile once (linear lane) ->
   // Fl[(face * NS + t) * 3 + f]
@@ -616,7 +663,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 
   // ---- D: face terms, sources, output
   double w[3] = {0.0, 0.0, 0.0};
-  const double vs = ar.on ? ssig : vs_in;
+  double wr[3] = {0.0, 0.0, 0.0};   // Im F / (eps sigma) in FP64, Arnoldi form
+  const double vs = AR ? ssig : vs_in;
   if (active) {
     const T scale = -(T)g.two_over_delta * rs;
     const T invE = CS ? (T)(1.0 / eps) : T(1);
@@ -630,25 +678,26 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
       if (f == 1) r += src1;
       if (f == 2) r += src2;
       w[f] = CS ? (double)(r * invE) * vs : (double)r;
+      wr[f] = (double)r;
     }
-    if (!ar.on) {
+    if constexpr (!AR) {
 #pragma unroll
       for (int f = 0; f < 3; ++f) out[f * N + gidx] = w[f];
     }
   }
-  if (!ar.on) return;
+  if constexpr (!AR) return;
 
-  // ---- Arnoldi epilogue: w += sum_k W_k c_k ; partial <v_j, w>, <v_{j-1}, w>
+  // ---- Arnoldi epilogue: w = sigma_j (J v~_j + W u_j); partial <v_j, w>, <v_{j-1}, w>
   double d0 = 0.0, d1 = 0.0;
   if (active) {
+    const double invE = 1.0 / eps;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int id = f * N + gidx;
-      double a = w[f];
-      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * sbj[k];
+      const double a = vs * (wr[f] * invE + wb[f]);
       out[id] = a;
       d0 += a * (vs * vtrue[f]);
-      if (ar.vprev) d1 += a * ar.vprev[id];
+      d1 += a * vp[f];
     }
   }
   block_sum2(d0, d1, red);
@@ -679,17 +728,33 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const 
 // Gram-Schmidt step.  Prologue: the inner products h_{j,j}, h_{j-1,j} (top
 // partials of the J v kernel plus the bottom blocks; classical Gram-Schmidt
 // over the last two vectors) and the new bottom block, recorded by workgroup
-// 0.  Body: w <- w - h_jj sigma_j v~_j - h_{j-1,j} v_{j-1}; v_j <- sigma_j v~_j
-// (stored normalised); partial ||w||^2 per workgroup.
-__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, double *w, double *vj,
+// 0.  Body: w <- w - h_jj sigma_j v~_j - h_{j-1,j} sigma_{j-1} v~_{j-1};
+// partial ||w||^2 per workgroup.  Basis vectors stay as built (v~_k), their
+// scales sigma_k kept in KDev.  The first UNROLL elements of each thread are
+// read before the prologue, in flight during its reductions.
+__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, double *w, const double *vj,
                                                                const double *vprev, const double *pin, int np_in,
                                                                double *pout, KDev *kd) {
-  __shared__ double red[256];
-  if (kd->happy) return;
-  const double d0 = reduce_fixed(pin, np_in, 2, 0, red);
-  const double d1 = reduce_fixed(pin, np_in, 2, 1, red);
-  const int ld = MAX_M + 2;
+  constexpr int UNROLL = 4;
+  __shared__ double red[512];
   const bool two = (j >= 1) && (vprev != nullptr);
+  const int64_t gs = (int64_t)gridDim.x * BLOCK;
+  const int64_t i0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  double xw[UNROLL], xv[UNROLL], xp[UNROLL];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    const int64_t i = i0 + u * gs;
+    xw[u] = xv[u] = xp[u] = 0.0;
+    if (i < n3) {
+      xw[u] = w[i];
+      xv[u] = vj[i];
+      if (two) xp[u] = vprev[i];
+    }
+  }
+  if (kd->happy) return;
+  double d0, d1;
+  reduce_fixed2(pin, np_in, red, d0, d1);
+  const int ld = MAX_M + 2;
   const double *bj = kd->bot + j * MAX_P;
   const double *bp = kd->bot + (j - (j >= 1 ? 1 : 0)) * MAX_P;
   double wb[MAX_P];
@@ -713,14 +778,22 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j
     }
     kd->wn2[j + 1] = nb2;
   }
-  const double sj = kd->sigma[j];
+  const double ca = hjj * kd->sigma[j];
+  const double cb = two ? hpj * kd->sigma[j - 1] : 0.0;
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
-    const double vv = sj * vj[i];
-    double x = w[i] - hjj * vv;
-    if (two) x -= hpj * vprev[i];
+#pragma unroll
+  for (int u = 0; u < UNROLL; ++u) {
+    const int64_t i = i0 + u * gs;
+    if (i < n3) {
+      const double x = (xw[u] - ca * xv[u]) - cb * xp[u];
+      w[i] = x;
+      acc += x * x;
+    }
+  }
+  for (int64_t i = i0 + UNROLL * gs; i < n3; i += gs) {
+    double x = w[i] - ca * vj[i];
+    if (two) x -= cb * vprev[i];
     w[i] = x;
-    vj[i] = vv;
     acc += x * x;
   }
   const double b = block_sum(acc, red);
@@ -740,14 +813,14 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const 
   if (threadIdx.x == 0) pout[blockIdx.x] = b;
 }
 
-// accepted sub-step: x = beta * sum_{k<J} v_k E[k][0]
+// accepted sub-step: x = beta * sum_{k<J} sigma_k v~_k E[k][0]
 __global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, const double *V, int64_t ldv, const KDev *kd,
                                                                 double *x) {
   const int J = kd->J;
   const double beta = kd->beta;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
     double acc = 0.0;
-    for (int k = 0; k < J; ++k) acc += V[k * ldv + i] * kd->E0[k];
+    for (int k = 0; k < J; ++k) acc += V[k * ldv + i] * (kd->sigma[k] * kd->E0[k]);
     x[i] = beta * acc;
   }
 }
@@ -997,29 +1070,30 @@ size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32) {
   return (size_t)dfr_lds_layout(ns, tx, ty, 2, ts).total * ts;
 }
 
-int64_t dfr_grid_blocks(const Ctx *c) {
-  const int64_t nlog = 6LL * (c->ne / c->tile_tx) * (c->ne / c->tile_ty);
+int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi) {
+  const int tx = arnoldi ? c->ar_tx : c->tile_tx, ty = arnoldi ? c->ar_ty : c->tile_ty;
+  const int64_t nlog = 6LL * (c->ne / tx) * (c->ne / ty);
   return ((nlog + 7) / 8) * 8;
 }
 
-template <int NS, typename T, typename TQ, bool CS>
+template <int NS, typename T, typename TQ, bool CS, bool AR>
 static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale, double eps, double *out,
                       const ArnoldiArgs &ar) {
-  const int tx = c->tile_tx, ty = c->tile_ty;
+  const int tx = ar.on ? c->ar_tx : c->tile_tx, ty = ar.on ? c->ar_ty : c->tile_ty;
   const size_t lds = (size_t)dfr_lds_layout(NS, tx, ty, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T);
   const int threads = std::max(256, ((tx * ty * NS * NS + 63) / 64) * 64);
-  const int64_t nb = dfr_grid_blocks(c);
-  dfr_launch(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV), (dfr_kernel<NS, T, TQ, CS>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
+  const int64_t nb = dfr_grid_blocks(c, ar.on != 0);
+  dfr_launch(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV), (dfr_kernel<NS, T, TQ, CS, AR>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
 }
 
 template <int NS>
 static int set_lds_attr(size_t bytes) {
-  DFR_HIP(hipFuncSetAttribute((const void *)dfr_kernel<NS, double, double, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  DFR_HIP(hipFuncSetAttribute((const void *)dfr_kernel<NS, double, double, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  DFR_HIP(hipFuncSetAttribute((const void *)dfr_kernel<NS, float, float, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  const void *fns[] = {(const void *)dfr_kernel<NS, double, double, false, false>,
+                       (const void *)dfr_kernel<NS, double, double, true, false>,
+                       (const void *)dfr_kernel<NS, float, float, true, false>,
+                       (const void *)dfr_kernel<NS, double, double, true, true>,
+                       (const void *)dfr_kernel<NS, float, float, true, true>};
+  for (const void *f : fns) DFR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return DFR_OK;
 }
 
@@ -1041,13 +1115,20 @@ template <typename T, typename TQ, bool CS>
 static int dispatch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale, double eps, double *out,
                        const ArnoldiArgs &ar) {
   switch (c->ns) {
-    case 2: launch_ns<2, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
-    case 3: launch_ns<3, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
-    case 4: launch_ns<4, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
-    case 5: launch_ns<5, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
-    case 6: launch_ns<6, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
-    case 7: launch_ns<7, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
-    case 8: launch_ns<8, T, TQ, CS>(c, q, v, vscale, eps, out, ar); break;
+    case 2: ar.on ? launch_ns<2, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<2, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
+    case 3: ar.on ? launch_ns<3, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<3, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
+    case 4: ar.on ? launch_ns<4, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<4, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
+    case 5: ar.on ? launch_ns<5, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<5, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
+    case 6: ar.on ? launch_ns<6, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<6, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
+    case 7: ar.on ? launch_ns<7, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<7, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
+    case 8: ar.on ? launch_ns<8, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
+            : launch_ns<8, T, TQ, CS, false>(c, q, v, vscale, eps, out, ar); break;
     default: set_error("unsupported number of GL points"); return DFR_E_INVAL;
   }
   DFR_HIP(hipGetLastError());
@@ -1079,7 +1160,7 @@ int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out
   return DFR_OK;
 }
 
-int launch_update(Ctx *c, int j, double *w, double *vj, const double *vprev, const double *pin, int np_in,
+int launch_update(Ctx *c, int j, double *w, const double *vj, const double *vprev, const double *pin, int np_in,
                   double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);

@@ -97,8 +97,8 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
                       const kiops_opts &o, double eps, bool fp32, double *w, KiopsRun &st) {
   const int64_t n3 = 3 * c.n;
   if (!(tau_out > 0.0) || !(o.tol > 0.0) || o.m_max < 1 || o.m_max > MAX_M || o.m_min < 1 || o.iop < 1 ||
-      n_phi < 0 || n_phi > MAX_P) {
-    set_error("kiops: invalid options (need tau > 0, tol > 0, 1 <= m_min, m_max <= 64, iop >= 1, n_phi <= 8)");
+      o.iop > 2 || n_phi < 0 || n_phi > MAX_P) {
+    set_error("kiops: invalid options (need tau > 0, tol > 0, 1 <= m_min, m_max <= 64, iop = 1 or 2, n_phi <= 8)");
     return DFR_E_INVAL;
   }
   if (o.m_max > c.max_m) {
@@ -202,7 +202,7 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
         skipped = true;
       } else {
         rc = launch_dfr(&c, q, q32, V + (int64_t)j * n3, nullptr, eps, true, fp32, out, &ar);
-        npA = (int)dfr_grid_blocks(&c);
+        npA = (int)dfr_grid_blocks(&c, true);
       }
       if (rc) return rc;
       rc = launch_update(&c, j, out, V + (int64_t)j * n3, ar.vprev, pA, npA, pB, &npB);

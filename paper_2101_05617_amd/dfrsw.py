@@ -82,6 +82,7 @@ def lib():
             "epi_destroy": (i, [vp]),
             "dfr_set_tile": (i, [vp, i, i]),
             "dfr_get_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
+            "dfr_get_krylov_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_autotune": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_timing_enable": (i, [vp, i]),
             "dfr_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64)]),
@@ -98,7 +99,7 @@ def lib():
 def exported_symbols():
     return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
-            "epi_num_steps", "epi_destroy", "dfr_set_tile", "dfr_get_tile", "dfr_autotune", "dfr_timing_enable",
+            "epi_num_steps", "epi_destroy", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_last_error"]
 
 
@@ -222,6 +223,12 @@ def dfr_set_tile(g: Grid, tx, ty):
 def dfr_get_tile(g: Grid):
     tx, ty = ctypes.c_int(), ctypes.c_int()
     _check(lib().dfr_get_tile(g.handle, ctypes.byref(tx), ctypes.byref(ty)))
+    return tx.value, ty.value
+
+
+def dfr_get_krylov_tile(g: Grid):
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    _check(lib().dfr_get_krylov_tile(g.handle, ctypes.byref(tx), ctypes.byref(ty)))
     return tx.value, ty.value
 
 

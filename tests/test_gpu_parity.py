@@ -201,6 +201,24 @@ def test_kiops_substepping_parity():
     assert np.linalg.norm(to_host(got) - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
+def test_kiops_iop1_parity_and_invalid_iop():
+    # orthogonalisation against the last vector only; iop > 2 is rejected
+    w = small(C0, 3, 4, u_amp=1.0)
+    G, D, Q = pair(w)
+    from paper_2101_05617_amd import dfrsw
+    F = G.rhs(Q)
+    tau = 4 * w.dt_nd
+    ref, rst = okiops.kiops(tau, lambda v: G.jvp(Q, v), [None, F], tol=1e-12, m_max=32, iop=1)
+    got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(1e-12, 32, iop=1))
+    assert (gst["n_substeps"], gst["n_rejected"], gst["n_matvec"]) == (rst.n_substeps, rst.n_rejected, rst.n_matvec)
+    err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
+    record("kiops_iop1", err)
+    assert err <= 1e-11
+    with pytest.raises(dfrsw.DfrError) as e:
+        dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(1e-12, 32, iop=3))
+    assert e.value.code == -1
+
+
 def _epi_compare(w, steps, s, tol_rel=1e-11, prec="fp64", eps=1e-150, check_every=True):
     G, D, Q = pair(w)
     from paper_2101_05617_amd import dfrsw
