@@ -62,6 +62,88 @@ def time_jv(g, q, vs, outs, eps, prec, reps):
     return e0.elapsed_time(e1) / reps
 
 
+CAL_BYTES = 256 * 1024 * 1024
+
+
+def calibration_copy():
+    """A plain device-to-device copy of exactly 256 MiB: the calibration point
+    of the FETCH_SIZE / WRITE_SIZE counters in profiled runs."""
+    import torch
+    a = torch.ones(CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "dfrsw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2101_05617_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_profile(args):
+    """Text summary of rocprofv3 output: per-kernel durations (--kernel-trace
+    --stats) and, from FETCH_SIZE / WRITE_SIZE passes, the HBM bytes per launch
+    of the kernel named by --kernel, scaled by what the same counter reads for
+    the 256 MiB calibration copy."""
+    import csv
+    lines = []
+    rows = list(csv.DictReader(open(os.path.join(args.summarize_profile, "run_kernel_stats.csv"))))
+    lines.append(f"{'kernel':90s} {'calls':>6s} {'avg_us':>9s} {'total_ms':>9s} {'pct':>6s}")
+    for r in rows[:12]:
+        lines.append(f"{r['Name'][:90]:90s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:9.3f} {float(r['Percentage']):6.2f}")
+    sel = [r for r in rows if args.kernel in r["Name"]]
+    if sel:
+        lines.append(f"selected kernel: {sel[0]['Name'][:120]}")
+        lines.append(f"selected_avg_us (all launches, tuning included): {float(sel[0]['AverageNs']) / 1e3:.3f} "
+                     f"over {sel[0]['Calls']} launches")
+        tr = [r for r in csv.DictReader(open(os.path.join(args.summarize_profile, "run_kernel_trace.csv")))
+              if args.kernel in r["Kernel_Name"]]
+        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+        last = tr[-args.last:] if args.last else tr
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in last]
+        lines.append(f"timed_region_avg_us: {sum(d) / len(d):.3f} over the last {len(d)} launches")
+    traffic = {}
+    for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        if not d:
+            continue
+        cc = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        cal = max(float(r["Counter_Value"]) for r in cc
+                  if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"])
+        vals = [float(r["Counter_Value"]) for r in cc if r["Counter_Name"] == counter and args.kernel in r["Kernel_Name"]]
+        factor = (CAL_BYTES / 1024.0) / cal
+        per = sum(vals) / len(vals) * factor * 1024.0
+        traffic[counter] = per
+        lines.append(f"{counter}: the calibration copy counts {cal:.1f} KiB for {CAL_BYTES // 1024} KiB "
+                     f"(factor {factor:.3f}); kernel mean {sum(vals) / len(vals):.1f} KiB over {len(vals)} "
+                     f"dispatches -> {per / 1e6:.3f} MB per launch")
+    if len(traffic) == 2:
+        lines.append(f"traffic_bytes_per_launch: {traffic['FETCH_SIZE'] + traffic['WRITE_SIZE']:.0f} "
+                     f"fetch {traffic['FETCH_SIZE']:.0f} write {traffic['WRITE_SIZE']:.0f} "
+                     f"kernel_source: {kernel_source_digest()}")
+    print("\n".join(lines))
+    return 0
+
+
+def profiled_traffic(name):
+    """HBM bytes per launch recorded in profiles/<name> for the current kernel
+    source, or None (no record, or the kernels changed since)."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            parts = line.split()
+            if parts[-1] == kernel_source_digest():
+                return float(parts[1])
+    return None
+
+
 def cpu_baseline_leg(workload_name):
     """Time the oracle on this host: one steady-state EPI step after the
     start-up steps (untimed, one EPI2 sub-step each)."""
@@ -107,12 +189,7 @@ def jv_only(w, args):
     outs = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
     eps = 1e-20 if args.prec == "fp32_jv" else 1e-150
     t = time_jv(g, q, vs, outs, eps, args.prec, args.jv_reps)
-    # a plain device copy of exactly 256 MiB, the calibration point for the
-    # FETCH_SIZE / WRITE_SIZE counters
-    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
+    calibration_copy()
     bpn = jv_bytes_per_node(args.prec)
     print(json.dumps({"workload": w.name, "prec": args.prec, "nodes": N, "tile": tile, "us": t * 1e3,
                       "GBs": bpn * N / (t * 1e-3) / 1e9, "frac_hbm": bpn * N / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}),
@@ -133,7 +210,17 @@ def main():
     ap.add_argument("--jv-only", action="store_true",
                     help="only time the plain complex-step J*v kernel of --workload (for profiling)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_jv"], help="precision of --jv-only")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print a summary of rocprofv3 output in DIR (kernel trace) and exit")
+    ap.add_argument("--fetch", metavar="DIR", help="with --summarize-profile: a FETCH_SIZE pass")
+    ap.add_argument("--write", metavar="DIR", help="with --summarize-profile: a WRITE_SIZE pass")
+    ap.add_argument("--kernel", default="true, true>", help="with --summarize-profile: kernel name substring")
+    ap.add_argument("--last", type=int, default=0,
+                    help="with --summarize-profile: average over the last N launches (the timed region)")
     args = ap.parse_args()
+
+    if args.summarize_profile:
+        return summarize_profile(args)
 
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)
@@ -249,7 +336,8 @@ def main():
         "roofline": {
             "kernel": "dfr_kernel complex-step J*v with fused Arnoldi epilogue (inside KIOPS)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(f"dfr_kernel_krylov_{w.name}.txt"),
             "bytes_per_node": arnoldi_jv_bytes_per_node(M), "avg_launch_us": avg_jva_ms * 1e3,
             "launches": n_jva,
         },
@@ -265,6 +353,7 @@ def main():
     }
     del st, vs, outs, q, q0
     torch.cuda.synchronize()
+    calibration_copy()
 
     # ---- the ne = 60, p = 6 J*v (the roofline target size), buffers rotated
     if not args.no_c2:
@@ -285,9 +374,12 @@ def main():
         out["jv_ne60_p6"] = {
             "nodes": N2, "tile_fp64": tile2, "tile_fp32": tile2_32,
             "fp64": {"us": t64 * 1e3, "jv_per_s": 1e3 / t64, "GBs": 72 * N2 / (t64 * 1e-3) / 1e9,
-                     "frac_hbm": 72 * N2 / (t64 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "frac_hbm": 72 * N2 / (t64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("dfr_kernel_jv_fp64_c2_ne60_p6_jet.txt")},
             "fp32_jv": {"us": t32 * 1e3, "jv_per_s": 1e3 / t32, "GBs": 60 * N2 / (t32 * 1e-3) / 1e9,
-                        "frac_hbm": 60 * N2 / (t32 * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                        "frac_hbm": 60 * N2 / (t32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": profiled_traffic("dfr_kernel_jv_fp32_c2_ne60_p6_jet.txt"),
+                        "note": "timed per call including the FP32 copy of q (to_f32_kernel)"},
         }
         del v2, o2, q2, g2
 
