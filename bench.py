@@ -144,6 +144,112 @@ def profiled_traffic(name):
     return None
 
 
+def mixed_study(steps):
+    """c2_ne60_p6_jet: the same EPI6 integration with the plain FP64 product and
+    with the complex-FP32 product; steps/s of each (start-up included) and the
+    relative L2 difference in h after `steps` steps."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    w = inputs.WORKLOADS["c2_ne60_p6_jet"]
+    opts = dfrsw.kiops_opts(tol=w.tol, m_max=w.m_max)
+    res, finals = {}, {}
+    for prec, eps in (("fp64", 1e-150), ("fp32_jv", w.eps)):
+        g = dfrsw.Grid(w.ne, w.p, *w.constants())
+        dfrsw.dfr_autotune(g, prec)
+        P, B1, B2 = g.node_frames()
+        Q, _ = inputs.initial_state(w, P, B1, B2)
+        st = dfrsw.epi_create(g, w.order, w.dt_nd, torch.from_numpy(Q).cuda(),
+                              startup_substeps=w.startup_substeps, eps=eps, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nmv = 0
+        t_startup = None
+        for k in range(steps):
+            nmv += dfrsw.epi_step(g, st, opts)["n_matvec"]
+            if k + 1 == w.order - 2:
+                torch.cuda.synchronize()
+                t_startup = time.perf_counter()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        finals[prec] = dfrsw.epi_get_state(st).cpu().numpy()
+        n_after = steps - (w.order - 2)
+        res[prec] = {"steps_per_s": steps / (t1 - t0), "wall_s": t1 - t0, "jv_per_step": nmv / steps,
+                     "epi6_steps_per_s_after_startup": n_after / (t1 - t_startup) if t_startup else None,
+                     "tile": dfrsw.dfr_get_tile(g), "tile_krylov": dfrsw.dfr_get_krylov_tile(g)}
+        log(f"c2 {prec}: {steps} steps in {t1 - t0:.2f}s, {nmv / steps:.0f} J*v/step")
+        del st, g
+        torch.cuda.synchronize()
+    N = w.n_nodes
+    a, b = finals["fp32_jv"], finals["fp64"]
+    err_h = float(np.linalg.norm(a[:N] - b[:N]) / np.linalg.norm(b[:N]))
+    err_all = max(float(np.linalg.norm(a[f * N:(f + 1) * N] - b[f * N:(f + 1) * N]) /
+                        np.linalg.norm(b[f * N:(f + 1) * N])) for f in range(3))
+    return {"workload": f"{w.name}: ne={w.ne}, p={w.p} ({N} nodes), EPI6, dt={w.dt_s:g}s, {steps} steps "
+                        f"({steps * w.dt_s / 86400:g} days), tol {w.tol:g}, m<={w.m_max}",
+            "fp64": res["fp64"], "fp32_jv": res["fp32_jv"],
+            "speedup_mixed_over_fp64": res["fp32_jv"]["steps_per_s"] / res["fp64"]["steps_per_s"],
+            "rel_l2_error_h_mixed_vs_fp64": err_h, "rel_l2_error_max_field": err_all}
+
+
+def ensemble_study(n_members, steps, n_workers):
+    """The ensemble workload: `n_members` members (ne in {8..40}, p in {4,5,6},
+    EPI4, dt 900 s, tol 1e-10, m <= 32).  Plain FP64, members one after
+    another, against the batched form (complex-FP32 products, one stream per
+    member, epi_ensemble_step with n_workers threads).  Both run the EPI2
+    start-up steps untimed, then `steps` timed EPI4 steps; the error is the
+    relative L2 difference in h, all members together and the worst member."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    from paper_2101_05617_amd.ensemble import Ensemble
+    members = inputs.ensemble_members(n_members)
+    w0 = members[0]
+    opts = dfrsw.kiops_opts(tol=w0.tol, m_max=w0.m_max)
+    n_start = w0.order - 2
+    total_nodes = sum(w.n_nodes for w in members)
+    res = {}
+    finals = {}
+    for form in ("fp64_sequential", "fp32_jv_batched"):
+        batched = form.endswith("batched")
+        ens = Ensemble(members, prec="fp32_jv" if batched else "fp64", own_streams=batched)
+        for _ in range(n_start):
+            ens.step(opts, n_workers) if batched else ens.step_sequential(opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nmv = 0
+        for _ in range(steps):
+            st = ens.step(opts, n_workers) if batched else ens.step_sequential(opts)
+            nmv += sum(x["n_matvec"] for x in st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        finals[form] = [ens.state(k) for k in range(len(members))]
+        res[form] = {"member_steps_per_s": n_members * steps / dt, "wall_s": dt,
+                     "jv_per_member_step": nmv / (n_members * steps)}
+        log(f"ensemble {form}: {n_members} x {steps} steps in {dt:.2f}s")
+        ens.close()
+        del ens
+        torch.cuda.synchronize()
+    num = den = 0.0
+    worst = 0.0
+    for w, a, b in zip(members, finals["fp32_jv_batched"], finals["fp64_sequential"]):
+        N = w.n_nodes
+        e2, r2 = float(np.sum((a[:N] - b[:N]) ** 2)), float(np.sum(b[:N] ** 2))
+        num += e2
+        den += r2
+        worst = max(worst, (e2 / r2) ** 0.5)
+    return {"workload": f"{n_members} members, ne in {{8..40}}, p in {{4,5,6}} ({total_nodes} nodes in all), EPI4, "
+                        f"dt 900 s, tol {w0.tol:g}, m<={w0.m_max}; {n_start} start-up steps untimed, {steps} timed",
+            "n_workers": n_workers, "fp64_sequential": res["fp64_sequential"],
+            "fp32_jv_batched": res["fp32_jv_batched"],
+            "speedup_batched_over_fp64": res["fp32_jv_batched"]["member_steps_per_s"] /
+            res["fp64_sequential"]["member_steps_per_s"],
+            "rel_l2_error_h_all_members": (num / den) ** 0.5, "rel_l2_error_h_worst_member": worst,
+            "simulated_days": (n_start + steps) * w0.dt_s / 86400.0}
+
+
 def cpu_baseline_leg(workload_name):
     """Time the oracle on this host: one steady-state EPI step after the
     start-up steps (untimed, one EPI2 sub-step each)."""
@@ -206,6 +312,12 @@ def main():
     ap.add_argument("--jv-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the ne=60, p=6 J*v roofline figures")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the ne=60, p=6 mixed-precision EPI6 day")
+    ap.add_argument("--mixed-steps", type=int, default=72)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member ensemble comparison")
+    ap.add_argument("--ensemble-members", type=int, default=64)
+    ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
+    ap.add_argument("--ensemble-workers", type=int, default=8)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--jv-only", action="store_true",
                     help="only time the plain complex-step J*v kernel of --workload (for profiling)")
@@ -382,6 +494,16 @@ def main():
                         "note": "timed per call including the FP32 copy of q (to_f32_kernel)"},
         }
         del v2, o2, q2, g2
+
+    # ---- mixed precision on the jet workload: complex-FP32 J*v inside the
+    # FP64 Krylov / EPI6 machinery against the plain FP64 path, one simulated day
+    if not args.no_mixed:
+        out["mixed_c2"] = mixed_study(args.mixed_steps)
+
+    # ---- the ensemble workload: batched mixed form against plain FP64 one
+    # member after another
+    if not args.no_ensemble:
+        out["ensemble_c3"] = ensemble_study(args.ensemble_members, args.ensemble_steps, args.ensemble_workers)
 
     # ---- the oracle on this host's cores (bounded sample, one thread)
     if not args.no_cpu_baseline:

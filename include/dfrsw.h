@@ -154,6 +154,20 @@ int epi_get_state(const epi_state *st, double *q);
 int64_t epi_num_steps(const epi_state *st);
 int epi_destroy(epi_state *st);
 
+/* Ensemble: advance n independent integrations (members) by one step each,
+ * concurrently.  n_workers host threads take the members, largest first, and
+ * run epi_step on them (q_out NULL); the members' kernels and read-backs
+ * overlap on the GPU when the members' contexts have streams of their own
+ * (members may share a stream: their work then serialises on it).
+ * ctxs[i], states[i]: member i's context and state (all contexts distinct,
+ * else DFR_E_INVAL).  stats: NULL or n entries, one per
+ * member.  On error the first failure is returned (the message names the
+ * member); members that completed their step stay advanced.  The ensemble
+ * workload of Sec. 5 style runs (many small grids) is bound by launch and
+ * read-back latency per member; this is its batched form. */
+int epi_ensemble_step(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *opts, int n_workers,
+                      kiops_stats *stats);
+
 /* Kernel timing with HIP events, for measurement.  While enabled, every
  * kernel the library launches on the context's stream is bracketed by a pair
  * of events, classified by kind:

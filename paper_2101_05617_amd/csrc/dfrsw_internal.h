@@ -77,6 +77,67 @@ struct ArnoldiArgs {
   double ybot[MAX_P];     // mu y(t) of the start vector (start only)
 };
 
+// One member's part of a batched launch (several grids in one kernel
+// launch).  A member owns the workgroups (or, for the DFR kernel, the
+// logical blocks) [b0, b0 + nblk).
+struct DfrCall {
+  const GridArgs *g;      // device copy of the member's grid arguments
+  const Ops1D *ops;       // device copy of its 1-D operators
+  int TX, TY;             // its tile
+  int b0, ntiles;
+  const void *q;          // state (double, or float in the FP32 form)
+  const double *v;
+  const double *vscale;
+  double eps;
+  double *out;
+  ArnoldiArgs ar;
+};
+struct FirstCall {
+  int b0, nblk;
+  int64_t n3;
+  ArnoldiArgs ar;
+  double *out;
+};
+struct UpdateCall {
+  int b0, nblk;
+  int64_t n3;
+  int j, p;
+  double *w;
+  const double *vj, *vprev, *pin;
+  int np_in;
+  double *pout;
+  struct KDev *kd;
+};
+struct StartCall {
+  int b0, nblk;
+  int64_t n3;
+  const double *x;
+  double *v0, *pout;
+};
+struct CombineCall {
+  int b0, nblk;
+  int64_t n3;
+  const double *V;
+  const struct KDev *kd;
+  double *x;
+};
+struct ExpmCall {        // one workgroup per member
+  struct KDev *kd;
+  double tau;
+  struct KHost *res;
+  int jfin;
+  const double *pin;
+  int np_in;
+  double tol;
+};
+struct AxpbyCall {       // out = a x + b y (y may be NULL); also norms, copies, checks
+  int b0, nblk;
+  int64_t n;
+  double a, b;
+  const double *x, *y;
+  double *out;
+};
+
 // Device-side KIOPS state (one per context).
 struct KDev {
   double H[(MAX_M + 2) * (MAX_M + 2)];     // Hessenberg, row-major, ld = MAX_M + 2
@@ -176,6 +237,9 @@ int latched_error(Ctx &c);
 size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32);
 int dfr_set_lds_limits(Ctx *c, size_t bytes);
 int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi);
+int64_t dfr_num_tiles(const Ctx *c, bool arnoldi);
+int launch_norm2(Ctx *c, int64_t n, const double *x, double *partials, int nblk);
+int launch_sum(Ctx *c, int np, const double *partials, double *out);
 
 }  // namespace dfrsw
 

@@ -155,13 +155,13 @@ __device__ void reduce_fixed2(const double *pin, int np, double *red, double &s0
 // the norm of the vector v_j (start vector, or the vector built by the
 // previous update), sigma_j = 1/||.|| for the stored top block and the
 // normalised bottom block b_j.  Returns false on a happy breakdown.  In
-// workgroup 0 the threads lane < nthr record the values (lane 0 the scalars).
-__device__ bool arnoldi_finish(const ArnoldiArgs &ar, double s, int lane, int nthr, double &sig,
+// the writer workgroup (w0) the threads lane < nthr record the values (lane 0
+// the scalars).
+__device__ bool arnoldi_finish(const ArnoldiArgs &ar, double s, int lane, int nthr, bool w0, double &sig,
                                double bj[MAX_P]) {
   KDev *kd = ar.kd;
   const int j = ar.j, p = ar.p;
   const int ld = MAX_M + 2;
-  const bool w0 = blockIdx.x == 0;
   if (ar.start) {
     double s2 = s;
     for (int k = 0; k < p; ++k) s2 += ar.ybot[k] * ar.ybot[k];
@@ -200,9 +200,9 @@ __device__ bool arnoldi_finish(const ArnoldiArgs &ar, double s, int lane, int nt
 }
 
 // the prologue with its reduction, all threads of the workgroup taking part
-__device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, double &sig, double bj[MAX_P]) {
+__device__ bool arnoldi_prologue(const ArnoldiArgs &ar, double *red, bool w0, double &sig, double bj[MAX_P]) {
   const double s = reduce_fixed(ar.pin, ar.np_in, 1, 0, red);
-  return arnoldi_finish(ar, s, threadIdx.x, blockDim.x, sig, bj);
+  return arnoldi_finish(ar, s, threadIdx.x, blockDim.x, w0, sig, bj);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,12 +315,14 @@ __device__ __forceinline__ T lin(cx<T> z) {
   else return z.r;
 }
 
+// The kernel body: tile `lb` (0 <= lb < 6 (ne/TX)(ne/TY)) of the grid
+// described by g.  Its partial inner products (Krylov form) go to
+// ar.pout[2 lb], ar.pout[2 lb + 1]; tile 0 records the prologue's values.
 template <int NS, typename T, typename TQ, bool CS, bool AR>
-__global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
-                                                               const int TY, const TQ *__restrict__ q,
-                                                               const double *__restrict__ v,
-                                                               const double *__restrict__ vscale, double eps,
-                                                               double *__restrict__ out, const ArnoldiArgs ar) {
+__device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, const int TX, const int TY, const int lb,
+                                         const TQ *__restrict__ q, const double *__restrict__ v,
+                                         const double *__restrict__ vscale, double eps, double *__restrict__ out,
+                                         const ArnoldiArgs &ar) {
   constexpr int NN = NS * NS;
   constexpr int L = CS ? 2 : 1;   // parts kept of a state value
   extern __shared__ double dyn[];
@@ -342,14 +344,6 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   T *TR = reinterpret_cast<T *>(dyn) + lay.trace;
   FaceDesc *FD = reinterpret_cast<FaceDesc *>(reinterpret_cast<T *>(dyn) + lay.faces);
 
-  const int lb = (int)logical_block(6 * ntx * nty);
-  if (lb < 0) {                        // uniform: padding block of the XCD mapping
-    if (AR && tid == 0) {
-      ar.pout[blockIdx.x * 2 + 0] = 0.0;
-      ar.pout[blockIdx.x * 2 + 1] = 0.0;
-    }
-    return;
-  }
   // The direction enters unscaled: J (sigma v) = sigma J v, the scale sigma
   // (vscale, or the Arnoldi sigma_j) multiplies the result.  In Arnoldi mode
   // the loads of the previous kernel's partial sums are issued here and the
@@ -548,7 +542,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     double sg_, bj[MAX_P];
-    const bool ok = arnoldi_finish(ar, x, tid, 64, sg_, bj);
+    const bool ok = arnoldi_finish(ar, x, tid, 64, lb == 0, sg_, bj);
     if (tid == 0) {
       shappy = ok ? 0 : 1;
       ssig = sg_;
@@ -702,27 +696,83 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
   }
   block_sum2(d0, d1, red);
   if (tid == 0) {
-    ar.pout[blockIdx.x * 2 + 0] = d0;
-    ar.pout[blockIdx.x * 2 + 1] = d1;
+    ar.pout[lb * 2 + 0] = d0;
+    ar.pout[lb * 2 + 1] = d1;
   }
+}
+
+// one grid: the logical blocks are its tiles (XCD-aware order), the grid
+// rounded up to whole groups of eight workgroups
+template <int NS, typename T, typename TQ, bool CS, bool AR>
+__global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
+                                                               const int TY, const TQ *__restrict__ q,
+                                                               const double *__restrict__ v,
+                                                               const double *__restrict__ vscale, double eps,
+                                                               double *__restrict__ out, const ArnoldiArgs ar) {
+  const int lb = (int)logical_block(6 * (g.ne / TX) * (g.ne / TY));
+  if (lb < 0) return;   // uniform: padding workgroup of the XCD mapping
+  dfr_body<NS, T, TQ, CS, AR>(g, ops, TX, TY, lb, q, v, vscale, eps, out, ar);
+}
+
+// several grids (ensemble members) in one launch: member m owns the logical
+// blocks [b0, b0 + ntiles)
+template <int NS, typename T, typename TQ, bool CS, bool AR>
+__global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCall *__restrict__ calls, int ncalls,
+                                                                     int nlogical) {
+  __shared__ int s_m;
+  const int lbg = (int)logical_block(nlogical);
+  if (lbg < 0) return;   // uniform
+  for (int t = threadIdx.x; t < ncalls; t += blockDim.x) {
+    const int b0 = calls[t].b0;
+    if (lbg >= b0 && lbg < b0 + calls[t].ntiles) s_m = t;
+  }
+  __syncthreads();
+  const DfrCall &c = calls[s_m];
+  dfr_body<NS, T, TQ, CS, AR>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q), c.v,
+                              c.vscale, c.eps, c.out, c.ar);
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels of the Krylov iteration.  Each is a body run by workgroup
+// `blk` of `nblk` (grid-stride over its vector), with two entry points: one
+// vector (blk = blockIdx.x), or a batch of members' vectors in one launch
+// (member m owns the workgroups [b0, b0 + nblk); find_call locates it).
+
+template <typename C>
+__device__ __forceinline__ int find_call(const C *__restrict__ calls, int ncalls) {
+  __shared__ int s_m;
+  const int b = blockIdx.x;
+  for (int t = threadIdx.x; t < ncalls; t += blockDim.x) {
+    const int b0 = calls[t].b0;
+    if (b >= b0 && b < b0 + calls[t].nblk) s_m = t;
+  }
+  __syncthreads();
+  return s_m;
 }
 
 // first Arnoldi step of a sub-step whose top block is identically zero:
 // w = W b_0 (no J v); both partial inner products vanish
-__global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, double *out) {
+__device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3, const ArnoldiArgs &ar, double *out) {
   __shared__ double red[256];
   if (ar.kd->happy) return;
   double sig, bj[MAX_P];
-  if (!arnoldi_prologue(ar, red, sig, bj)) return;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
+  if (!arnoldi_prologue(ar, red, blk == 0, sig, bj)) return;
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     double acc = 0.0;
     for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * bj[k];
     out[i] = acc;
   }
   if (threadIdx.x == 0) {
-    ar.pout[blockIdx.x * 2 + 0] = 0.0;
-    ar.pout[blockIdx.x * 2 + 1] = 0.0;
+    ar.pout[blk * 2 + 0] = 0.0;
+    ar.pout[blk * 2 + 1] = 0.0;
   }
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, double *out) {
+  arnoldi_first_body(blockIdx.x, gridDim.x, n3, ar, out);
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__restrict__ calls, int ncalls) {
+  const FirstCall &c = calls[find_call(calls, ncalls)];
+  arnoldi_first_body(blockIdx.x - c.b0, c.nblk, c.n3, c.ar, c.out);
 }
 
 // Gram-Schmidt step.  Prologue: the inner products h_{j,j}, h_{j-1,j} (top
@@ -732,14 +782,14 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const 
 // partial ||w||^2 per workgroup.  Basis vectors stay as built (v~_k), their
 // scales sigma_k kept in KDev.  The first UNROLL elements of each thread are
 // read before the prologue, in flight during its reductions.
-__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, double *w, const double *vj,
-                                                               const double *vprev, const double *pin, int np_in,
-                                                               double *pout, KDev *kd) {
+__device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n3, int j, int p, double *w,
+                                                    const double *vj, const double *vprev, const double *pin,
+                                                    int np_in, double *pout, KDev *kd) {
   constexpr int UNROLL = 4;
   __shared__ double red[512];
   const bool two = (j >= 1) && (vprev != nullptr);
-  const int64_t gs = (int64_t)gridDim.x * BLOCK;
-  const int64_t i0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t gs = (int64_t)nblk * BLOCK;
+  const int64_t i0 = (int64_t)blk * BLOCK + threadIdx.x;
   double xw[UNROLL], xv[UNROLL], xp[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
@@ -766,7 +816,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j
   } else {
     hpj = 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk == 0 && threadIdx.x == 0) {
     kd->H[j * ld + j] = hjj;
     if (two) kd->H[(j - 1) * ld + j] = hpj;
     double nb2 = 0.0;
@@ -797,39 +847,63 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j
     acc += x * x;
   }
   const double b = block_sum(acc, red);
-  if (threadIdx.x == 0) pout[blockIdx.x] = b;
+  if (threadIdx.x == 0) pout[blk] = b;
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, double *w, const double *vj,
+                                                               const double *vprev, const double *pin, int np_in,
+                                                               double *pout, KDev *kd) {
+  arnoldi_update_body(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls) {
+  const UpdateCall &c = calls[find_call(calls, ncalls)];
+  arnoldi_update_body(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, c.w, c.vj, c.vprev, c.pin, c.np_in, c.pout, c.kd);
 }
 
 // start of a sub-step: v~_0 = x (copied), partial ||x||^2 per workgroup
-__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, double *v0, double *pout) {
+__device__ __forceinline__ void arnoldi_start_body(int blk, int nblk, int64_t n3, const double *x, double *v0,
+                                                   double *pout) {
   __shared__ double red[BLOCK / 64];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     const double xv = x[i];
     v0[i] = xv;
     acc += xv * xv;
   }
   const double b = block_sum(acc, red);
-  if (threadIdx.x == 0) pout[blockIdx.x] = b;
+  if (threadIdx.x == 0) pout[blk] = b;
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, double *v0, double *pout) {
+  arnoldi_start_body(blockIdx.x, gridDim.x, n3, x, v0, pout);
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_start_batch(const StartCall *__restrict__ calls, int ncalls) {
+  const StartCall &c = calls[find_call(calls, ncalls)];
+  arnoldi_start_body(blockIdx.x - c.b0, c.nblk, c.n3, c.x, c.v0, c.pout);
 }
 
-// accepted sub-step: x = beta * sum_{k<J} sigma_k v~_k E[k][0]
-__global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, const double *V, int64_t ldv, const KDev *kd,
-                                                                double *x) {
+// accepted sub-step: x = beta * sum_{k<J} sigma_k v~_k E[k][0]; the
+// coefficients are staged in LDS
+__device__ __forceinline__ void arnoldi_combine_body(int blk, int nblk, int64_t n3, const double *V, int64_t ldv,
+                                                     const KDev *kd, double *x) {
+  __shared__ double cf[MAX_M + 1];
   const int J = kd->J;
   const double beta = kd->beta;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n3; i += (int64_t)gridDim.x * BLOCK) {
+  for (int k = threadIdx.x; k < J; k += blockDim.x) cf[k] = kd->sigma[k] * kd->E0[k];
+  __syncthreads();
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     double acc = 0.0;
-    for (int k = 0; k < J; ++k) acc += V[k * ldv + i] * (kd->sigma[k] * kd->E0[k]);
+    for (int k = 0; k < J; ++k) acc += V[k * ldv + i] * cf[k];
     x[i] = beta * acc;
   }
 }
+__global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, const double *V, int64_t ldv, const KDev *kd,
+                                                                double *x) {
+  arnoldi_combine_body(blockIdx.x, gridDim.x, n3, V, ldv, kd, x);
+}
+__global__ __launch_bounds__(BLOCK) void arnoldi_combine_batch(const CombineCall *__restrict__ calls, int ncalls) {
+  const CombineCall &c = calls[find_call(calls, ncalls)];
+  arnoldi_combine_body(blockIdx.x - c.b0, c.nblk, c.n3, c.V, c.n3, c.kd, c.x);
+}
 
-// ---------------------------------------------------------------------------
-// exp(tau H_aug), H_aug = [[H_J, e_1], [0, 0]] ((J+1) x (J+1)), in one
-// workgroup: scaling to ||.||_1 <= 1, Taylor polynomial of degree 18 in
-// Paterson-Stockmeyer form (blocks of A^2), then repeated squaring.  The
-// truncation error for ||A||_1 <= 1 is below sum_{k>=19} 1/k! < 1e-17.
 // ---------------------------------------------------------------------------
 // The small exponential of the Krylov step: E = exp(tau H_aug) with
 // H_aug = [[H_J, e_1], [0, 0]] ((J+1) x (J+1)); only E[:J, 0] (the sub-step
@@ -896,8 +970,8 @@ size_t expm_lds_bytes(int m) {
   return (size_t)4 * P * (P + 1) * sizeof(double);
 }
 
-__global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
-                                                          int np_in, double tol) {
+__device__ __forceinline__ void expm_body(KDev *kd, double tau, KHost *res, int jfin, const double *pin, int np_in,
+                                          double tol) {
   extern __shared__ double lds[];
   __shared__ double red[256];
   __shared__ double cnorm;
@@ -1019,20 +1093,75 @@ __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, 
     res->happy = kd->happy;
   }
 }
+__global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
+                                                          int np_in, double tol) {
+  expm_body(kd, tau, res, jfin, pin, np_in, tol);
+}
+// one workgroup per member
+__global__ __launch_bounds__(EXPM_BLOCK) void expm_batch(const ExpmCall *__restrict__ calls) {
+  const ExpmCall &c = calls[blockIdx.x];
+  expm_body(c.kd, c.tau, c.res, c.jfin, c.pin, c.np_in, c.tol);
+}
 
 // ---------------------------------------------------------------------------
 // vector helpers
-__global__ __launch_bounds__(BLOCK) void axpby_kernel(int64_t n, double a, const double *x, double b, const double *y,
-                                                      double *out) {
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+__device__ __forceinline__ void axpby_body(int blk, int nblk, int64_t n, double a, const double *x, double b,
+                                           const double *y, double *out) {
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n; i += (int64_t)nblk * BLOCK) {
     double r = a * x[i];
     if (y) r += b * y[i];
     out[i] = r;
   }
 }
+__global__ __launch_bounds__(BLOCK) void axpby_kernel(int64_t n, double a, const double *x, double b, const double *y,
+                                                      double *out) {
+  axpby_body(blockIdx.x, gridDim.x, n, a, x, b, y, out);
+}
+__global__ __launch_bounds__(BLOCK) void axpby_batch(const AxpbyCall *__restrict__ calls, int ncalls) {
+  const AxpbyCall &c = calls[find_call(calls, ncalls)];
+  axpby_body(blockIdx.x - c.b0, c.nblk, c.n, c.a, c.x, c.b, c.y, c.out);
+}
 
 __global__ __launch_bounds__(BLOCK) void to_f32_kernel(int64_t n, const double *x, float *y) {
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) y[i] = (float)x[i];
+}
+__global__ __launch_bounds__(BLOCK) void to_f32_batch(const AxpbyCall *__restrict__ calls, int ncalls) {
+  const AxpbyCall &c = calls[find_call(calls, ncalls)];
+  float *y = reinterpret_cast<float *>(c.out);
+  for (int64_t i = (int64_t)(blockIdx.x - c.b0) * BLOCK + threadIdx.x; i < c.n; i += (int64_t)c.nblk * BLOCK)
+    y[i] = (float)c.x[i];
+}
+
+// ||x||_2^2: per-workgroup partial sums, then one workgroup sums them in a
+// fixed order
+__device__ __forceinline__ void norm2_body(int blk, int nblk, int64_t n, const double *x, double *partials) {
+  __shared__ double red[BLOCK / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n; i += (int64_t)nblk * BLOCK) acc += x[i] * x[i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blk] = s;
+}
+__global__ __launch_bounds__(BLOCK) void norm2_kernel(int64_t n, const double *x, double *partials) {
+  norm2_body(blockIdx.x, gridDim.x, n, x, partials);
+}
+__global__ __launch_bounds__(BLOCK) void norm2_batch(const AxpbyCall *__restrict__ calls, int ncalls) {
+  const AxpbyCall &c = calls[find_call(calls, ncalls)];
+  norm2_body(blockIdx.x - c.b0, c.nblk, c.n, c.x, c.out);
+}
+__device__ __forceinline__ void sum_body(int np, const double *partials, double *out) {
+  __shared__ double red[BLOCK / 64];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < np; k += BLOCK) acc += partials[k];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) *out = s;
+}
+__global__ __launch_bounds__(BLOCK) void sum_kernel(int np, const double *partials, double *out) {
+  sum_body(np, partials, out);
+}
+// one workgroup per call: out = sum of the call's nblk partials in x
+__global__ __launch_bounds__(BLOCK) void sum_batch(const AxpbyCall *__restrict__ calls) {
+  const AxpbyCall &c = calls[blockIdx.x];
+  sum_body(c.nblk, c.x, c.out);
 }
 
 // a positive smooth state (H = 1 + 0.1 sin, small momenta) and a direction,
@@ -1045,14 +1174,22 @@ __global__ __launch_bounds__(BLOCK) void fill_kernel(int64_t n, double *q, doubl
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void check_state_kernel(int64_t n, const double *q, int *err) {
+__device__ __forceinline__ void check_state_body(int blk, int nblk, int64_t n, const double *q, int *err) {
   int bad = 0;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < 3 * n; i += (int64_t)nblk * BLOCK) {
     const double x = q[i];
     if (!isfinite(x)) bad |= 1;
     if (i < n && !(x > 0.0)) bad |= 2;
   }
   if (bad) atomicOr(err, bad);
+}
+__global__ __launch_bounds__(BLOCK) void check_state_kernel(int64_t n, const double *q, int *err) {
+  check_state_body(blockIdx.x, gridDim.x, n, q, err);
+}
+// n = nodes (the vector holds 3n values); out = the member's error flag
+__global__ __launch_bounds__(BLOCK) void check_state_batch(const AxpbyCall *__restrict__ calls, int ncalls) {
+  const AxpbyCall &c = calls[find_call(calls, ncalls)];
+  check_state_body(blockIdx.x - c.b0, c.nblk, c.n, c.x, reinterpret_cast<int *>(c.out));
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,6 +1205,23 @@ static inline int grid_for(int64_t n) {
 size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32) {
   const int ts = fp32 ? (int)sizeof(float) : (int)sizeof(double);
   return (size_t)dfr_lds_layout(ns, tx, ty, 2, ts).total * ts;
+}
+
+int64_t dfr_num_tiles(const Ctx *c, bool arnoldi) {
+  const int tx = arnoldi ? c->ar_tx : c->tile_tx, ty = arnoldi ? c->ar_ty : c->tile_ty;
+  return 6LL * (c->ne / tx) * (c->ne / ty);
+}
+
+int launch_norm2(Ctx *c, int64_t n, const double *x, double *partials, int nblk) {
+  dfr_launch(c, DFR_K_OTHER, norm2_kernel, dim3((unsigned)nblk), dim3(BLOCK), 0, n, x, partials);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_sum(Ctx *c, int np, const double *partials, double *out) {
+  dfr_launch(c, DFR_K_FINALIZE, sum_kernel, dim3(1), dim3(BLOCK), 0, np, partials, out);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
 }
 
 int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi) {

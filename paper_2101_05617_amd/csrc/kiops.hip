@@ -28,44 +28,16 @@
 #include "dfrsw_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
 
 namespace dfrsw {
 
 int latched_error(Ctx &c);
-
-// ||x||_2^2: per-block partial sums, then one block sums them in a fixed order
-__global__ __launch_bounds__(BLOCK) void norm2_kernel(int64_t n, const double *x, double *partials) {
-  __shared__ double red[BLOCK / 64];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) acc += x[i] * x[i];
-  double v = acc;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
-    partials[blockIdx.x] = s;
-  }
-}
-
-__global__ __launch_bounds__(BLOCK) void sum_kernel(int np, const double *partials, double *out) {
-  __shared__ double red[BLOCK / 64];
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < np; k += BLOCK) acc += partials[k];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < BLOCK / 64; ++k) s += red[k];
-    *out = s;
-  }
-}
 
 static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
   const int64_t n3 = 3 * c.n;
@@ -78,10 +50,9 @@ static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
       got[i] = 0.0;
       continue;
     }
-    dfr_launch(&c, DFR_K_OTHER, norm2_kernel, dim3((unsigned)b), dim3(BLOCK), 0, n3, x[i], c.d_partials);
-    DFR_HIP(hipGetLastError());
-    dfr_launch(&c, DFR_K_FINALIZE, sum_kernel, dim3(1), dim3(BLOCK), 0, (int)b, c.d_partials, d_out);
-    DFR_HIP(hipGetLastError());
+    int rc = launch_norm2(&c, n3, x[i], c.d_partials, (int)b);
+    if (!rc) rc = launch_sum(&c, (int)b, c.d_partials, d_out);
+    if (rc) return rc;
     DFR_HIP(hipMemcpyAsync(&got[i], d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
     DFR_HIP(hipStreamSynchronize(c.stream));
   }
@@ -202,7 +173,7 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
         skipped = true;
       } else {
         rc = launch_dfr(&c, q, q32, V + (int64_t)j * n3, nullptr, eps, true, fp32, out, &ar);
-        npA = (int)dfr_grid_blocks(&c, true);
+        npA = (int)dfr_num_tiles(&c, true);
       }
       if (rc) return rc;
       rc = launch_update(&c, j, out, V + (int64_t)j * n3, ar.vprev, pA, npA, pB, &npB);
@@ -545,6 +516,65 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
   if (q_out) DFR_HIP(hipMemcpyAsync(q_out, st->q, sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
   DFR_HIP(hipStreamSynchronize(c.stream));
   return latched_error(c);
+}
+
+int epi_ensemble_step(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *o, int n_workers,
+                      kiops_stats *stats) {
+  if (n < 1 || !ctxs || !states || !o) {
+    set_error("epi_ensemble_step: invalid argument");
+    return DFR_E_INVAL;
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !states[i] || states[i]->c != &ctxs[i]->c) {
+      set_error("epi_ensemble_step: member " + std::to_string(i) + " has no matching context and state");
+      return DFR_E_INVAL;
+    }
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) {
+        set_error("epi_ensemble_step: members " + std::to_string(k) + " and " + std::to_string(i) +
+                  " share a context");
+        return DFR_E_INVAL;
+      }
+    order[i] = i;
+  }
+  // largest members first, taken from a shared counter by the workers
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ctxs[a]->c.n > ctxs[b]->c.n; });
+  const int nw = std::max(1, std::min(n_workers, n));
+  std::atomic<int> next{0};
+  std::atomic<int> first_rc{0};
+  std::string first_msg;
+  std::atomic<bool> msg_taken{false};
+  auto work = [&]() {
+    int dev = ctxs[order[0]]->c.device;
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n || first_rc.load() != 0) break;
+      const int i = order[k];
+      if (ctxs[i]->c.device != dev) dev = ctxs[i]->c.device;
+      int rc = hipSetDevice(dev) == hipSuccess ? DFR_OK : DFR_E_HIP;
+      if (!rc) rc = epi_step(ctxs[i], states[i], o, nullptr, stats ? &stats[i] : nullptr);
+      if (rc) {
+        int zero = 0;
+        if (first_rc.compare_exchange_strong(zero, rc) && !msg_taken.exchange(true))
+          first_msg = "member " + std::to_string(i) + ": " + dfr_last_error();
+        break;
+      }
+    }
+  };
+  if (nw == 1) {
+    work();
+  } else {
+    std::vector<std::thread> pool;
+    pool.reserve(nw);
+    for (int w = 0; w < nw; ++w) pool.emplace_back(work);
+    for (auto &t : pool) t.join();
+  }
+  if (first_rc.load() != 0) {
+    set_error("epi_ensemble_step: " + first_msg);
+    return first_rc.load();
+  }
+  return DFR_OK;
 }
 
 }  // extern "C"

@@ -80,6 +80,8 @@ def lib():
             "epi_get_state": (i, [vp, vp]),
             "epi_num_steps": (i64, [vp]),
             "epi_destroy": (i, [vp]),
+            "epi_ensemble_step": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(KiopsOpts), i,
+                                      ctypes.POINTER(KiopsStats)]),
             "dfr_set_tile": (i, [vp, i, i]),
             "dfr_get_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_get_krylov_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
@@ -99,7 +101,7 @@ def lib():
 def exported_symbols():
     return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
-            "epi_num_steps", "epi_destroy", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
+            "epi_num_steps", "epi_destroy", "epi_ensemble_step", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_last_error"]
 
 
@@ -258,6 +260,19 @@ def epi_step(g: Grid, st: EpiState, opts=None, q_out=None):
     _check(lib().epi_step(g.handle, st.handle, ctypes.byref(opts), None if q_out is None else _dev(q_out),
                           ctypes.byref(s)))
     return s.as_dict()
+
+
+def epi_ensemble_step(grids, states, opts=None, n_workers=8):
+    """One step of every member (grids[i], states[i]); returns per-member stats."""
+    opts = opts or kiops_opts()
+    n = len(grids)
+    if n != len(states) or n == 0:
+        raise ValueError("need one state per grid")
+    ca = (ctypes.c_void_p * n)(*[g.handle for g in grids])
+    sa = (ctypes.c_void_p * n)(*[s.handle for s in states])
+    st = (KiopsStats * n)()
+    _check(lib().epi_ensemble_step(n, ca, sa, ctypes.byref(opts), int(n_workers), st))
+    return [x.as_dict() for x in st]
 
 
 def epi_get_state(st: EpiState, q=None):
