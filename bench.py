@@ -195,11 +195,12 @@ def mixed_study(steps):
 
 def ensemble_study(n_members, steps, n_workers):
     """The ensemble workload: `n_members` members (ne in {8..40}, p in {4,5,6},
-    EPI4, dt 900 s, tol 1e-10, m <= 32).  Plain FP64, members one after
-    another, against the batched form (complex-FP32 products, one stream per
-    member, epi_ensemble_step with n_workers threads).  Both run the EPI2
+    EPI4, dt 900 s, tol 1e-10, m <= 32).  Plain FP64 with the members one
+    after another, against the batched form (one launch per operation for all
+    members) in FP64 and with complex-FP32 products.  Every form runs the EPI2
     start-up steps untimed, then `steps` timed EPI4 steps; the error is the
-    relative L2 difference in h, all members together and the worst member."""
+    relative L2 difference in h from the plain FP64 run, all members together
+    and the worst member."""
     import numpy as np
     import torch
 
@@ -212,41 +213,46 @@ def ensemble_study(n_members, steps, n_workers):
     total_nodes = sum(w.n_nodes for w in members)
     res = {}
     finals = {}
-    for form in ("fp64_sequential", "fp32_jv_batched"):
-        batched = form.endswith("batched")
-        ens = Ensemble(members, prec="fp32_jv" if batched else "fp64", own_streams=batched)
+    for name, prec, form in (("fp64_sequential", "fp64", "sequential"), ("fp64_batched", "fp64", "batched"),
+                             ("fp32_jv_batched", "fp32_jv", "batched")):
+        ens = Ensemble(members, prec=prec, form=form)
         for _ in range(n_start):
-            ens.step(opts, n_workers) if batched else ens.step_sequential(opts)
+            ens.step(opts, n_workers)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nmv = 0
         for _ in range(steps):
-            st = ens.step(opts, n_workers) if batched else ens.step_sequential(opts)
+            st = ens.step(opts, n_workers)
             nmv += sum(x["n_matvec"] for x in st)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        finals[form] = [ens.state(k) for k in range(len(members))]
-        res[form] = {"member_steps_per_s": n_members * steps / dt, "wall_s": dt,
+        finals[name] = [ens.state(k) for k in range(len(members))]
+        res[name] = {"member_steps_per_s": n_members * steps / dt, "wall_s": dt,
                      "jv_per_member_step": nmv / (n_members * steps)}
-        log(f"ensemble {form}: {n_members} x {steps} steps in {dt:.2f}s")
+        log(f"ensemble {name}: {n_members} x {steps} steps in {dt:.2f}s")
         ens.close()
         del ens
         torch.cuda.synchronize()
-    num = den = 0.0
-    worst = 0.0
-    for w, a, b in zip(members, finals["fp32_jv_batched"], finals["fp64_sequential"]):
-        N = w.n_nodes
-        e2, r2 = float(np.sum((a[:N] - b[:N]) ** 2)), float(np.sum(b[:N] ** 2))
-        num += e2
-        den += r2
-        worst = max(worst, (e2 / r2) ** 0.5)
+
+    def err(name):
+        num = den = worst = 0.0
+        for w, a, b in zip(members, finals[name], finals["fp64_sequential"]):
+            N = w.n_nodes
+            e2, r2 = float(np.sum((a[:N] - b[:N]) ** 2)), float(np.sum(b[:N] ** 2))
+            num += e2
+            den += r2
+            worst = max(worst, (e2 / r2) ** 0.5)
+        return (num / den) ** 0.5, worst
+    e32, w32 = err("fp32_jv_batched")
+    e64, w64 = err("fp64_batched")
+    base = res["fp64_sequential"]["member_steps_per_s"]
     return {"workload": f"{n_members} members, ne in {{8..40}}, p in {{4,5,6}} ({total_nodes} nodes in all), EPI4, "
                         f"dt 900 s, tol {w0.tol:g}, m<={w0.m_max}; {n_start} start-up steps untimed, {steps} timed",
-            "n_workers": n_workers, "fp64_sequential": res["fp64_sequential"],
-            "fp32_jv_batched": res["fp32_jv_batched"],
-            "speedup_batched_over_fp64": res["fp32_jv_batched"]["member_steps_per_s"] /
-            res["fp64_sequential"]["member_steps_per_s"],
-            "rel_l2_error_h_all_members": (num / den) ** 0.5, "rel_l2_error_h_worst_member": worst,
+            **res,
+            "speedup_fp32_batched_over_fp64_sequential": res["fp32_jv_batched"]["member_steps_per_s"] / base,
+            "speedup_fp64_batched_over_fp64_sequential": res["fp64_batched"]["member_steps_per_s"] / base,
+            "rel_l2_error_h_fp32_batched": {"all_members": e32, "worst_member": w32},
+            "rel_l2_error_h_fp64_batched": {"all_members": e64, "worst_member": w64},
             "simulated_days": (n_start + steps) * w0.dt_s / 86400.0}
 
 

@@ -154,19 +154,49 @@ int epi_get_state(const epi_state *st, double *q);
 int64_t epi_num_steps(const epi_state *st);
 int epi_destroy(epi_state *st);
 
-/* Ensemble: advance n independent integrations (members) by one step each,
- * concurrently.  n_workers host threads take the members, largest first, and
- * run epi_step on them (q_out NULL); the members' kernels and read-backs
- * overlap on the GPU when the members' contexts have streams of their own
- * (members may share a stream: their work then serialises on it).
- * ctxs[i], states[i]: member i's context and state (all contexts distinct,
- * else DFR_E_INVAL).  stats: NULL or n entries, one per
- * member.  On error the first failure is returned (the message names the
- * member); members that completed their step stay advanced.  The ensemble
- * workload of Sec. 5 style runs (many small grids) is bound by launch and
- * read-back latency per member; this is its batched form. */
-int epi_ensemble_step(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *opts, int n_workers,
-                      kiops_stats *stats);
+/* Ensembles (many independent grids, e.g. an ensemble of small forecasts).
+ *
+ * Batched form.  dfr_ensemble_create makes one context per member (member i
+ * from members[i]; up to 256 members; all on hip_stream) plus device tables
+ * that let one kernel launch serve every member.  epi_ensemble_step advances
+ * every member by one EPI step: each operation of the step and of the Krylov
+ * iteration (Sec. 4, Eq. 29) is one launch for all members; every member
+ * keeps its own KIOPS controller, and members take Arnoldi steps in lockstep
+ * rounds with one read-back per round in which some member's sweep reaches
+ * its exponential.  Member results equal those of epi_step on the member
+ * alone up to rounding (same kernels and reduction orders).  All members of
+ * an epi_ensemble must share order, dt, start-up sub-steps and precision
+ * (DFR_E_INVAL otherwise).  q0: host array of n device pointers (3 N_i
+ * doubles each, copied).  stats: NULL or n entries.  dfr_ensemble_member
+ * returns member i's context (owned by the ensemble; usable with every
+ * single-grid entry point, e.g. dfr_node_frames, dfr_autotune, whose tiles the
+ * batched launches then use).  Errors name the member. */
+typedef struct dfr_ensemble dfr_ensemble;
+typedef struct epi_ensemble epi_ensemble;
+int dfr_ensemble_create(int n_members, const dfr_grid_desc *members, void *hip_stream, dfr_ensemble **out);
+int dfr_ensemble_destroy(dfr_ensemble *e);
+int dfr_ensemble_size(const dfr_ensemble *e);
+dfr_ctx *dfr_ensemble_member(dfr_ensemble *e, int i);
+/* Give all members with the same p one common tile (both forms), the fastest
+ * of the tiles admissible for every one of them, timed on batched launches of
+ * the Krylov-form product of the given precision (synchronises; uses the
+ * members' Krylov workspaces as scratch). */
+int dfr_ensemble_autotune(dfr_ensemble *e, dfr_precision prec);
+int epi_ensemble_create(dfr_ensemble *e, int order, double dt, int startup_substeps, const double *const *q0,
+                        double eps, dfr_precision prec, epi_ensemble **out);
+int epi_ensemble_step(dfr_ensemble *e, epi_ensemble *x, const kiops_opts *opts, kiops_stats *stats);
+int epi_ensemble_get_state(const epi_ensemble *x, int i, double *q);
+int epi_ensemble_destroy(epi_ensemble *x);
+
+/* Concurrent form, for members that need not share order, dt or precision:
+ * n_workers host threads take the members (contexts from dfr_create, each
+ * ideally on its own stream), largest first, and run epi_step on them.
+ * ctxs[i], states[i]: member i's context and state (contexts distinct, else
+ * DFR_E_INVAL; members sharing a stream serialise on it).  stats: NULL or n
+ * entries.  The first failure is returned (the message names the member);
+ * members that completed their step stay advanced. */
+int epi_step_concurrent(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *opts, int n_workers,
+                        kiops_stats *stats);
 
 /* Kernel timing with HIP events, for measurement.  While enabled, every
  * kernel the library launches on the context's stream is bracketed by a pair

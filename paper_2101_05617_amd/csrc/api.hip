@@ -350,7 +350,7 @@ static int setup_geometry(Ctx &c, const double *hB) {
 
 // admissible element tiles: TX, TY divide ne, one thread per node (<= 1024),
 // dynamic LDS within the device limit
-static std::vector<std::pair<int, int>> tile_candidates(const Ctx &c) {
+std::vector<std::pair<int, int>> tile_candidates(const Ctx &c) {
   std::vector<std::pair<int, int>> out;
   const int nn = c.ns * c.ns;
   for (int tx = 1; tx <= c.ne; ++tx) {

@@ -1,0 +1,744 @@
+// Ensembles: several independent grids ("members", each with its own ne, p,
+// tiles and state) advanced together.  Every operation of the EPI step and
+// of the Krylov iteration is one kernel launch for all members: the batched
+// kernels take a table of per-member calls (kernels.hip), so small members do
+// not each pay launch and read-back latency.  Each member runs its own KIOPS
+// controller (the state machine of kiops.hip); members take Arnoldi steps in
+// lockstep rounds, and a round ends with one read-back for all members whose
+// sweep reached its exponential.  Results are those of the single-grid path
+// member by member (same kernels, same reduction orders).
+#include "dfrsw_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+using namespace dfrsw;
+
+struct dfr_ensemble {
+  int n = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<dfr_ctx *> mem;
+  GridArgs *d_ga = nullptr;          // device copies of the members' grid arguments
+  Ops1D *d_ops = nullptr;            // and 1-D operators
+  Stage stage;                       // call tables
+  double *d_res = nullptr, *h_res = nullptr;   // per-call scalar results (norms)
+  KHost *d_kh = nullptr, *h_kh = nullptr;       // per-member exponential results
+  int **d_errp = nullptr;            // the members' error flags
+  int *d_errv = nullptr, *h_errv = nullptr;
+  std::vector<hipEvent_t> evfree;    // events for read-backs in flight
+};
+
+struct epi_ensemble {
+  dfr_ensemble *e = nullptr;
+  std::vector<epi_state *> st;
+};
+
+namespace dfrsw {
+
+int kiops_validate(const Ctx &c, const kiops_opts &o, int n_phi, double tau_out);
+size_t expm_lds_bytes(int m);
+
+// read and clear the members' latched error flags
+__global__ void gather_err_kernel(int *const *ptrs, int n, int *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    out[i] = *ptrs[i];
+    *ptrs[i] = 0;
+  }
+}
+
+static constexpr size_t STAGE_BYTES = 64u << 20;
+
+static DfrCall make_call(dfr_ensemble &E, int i, bool arnoldi, const void *q, const double *v, double eps,
+                         double *out, const ArnoldiArgs *ar) {
+  Ctx &c = E.mem[i]->c;
+  DfrCall d{};
+  d.g = E.d_ga + i;
+  d.ops = E.d_ops + i;
+  d.g_ne = c.ne;
+  d.TX = arnoldi ? c.ar_tx : c.tile_tx;
+  d.TY = arnoldi ? c.ar_ty : c.tile_ty;
+  d.q = q;
+  d.v = v;
+  d.vscale = nullptr;
+  d.eps = eps;
+  d.out = out;
+  if (ar) d.ar = *ar;
+  return d;
+}
+
+// one launch per (number of GL points) group of the calls
+static int launch_dfr_groups(dfr_ensemble &E, const std::vector<int> &member, std::vector<DfrCall> &calls, bool cs,
+                             bool fp32, bool arnoldi) {
+  for (int ns = 2; ns <= MAX_NS; ++ns) {
+    std::vector<DfrCall> grp;
+    for (size_t k = 0; k < calls.size(); ++k)
+      if (E.mem[member[k]]->c.ns == ns) grp.push_back(calls[k]);
+    if (grp.empty()) continue;
+    const int rc = launch_dfr_batch(E.stream, E.stage, ns, cs, fp32, arnoldi, grp);
+    if (rc) return rc;
+  }
+  return DFR_OK;
+}
+
+static AxpbyCall vcall(int64_t n, double a, const double *x, double b, const double *y, double *out) {
+  AxpbyCall c{};
+  c.nblk = vec_blocks(n);
+  c.n = n;
+  c.a = a;
+  c.b = b;
+  c.x = x;
+  c.y = y;
+  c.out = out;
+  return c;
+}
+
+static int ensemble_errors(dfr_ensemble &E);
+
+static int sync_reset(dfr_ensemble &E) {
+  DFR_HIP(hipStreamSynchronize(E.stream));
+  reset_stage(E.stage);
+  return DFR_OK;
+}
+
+// KIOPS for machines K (K[a] belongs to member mi[a]), all at once
+static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std::vector<int> &mi,
+                       const kiops_opts &o) {
+  const int nk = (int)K.size();
+  int rc = DFR_OK;
+  // norms of every b_k: one launch of partial sums, one of finishing sums
+  std::vector<AxpbyCall> nc, sc;
+  std::vector<int> slot((size_t)nk * (MAX_P + 1), -1);
+  int nres = 0;
+  for (int a = 0; a < nk; ++a) {
+    Ctx &c = *K[a].c;
+    const int64_t n3 = 3 * c.n;
+    for (int k = 0; k <= K[a].n_phi; ++k) {
+      if (!K[a].b[k]) continue;
+      double *part = c.d_partials + (size_t)k * 1024;
+      nc.push_back(vcall(n3, 0.0, K[a].b[k], 0.0, nullptr, part));
+      AxpbyCall s{};
+      s.nblk = vec_blocks(n3);
+      s.x = part;
+      s.out = E.d_res + nres;
+      sc.push_back(s);
+      slot[(size_t)a * (MAX_P + 1) + k] = nres++;
+    }
+  }
+  if ((rc = launch_vec_batch(E.stream, E.stage, VB_NORM2, nc))) return rc;
+  if ((rc = launch_vec_batch(E.stream, E.stage, VB_SUM, sc))) return rc;
+  if (nres) DFR_HIP(hipMemcpyAsync(E.h_res, E.d_res, sizeof(double) * nres, hipMemcpyDeviceToHost, E.stream));
+  if ((rc = sync_reset(E))) return rc;
+  // scaling, W = nu [b_p..b_1], x = b_0
+  std::vector<AxpbyCall> wc;
+  for (int a = 0; a < nk; ++a) {
+    KiopsMachine &k = K[a];
+    Ctx &c = *k.c;
+    const int64_t n3 = 3 * c.n;
+    double nrm2[MAX_P + 1];
+    for (int i = 0; i <= k.n_phi; ++i) {
+      const int sl = slot[(size_t)a * (MAX_P + 1) + i];
+      nrm2[i] = sl >= 0 ? E.h_res[sl] : 0.0;
+    }
+    if (!km_init(k, nrm2, o)) {
+      wc.push_back(vcall(n3, 0.0, nullptr, 0.0, nullptr, k.w));
+      k.phase = KiopsMachine::DONE;
+      continue;
+    }
+    for (int i = 0; i < k.p; ++i)
+      wc.push_back(vcall(n3, k.nu, k.n_phi == 0 ? nullptr : k.b[k.p - i], 0.0, nullptr, c.d_W + i * n3));
+    c.kiops_p = k.p;
+    c.kiops_mmax = k.m_max;
+    wc.push_back(vcall(n3, 1.0, k.b[0], 0.0, nullptr, k.w));
+  }
+  if ((rc = launch_vec_batch(E.stream, E.stage, VB_AXPBY, wc))) return rc;
+  const size_t lds = expm_lds_bytes(o.m_max);
+
+  // Rounds.  Every member that is not waiting for a decision takes one
+  // Arnoldi step (or launches its exponential).  The exponentials' results
+  // come back asynchronously (an event per round); decisions are taken as
+  // their read-backs arrive, so the host keeps queueing work for the other
+  // members and blocks only when no member can proceed.
+  struct Pending {
+    hipEvent_t ev;
+    std::vector<int> a;
+  };
+  std::deque<Pending> pend;
+  std::vector<char> waiting(nk, 0);
+  auto take_event = [&](hipEvent_t *ev) -> int {
+    if (!E.evfree.empty()) {
+      *ev = E.evfree.back();
+      E.evfree.pop_back();
+      return DFR_OK;
+    }
+    DFR_HIP(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    return DFR_OK;
+  };
+  auto harvest = [&](bool block) -> int {
+    std::vector<CombineCall> cc;
+    while (!pend.empty()) {
+      Pending &f = pend.front();
+      if (block) {
+        DFR_HIP(hipEventSynchronize(f.ev));
+        block = false;
+      } else {
+        const hipError_t q = hipEventQuery(f.ev);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          set_error(std::string("HIP error: ") + hipGetErrorString(q));
+          return DFR_E_HIP;
+        }
+      }
+      for (int a : f.a) {
+        KiopsMachine &k = K[a];
+        waiting[a] = 0;
+        bool accept = false;
+        int r = km_decide(k, E.h_kh[mi[a]], o, &accept);
+        if (r == DFR_E_NONFINITE) {
+          // a latched input error explains it (and names the member)
+          const int le = ensemble_errors(E);
+          if (le) return le;
+        }
+        if (r) {
+          set_error("member " + std::to_string(mi[a]) + ": " + dfr_last_error());
+          return r;
+        }
+        if (accept) {
+          CombineCall b{};
+          b.nblk = vec_blocks(3 * k.c->n);
+          b.n3 = 3 * k.c->n;
+          b.V = k.c->d_V;
+          b.kd = k.c->d_kd;
+          b.x = k.w;
+          cc.push_back(b);
+        }
+      }
+      E.evfree.push_back(f.ev);
+      pend.pop_front();
+    }
+    return launch_combine_batch(E.stream, E.stage, cc);
+  };
+  auto drain = [&]() {
+    for (auto &f : pend) {
+      (void)hipEventSynchronize(f.ev);
+      E.evfree.push_back(f.ev);
+    }
+    pend.clear();
+  };
+
+  for (;;) {
+    if ((rc = harvest(false))) {
+      drain();
+      return rc;
+    }
+    int active = 0, runnable = 0;
+    for (int a = 0; a < nk; ++a) {
+      if (K[a].phase == KiopsMachine::DONE) continue;
+      ++active;
+      if (!waiting[a]) ++runnable;
+    }
+    if (active == 0) break;
+    if (runnable == 0) {
+      if ((rc = harvest(true))) {
+        drain();
+        return rc;
+      }
+      continue;
+    }
+    std::vector<StartCall> starts;
+    std::vector<FirstCall> firsts;
+    std::vector<DfrCall> jv32, jv64;
+    std::vector<int> jv32_m, jv64_m;
+    std::vector<UpdateCall> ups;
+    std::vector<ExpmCall> ex;
+    std::vector<int> ex_a;
+    for (int a = 0; a < nk; ++a) {
+      KiopsMachine &k = K[a];
+      if (k.phase == KiopsMachine::DONE || waiting[a]) continue;
+      Ctx &c = *k.c;
+      const int64_t n3 = 3 * c.n;
+      if (k.phase == KiopsMachine::BEGIN) {
+        if ((rc = km_begin_attempt(k, o))) {
+          set_error("member " + std::to_string(mi[a]) + ": " + dfr_last_error());
+          drain();
+          return rc;
+        }
+        if (k.need_start) {
+          StartCall s{};
+          s.nblk = vec_blocks(n3);
+          s.n3 = n3;
+          s.x = k.w;
+          s.v0 = c.d_V;
+          s.pout = c.d_partials2;
+          starts.push_back(s);
+          k.npB = s.nblk;
+        }
+      }
+      if (k.phase == KiopsMachine::SWEEP) {
+        ArnoldiArgs ar;
+        km_arnoldi_args(k, o, ar);
+        double *out = c.d_V + (int64_t)(k.j + 1) * n3;
+        if (k.j == 0 && k.t == 0.0 && k.b0_absent) {
+          FirstCall f{};
+          f.nblk = vec_blocks(n3);
+          f.n3 = n3;
+          f.ar = ar;
+          f.out = out;
+          firsts.push_back(f);
+          k.npA = f.nblk;
+          k.skipped = true;
+        } else {
+          const void *qq = k.fp32 ? (const void *)k.q32 : (const void *)k.q;
+          DfrCall d = make_call(E, mi[a], true, qq, c.d_V + (int64_t)k.j * n3, k.eps, out, &ar);
+          if (k.fp32) {
+            jv32.push_back(d);
+            jv32_m.push_back(mi[a]);
+          } else {
+            jv64.push_back(d);
+            jv64_m.push_back(mi[a]);
+          }
+          k.npA = (int)dfr_num_tiles(&c, true);
+        }
+        UpdateCall u{};
+        u.nblk = vec_blocks(n3);
+        u.n3 = n3;
+        u.j = k.j;
+        u.p = k.p;
+        u.w = out;
+        u.vj = c.d_V + (int64_t)k.j * n3;
+        u.vprev = ar.vprev;
+        u.pin = c.d_partials;
+        u.np_in = k.npA;
+        u.pout = c.d_partials2;
+        u.kd = c.d_kd;
+        ups.push_back(u);
+        k.npB = u.nblk;
+        if (++k.j >= k.m) k.phase = KiopsMachine::EXPM;
+      }
+      if (k.phase == KiopsMachine::EXPM) {
+        ExpmCall x{};
+        x.kd = c.d_kd;
+        x.tau = k.tau;
+        x.res = E.d_kh + mi[a];
+        x.jfin = k.j;
+        x.pin = c.d_partials2;
+        x.np_in = k.npB;
+        x.tol = o.tol;
+        ex.push_back(x);
+        ex_a.push_back(a);
+      }
+    }
+    if (!rc) rc = launch_start_batch(E.stream, E.stage, starts);
+    if (!rc) rc = launch_first_batch(E.stream, E.stage, firsts);
+    if (!rc) rc = launch_dfr_groups(E, jv64_m, jv64, true, false, true);
+    if (!rc) rc = launch_dfr_groups(E, jv32_m, jv32, true, true, true);
+    if (!rc) rc = launch_update_batch(E.stream, E.stage, ups);
+    if (rc) {
+      drain();
+      return rc;
+    }
+    if (ex.empty()) continue;
+    Pending f;
+    if (!rc) rc = launch_expm_batch(E.stream, E.stage, ex, lds);
+    if (!rc) rc = take_event(&f.ev);
+    if (rc) {
+      drain();
+      return rc;
+    }
+    DFR_HIP(hipMemcpyAsync(E.h_kh, E.d_kh, sizeof(KHost) * E.n, hipMemcpyDeviceToHost, E.stream));
+    DFR_HIP(hipEventRecord(f.ev, E.stream));
+    f.a = ex_a;
+    for (int a : ex_a) waiting[a] = 1;
+    pend.push_back(std::move(f));
+  }
+  return DFR_OK;
+}
+
+// the members' latched errors (one read-back); the first one is returned
+static int ensemble_errors(dfr_ensemble &E) {
+  hipLaunchKernelGGL(gather_err_kernel, dim3((E.n + 255) / 256), dim3(256), 0, E.stream, E.d_errp, E.n, E.d_errv);
+  DFR_HIP(hipGetLastError());
+  DFR_HIP(hipMemcpyAsync(E.h_errv, E.d_errv, sizeof(int) * E.n, hipMemcpyDeviceToHost, E.stream));
+  int rc = sync_reset(E);
+  if (rc) return rc;
+  for (int i = 0; i < E.n; ++i) {
+    const int f = E.h_errv[i];
+    if (!f) continue;
+    if (f & 1) {
+      set_error("member " + std::to_string(i) + ": non-finite value in an input state");
+      return DFR_E_NONFINITE;
+    }
+    set_error("member " + std::to_string(i) + ": non-positive fluid depth H");
+    return DFR_E_DEPTH;
+  }
+  return DFR_OK;
+}
+
+static void free_ensemble(dfr_ensemble *E) {
+  if (!E) return;
+  if (E->stream) (void)hipStreamSynchronize(E->stream);
+  for (dfr_ctx *m : E->mem) dfr_destroy(m);
+  (void)hipFree(E->d_ga);
+  (void)hipFree(E->d_ops);
+  (void)hipFree(E->stage.d);
+  (void)hipHostFree(E->stage.h);
+  (void)hipFree(E->d_res);
+  (void)hipHostFree(E->h_res);
+  (void)hipFree(E->d_kh);
+  (void)hipHostFree(E->h_kh);
+  (void)hipFree(E->d_errp);
+  (void)hipFree(E->d_errv);
+  (void)hipHostFree(E->h_errv);
+  for (hipEvent_t ev : E->evfree) (void)hipEventDestroy(ev);
+  delete E;
+}
+
+}  // namespace dfrsw
+
+extern "C" {
+
+int dfr_ensemble_create(int n, const dfr_grid_desc *members, void *hip_stream, dfr_ensemble **out) {
+  if (n < 1 || n > 256 || !members || !out) {
+    set_error("dfr_ensemble_create: need 1 <= n <= 256 member descriptors");
+    return DFR_E_INVAL;
+  }
+  *out = nullptr;
+  dfr_ensemble *E = new (std::nothrow) dfr_ensemble();
+  if (!E) return DFR_E_NOMEM;
+  E->n = n;
+  E->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&E->device);
+  int rc = DFR_OK;
+  for (int i = 0; i < n && !rc; ++i) {
+    dfr_ctx *m = nullptr;
+    rc = dfr_create(&members[i], hip_stream, &m);
+    if (rc) {
+      set_error("member " + std::to_string(i) + ": " + dfr_last_error());
+      break;
+    }
+    E->mem.push_back(m);
+  }
+  auto fail = [&](int code) {
+    free_ensemble(E);
+    return code;
+  };
+  if (rc) return fail(rc);
+  std::vector<GridArgs> ga(n);
+  std::vector<Ops1D> ops(n);
+  std::vector<int *> errp(n);
+  for (int i = 0; i < n; ++i) {
+    ga[i] = E->mem[i]->c.ga;
+    ops[i] = E->mem[i]->c.ops;
+    errp[i] = E->mem[i]->c.d_err;
+  }
+  const size_t nres = (size_t)n * (MAX_P + 1);
+  if (hipMalloc(&E->d_ga, sizeof(GridArgs) * n) != hipSuccess || hipMalloc(&E->d_ops, sizeof(Ops1D) * n) != hipSuccess ||
+      hipMalloc(&E->stage.d, STAGE_BYTES) != hipSuccess ||
+      hipHostMalloc((void **)&E->stage.h, STAGE_BYTES, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&E->d_res, sizeof(double) * nres) != hipSuccess ||
+      hipHostMalloc((void **)&E->h_res, sizeof(double) * nres, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&E->d_kh, sizeof(KHost) * n) != hipSuccess ||
+      hipHostMalloc((void **)&E->h_kh, sizeof(KHost) * n, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&E->d_errp, sizeof(int *) * n) != hipSuccess || hipMalloc(&E->d_errv, sizeof(int) * n) != hipSuccess ||
+      hipHostMalloc((void **)&E->h_errv, sizeof(int) * n, hipHostMallocDefault) != hipSuccess) {
+    set_error("dfr_ensemble_create: allocation failed");
+    return fail(DFR_E_NOMEM);
+  }
+  E->stage.cap = STAGE_BYTES;
+  if (hipMemcpy(E->d_ga, ga.data(), sizeof(GridArgs) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(E->d_ops, ops.data(), sizeof(Ops1D) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(E->d_errp, errp.data(), sizeof(int *) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("dfr_ensemble_create: copy failed");
+    return fail(DFR_E_HIP);
+  }
+  *out = E;
+  return DFR_OK;
+}
+
+int dfr_ensemble_destroy(dfr_ensemble *E) {
+  free_ensemble(E);
+  return DFR_OK;
+}
+
+int dfr_ensemble_size(const dfr_ensemble *E) { return E ? E->n : -1; }
+
+dfr_ctx *dfr_ensemble_member(dfr_ensemble *E, int i) {
+  if (!E || i < 0 || i >= E->n) {
+    set_error("dfr_ensemble_member: no such member");
+    return nullptr;
+  }
+  return E->mem[i];
+}
+
+int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
+  if (!E || (prec != DFR_FP64 && prec != DFR_FP32_JV)) {
+    set_error("dfr_ensemble_autotune: invalid argument");
+    return DFR_E_INVAL;
+  }
+  const bool fp32 = prec == DFR_FP32_JV;
+  const int n = E->n;
+  int rc = DFR_OK;
+  // a smooth state and a direction in every member's Krylov workspace
+  for (int i = 0; i < n && !rc; ++i) {
+    Ctx &c = E->mem[i]->c;
+    const int64_t n3 = 3 * c.n;
+    rc = launch_fill(&c, c.d_V, c.d_V + n3);
+    if (!rc && fp32) rc = launch_copy_to_f32(&c, n3, c.d_V, (float *)c.d_qf32);
+    if (!rc) DFR_HIP(hipMemsetAsync(&c.d_kd->happy, 0, sizeof(int), E->stream));
+  }
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  DFR_HIP(hipEventCreate(&e0));
+  DFR_HIP(hipEventCreate(&e1));
+  for (int ns = 2; ns <= MAX_NS && !rc; ++ns) {
+    std::vector<int> grp;
+    for (int i = 0; i < n; ++i)
+      if (E->mem[i]->c.ns == ns) grp.push_back(i);
+    if (grp.empty()) continue;
+    // tiles admissible for every member of the group
+    std::vector<std::pair<int, int>> cand = tile_candidates(E->mem[grp[0]]->c);
+    for (size_t g = 1; g < grp.size(); ++g) {
+      const auto other = tile_candidates(E->mem[grp[g]]->c);
+      std::vector<std::pair<int, int>> keep;
+      for (const auto &t : cand)
+        if (std::find(other.begin(), other.end(), t) != other.end()) keep.push_back(t);
+      cand.swap(keep);
+    }
+    float best = 1e30f;
+    std::pair<int, int> bt{E->mem[grp[0]]->c.ar_tx, E->mem[grp[0]]->c.ar_ty};
+    for (const auto &t : cand) {
+      std::vector<DfrCall> calls;
+      std::vector<int> mem;
+      for (int i : grp) {
+        Ctx &c = E->mem[i]->c;
+        c.ar_tx = c.tile_tx = t.first;
+        c.ar_ty = c.tile_ty = t.second;
+        const int64_t n3 = 3 * c.n;
+        ArnoldiArgs ar{};
+        ar.on = 1;
+        ar.p = std::min(4, MAX_P);
+        ar.start = 1;
+        for (int k = 0; k < ar.p; ++k) ar.W[k] = c.d_V + n3;
+        ar.vprev = c.d_V;
+        ar.pin = c.d_V;
+        ar.np_in = 1;
+        ar.pout = c.d_partials;
+        ar.kd = c.d_kd;
+        ar.ybot[0] = 1.0;
+        const void *q = fp32 ? (const void *)c.d_qf32 : (const void *)c.d_V;
+        calls.push_back(make_call(*E, i, true, q, c.d_V + n3, fp32 ? 1e-20 : 1e-150, c.d_V + 2 * n3, &ar));
+        mem.push_back(i);
+      }
+      float ms = 0.f;
+      for (int r = 0; r < 4 && !rc; ++r) {
+        if (r == 1) (void)hipEventRecord(e0, E->stream);
+        std::vector<DfrCall> cc = calls;
+        rc = launch_dfr_groups(*E, mem, cc, true, fp32, true);
+      }
+      if (rc) break;
+      (void)hipEventRecord(e1, E->stream);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      reset_stage(E->stage);
+      if (ms < best) {
+        best = ms;
+        bt = t;
+      }
+    }
+    for (int i : grp) {
+      Ctx &c = E->mem[i]->c;
+      c.ar_tx = c.tile_tx = bt.first;
+      c.ar_ty = c.tile_ty = bt.second;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  return sync_reset(*E);
+}
+
+int epi_ensemble_create(dfr_ensemble *E, int order, double dt, int startup_substeps, const double *const *q0,
+                        double eps, dfr_precision prec, epi_ensemble **out) {
+  if (!E || !q0 || !out) {
+    set_error("epi_ensemble_create: invalid argument");
+    return DFR_E_INVAL;
+  }
+  *out = nullptr;
+  epi_ensemble *X = new (std::nothrow) epi_ensemble();
+  if (!X) return DFR_E_NOMEM;
+  X->e = E;
+  for (int i = 0; i < E->n; ++i) {
+    epi_state *st = nullptr;
+    const int rc = epi_create(E->mem[i], order, dt, startup_substeps, q0[i], eps, prec, &st);
+    if (rc) {
+      set_error("member " + std::to_string(i) + ": " + dfr_last_error());
+      for (epi_state *s : X->st) epi_destroy(s);
+      delete X;
+      return rc;
+    }
+    X->st.push_back(st);
+  }
+  *out = X;
+  return DFR_OK;
+}
+
+int epi_ensemble_destroy(epi_ensemble *X) {
+  if (!X) return DFR_OK;
+  for (epi_state *s : X->st) epi_destroy(s);
+  delete X;
+  return DFR_OK;
+}
+
+int epi_ensemble_get_state(const epi_ensemble *X, int i, double *q) {
+  if (!X || i < 0 || i >= (int)X->st.size()) {
+    set_error("epi_ensemble_get_state: no such member");
+    return DFR_E_INVAL;
+  }
+  return epi_get_state(X->st[i], q);
+}
+
+int epi_ensemble_step(dfr_ensemble *E, epi_ensemble *X, const kiops_opts *o, kiops_stats *stats) {
+  if (!E || !X || X->e != E || !o) {
+    set_error("epi_ensemble_step: invalid argument");
+    return DFR_E_INVAL;
+  }
+  const int n = E->n;
+  epi_state *s0 = X->st[0];
+  for (int i = 0; i < n; ++i) {
+    const epi_state *s = X->st[i];
+    if (s->order != s0->order || s->nsteps != s0->nsteps || s->s != s0->s || s->prec != s0->prec ||
+        s->dt != s0->dt) {
+      set_error("epi_ensemble_step: members differ in order, step count, start-up, precision or dt");
+      return DFR_E_INVAL;
+    }
+    int rc = kiops_validate(E->mem[i]->c, *o, s->M > 0 ? s->M : 1, s->dt);
+    if (rc) return rc;
+  }
+  if (stats) std::memset(stats, 0, sizeof(kiops_stats) * n);
+  const bool fp32 = s0->prec == DFR_FP32_JV;
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  int rc = sync_reset(*E);
+  if (rc) return rc;
+  hipStream_t S = E->stream;
+  Stage &ST = E->stage;
+  auto st = [&](int i) { return X->st[i]; };
+  auto cx = [&](int i) -> Ctx & { return E->mem[i]->c; };
+  auto n3 = [&](int i) { return 3 * cx(i).n; };
+  // vector launch helper: one call per member
+  auto vec = [&](auto make) {
+    std::vector<AxpbyCall> v;
+    for (int i = 0; i < n; ++i) v.push_back(make(i));
+    return launch_vec_batch(S, ST, VB_AXPBY, v);
+  };
+  auto rhs = [&](auto qof, auto outof) {
+    std::vector<DfrCall> c;
+    for (int i = 0; i < n; ++i) c.push_back(make_call(*E, i, false, qof(i), nullptr, 0.0, outof(i), nullptr));
+    return launch_dfr_groups(*E, all, c, false, false, false);
+  };
+  auto to_f32 = [&](auto qof) {
+    std::vector<AxpbyCall> v;
+    for (int i = 0; i < n; ++i) v.push_back(vcall(n3(i), 1.0, qof(i), 0.0, nullptr, cx(i).d_qf32));
+    return launch_vec_batch(S, ST, VB_TO_F32, v);
+  };
+  auto kiops = [&](auto qof, double tau, int n_phi, auto bof) {
+    std::vector<KiopsMachine> K(n);
+    for (int i = 0; i < n; ++i) {
+      KiopsMachine &k = K[i];
+      k.c = &cx(i);
+      k.q = qof(i);
+      k.q32 = fp32 ? (const float *)cx(i).d_qf32 : nullptr;
+      k.n_phi = n_phi;
+      for (int j = 0; j <= n_phi; ++j) k.b[j] = bof(i, j);
+      k.b0_absent = (k.b[0] == nullptr);
+      k.w = st(i)->w;
+      k.tau_out = tau;
+      k.eps = st(i)->eps;
+      k.fp32 = fp32;
+    }
+    int r = kiops_batch(*E, K, all, *o);
+    if (stats)
+      for (int i = 0; i < n; ++i) add_stats(&stats[i], K[i].st);
+    return r;
+  };
+
+  // state checks and F_n
+  {
+    std::vector<AxpbyCall> v;
+    for (int i = 0; i < n; ++i) {
+      AxpbyCall c = vcall(cx(i).n, 0.0, st(i)->q, 0.0, nullptr, (double *)cx(i).d_err);
+      c.nblk = vec_blocks(3 * cx(i).n);
+      v.push_back(c);
+    }
+    if ((rc = launch_vec_batch(S, ST, VB_CHECK, v))) return rc;
+  }
+  if ((rc = rhs([&](int i) { return (const void *)st(i)->q; }, [&](int i) { return st(i)->F; }))) return rc;
+  std::vector<double *> q_new(n);
+  if (s0->nsteps < s0->P || s0->order == 2) {
+    // EPI2 start-up (Eq. 25) with s sub-steps, or plain EPI2
+    const int s = s0->order == 2 ? 1 : s0->s;
+    const double hstep = s0->dt / s;
+    if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->q, 0.0, nullptr, st(i)->qs); }))) return rc;
+    for (int k = 0; k < s; ++k) {
+      if (k > 0 && (rc = rhs([&](int i) { return (const void *)st(i)->qs; }, [&](int i) { return st(i)->d; })))
+        return rc;
+      if (fp32 && (rc = to_f32([&](int i) { return (const double *)st(i)->qs; }))) return rc;
+      rc = kiops([&](int i) { return (const double *)st(i)->qs; }, hstep, 1,
+                 [&](int i, int j) { return j == 0 ? (const double *)nullptr : (k > 0 ? st(i)->d : st(i)->F); });
+      if (rc) return rc;
+      if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->qs, 1.0, st(i)->w, st(i)->qs); }))) return rc;
+    }
+    for (int i = 0; i < n; ++i) q_new[i] = st(i)->qs;
+  } else {
+    if (fp32 && (rc = to_f32([&](int i) { return (const double *)st(i)->q; }))) return rc;
+    const double eps = s0->eps;
+    for (int r = 0; r < s0->P; ++r) {
+      // R_r = F(q_{n-r}) - F_n - J_n (q_{n-r} - q_n)   (Eq. 33 generalised)
+      if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->hq[r], -1.0, st(i)->q, st(i)->d); }))) return rc;
+      std::vector<DfrCall> c;
+      for (int i = 0; i < n; ++i) {
+        const void *qq = fp32 ? (const void *)cx(i).d_qf32 : (const void *)st(i)->q;
+        c.push_back(make_call(*E, i, false, qq, st(i)->d, eps, st(i)->jd, nullptr));
+      }
+      if ((rc = launch_dfr_groups(*E, all, c, true, fp32, false))) return rc;
+      if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->hF[r], -1.0, st(i)->F, st(i)->R[r]); }))) return rc;
+      if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->R[r], -1.0, st(i)->jd, st(i)->R[r]); }))) return rc;
+    }
+    // b_1 = F_n, b_m = sum_i alpha_{m,i} R_i / dt^{m-1}
+    for (int m = 2; m <= s0->M; ++m) {
+      bool first = true;
+      for (int r = 1; r <= s0->P; ++r) {
+        const double a = s0->A[m - 1][r - 1];
+        if (a == 0.0) continue;
+        rc = vec([&](int i) {
+          double *bm = st(i)->bm[m - 1];
+          return first ? vcall(n3(i), a, st(i)->R[r - 1], 0.0, nullptr, bm)
+                       : vcall(n3(i), 1.0, bm, a, st(i)->R[r - 1], bm);
+        });
+        if (rc) return rc;
+        first = false;
+      }
+      const double sc = 1.0 / std::pow(s0->dt, (double)(m - 1));
+      rc = vec([&](int i) {
+        double *bm = st(i)->bm[m - 1];
+        return first ? vcall(n3(i), 0.0, nullptr, 0.0, nullptr, bm) : vcall(n3(i), sc, bm, 0.0, nullptr, bm);
+      });
+      if (rc) return rc;
+    }
+    rc = kiops([&](int i) { return (const double *)st(i)->q; }, s0->dt, s0->M, [&](int i, int j) {
+      return j == 0 ? (const double *)nullptr : (j == 1 ? (const double *)st(i)->F : (const double *)st(i)->bm[j - 1]);
+    });
+    if (rc) return rc;
+    if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->q, 1.0, st(i)->w, st(i)->qs); }))) return rc;
+    for (int i = 0; i < n; ++i) q_new[i] = st(i)->qs;
+  }
+  for (int i = 0; i < n; ++i) epi_rotate(st(i), q_new[i]);
+  return ensemble_errors(*E);
+}
+
+}  // extern "C"

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dfrsw.h"
@@ -83,6 +84,7 @@ struct ArnoldiArgs {
 struct DfrCall {
   const GridArgs *g;      // device copy of the member's grid arguments
   const Ops1D *ops;       // device copy of its 1-D operators
+  int g_ne;              // its ne
   int TX, TY;             // its tile
   int b0, ntiles;
   const void *q;          // state (double, or float in the FP32 form)
@@ -236,12 +238,94 @@ int launch_fill(Ctx *c, double *q, double *v);
 int latched_error(Ctx &c);
 size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32);
 int dfr_set_lds_limits(Ctx *c, size_t bytes);
+// KIOPS (kiops.hip): statistics of one run and its controller as a state
+// machine, shared by the single-grid driver and the batched driver.
+struct KiopsRun {
+  int n_matvec = 0, n_substeps = 0, n_rejected = 0, m_last = 0, happy = 0, n_expm = 0;
+};
+struct KiopsMachine {
+  Ctx *c = nullptr;
+  const double *q = nullptr;
+  const float *q32 = nullptr;
+  const double *b[MAX_P + 1] = {};
+  double *w = nullptr;
+  double tau_out = 0.0, eps = 0.0;
+  bool fp32 = false;
+  int n_phi = 0, p = 0;
+  bool b0_absent = true;
+  double nu = 1.0, mu = 1.0;
+  int m = 0, m_min = 0, m_max = 0;
+  double t = 0.0, tau = 0.0;
+  int j = 0;
+  double beta0 = -1.0;
+  int ireject = 0;
+  double old_tau = 0.0, old_omega = 0.0;
+  int old_m = -1, attempts = 0;
+  double ybot[MAX_P] = {};
+  int j_sweep = 0;
+  bool skipped = false, need_start = false;
+  int npA = 0, npB = 0;
+  enum Phase { BEGIN, SWEEP, EXPM, DONE } phase = BEGIN;
+  KiopsRun st;
+};
+int kiops_validate(const Ctx &c, const kiops_opts &o, int n_phi, double tau_out);
+bool km_init(KiopsMachine &k, const double *nrm2, const kiops_opts &o);
+int km_begin_attempt(KiopsMachine &k, const kiops_opts &o);
+void km_arnoldi_args(const KiopsMachine &k, const kiops_opts &o, ArnoldiArgs &ar);
+int km_decide(KiopsMachine &k, const KHost &r, const kiops_opts &o, bool *accept);
+int latched_error(Ctx &c);
+void epi_table(int order, std::vector<std::vector<double>> &A);
+void add_stats(kiops_stats *acc, const KiopsRun &r);
+}  // namespace dfrsw
+struct epi_state;
+namespace dfrsw {
+void epi_rotate(epi_state *st, double *q_new);
+
+// Staging of call tables for batched launches: a pinned host arena and its
+// device mirror; each table is copied on the stream before its launch.  The
+// arena is reset (reset_stage) only after the stream has been synchronised.
+struct Stage {
+  char *h = nullptr, *d = nullptr;
+  size_t cap = 0, used = 0;
+};
+int stage_put(Stage &st, hipStream_t s, const void *src, size_t bytes, void **dev);
+inline void reset_stage(Stage &st) { st.used = 0; }
+
+// batched launches: every call of one launch has the same form (and, for the
+// DFR kernel, the same number of GL points ns)
+int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool fp32, bool arnoldi,
+                     std::vector<DfrCall> &calls);
+int launch_first_batch(hipStream_t s, Stage &st, std::vector<FirstCall> &calls);
+int launch_update_batch(hipStream_t s, Stage &st, std::vector<UpdateCall> &calls);
+int launch_start_batch(hipStream_t s, Stage &st, std::vector<StartCall> &calls);
+int launch_combine_batch(hipStream_t s, Stage &st, std::vector<CombineCall> &calls);
+int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, size_t lds);
+enum { VB_AXPBY = 0, VB_TO_F32 = 1, VB_NORM2 = 2, VB_SUM = 3, VB_CHECK = 4 };
+int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls);
+int vec_blocks(int64_t n);   // workgroups of a vector kernel on n values (at most 1024)
+
 int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi);
 int64_t dfr_num_tiles(const Ctx *c, bool arnoldi);
+std::vector<std::pair<int, int>> tile_candidates(const Ctx &c);   // admissible tiles (api.hip)
 int launch_norm2(Ctx *c, int64_t n, const double *x, double *partials, int nblk);
 int launch_sum(Ctx *c, int np, const double *partials, double *out);
 
 }  // namespace dfrsw
+
+// Multistep EPI integrator state (kiops.hip): history q_{n-i}, F(q_{n-i}),
+// remainders, b-vectors.
+struct epi_state {
+  dfrsw::Ctx *c;
+  int order, P, M;
+  double dt;
+  int s;
+  double eps;
+  dfr_precision prec;
+  int64_t nsteps;
+  double *q, *F, *qs, *w, *d, *jd;
+  std::vector<double *> hq, hF, R, bm;
+  std::vector<std::vector<double>> A;   // alpha_{m,i}
+};
 
 struct dfr_ctx {
   dfrsw::Ctx c;

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 namespace dfrsw {
 
@@ -1105,10 +1106,11 @@ __global__ __launch_bounds__(EXPM_BLOCK) void expm_batch(const ExpmCall *__restr
 
 // ---------------------------------------------------------------------------
 // vector helpers
+// out = a x + b y; x or y may be NULL (no term)
 __device__ __forceinline__ void axpby_body(int blk, int nblk, int64_t n, double a, const double *x, double b,
                                            const double *y, double *out) {
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n; i += (int64_t)nblk * BLOCK) {
-    double r = a * x[i];
+    double r = x ? a * x[i] : 0.0;
     if (y) r += b * y[i];
     out[i] = r;
   }
@@ -1246,7 +1248,12 @@ static int set_lds_attr(size_t bytes) {
                        (const void *)dfr_kernel<NS, double, double, true, false>,
                        (const void *)dfr_kernel<NS, float, float, true, false>,
                        (const void *)dfr_kernel<NS, double, double, true, true>,
-                       (const void *)dfr_kernel<NS, float, float, true, true>};
+                       (const void *)dfr_kernel<NS, float, float, true, true>,
+                       (const void *)dfr_kernel_batch<NS, double, double, false, false>,
+                       (const void *)dfr_kernel_batch<NS, double, double, true, false>,
+                       (const void *)dfr_kernel_batch<NS, float, float, true, false>,
+                       (const void *)dfr_kernel_batch<NS, double, double, true, true>,
+                       (const void *)dfr_kernel_batch<NS, float, float, true, true>};
   for (const void *f : fns) DFR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return DFR_OK;
 }
@@ -1373,8 +1380,140 @@ int launch_check_state(Ctx *c, const double *q) {
 
 int set_expm_lds_limit(int m) {
   const size_t lds = expm_lds_bytes(m);
+  DFR_HIP(hipFuncSetAttribute((const void *)expm_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   DFR_HIP(hipFuncSetAttribute((const void *)expm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return DFR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched launchers
+
+int stage_put(Stage &st, hipStream_t s, const void *src, size_t bytes, void **dev) {
+  const size_t off = (st.used + 255) & ~(size_t)255;
+  if (off + bytes > st.cap) {
+    // the arena is full: wait for the copies in flight, then start over
+    DFR_HIP(hipStreamSynchronize(s));
+    st.used = 0;
+    return stage_put(st, s, src, bytes, dev);
+  }
+  std::memcpy(st.h + off, src, bytes);
+  DFR_HIP(hipMemcpyAsync(st.d + off, st.h + off, bytes, hipMemcpyHostToDevice, s));
+  st.used = off + bytes;
+  *dev = st.d + off;
+  return DFR_OK;
+}
+
+int vec_blocks(int64_t n) { return grid_reduce(n); }
+
+template <typename C>
+static int set_b0(std::vector<C> &calls) {
+  int b = 0;
+  for (auto &c : calls) {
+    c.b0 = b;
+    b += c.nblk;
+  }
+  return b;
+}
+
+template <int NS, typename T, typename TQ, bool CS, bool AR>
+static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &calls) {
+  int nlog = 0, threads = 256;
+  size_t lds = 0;
+  for (auto &c : calls) {
+    c.b0 = nlog;
+    c.ntiles = 6 * (c.g_ne / c.TX) * (c.g_ne / c.TY);
+    nlog += c.ntiles;
+    threads = std::max(threads, ((c.TX * c.TY * NS * NS + 63) / 64) * 64);
+    lds = std::max(lds, (size_t)dfr_lds_layout(NS, c.TX, c.TY, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T));
+  }
+  void *d = nullptr;
+  int rc = stage_put(st, s, calls.data(), sizeof(DfrCall) * calls.size(), &d);
+  if (rc) return rc;
+  const int grid = ((nlog + 7) / 8) * 8;
+  hipLaunchKernelGGL((dfr_kernel_batch<NS, T, TQ, CS, AR>), dim3(grid), dim3(threads), lds, s, (const DfrCall *)d,
+                     (int)calls.size(), nlog);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+template <int NS>
+static int launch_dfr_batch_form(hipStream_t s, Stage &st, bool cs, bool fp32, bool ar, std::vector<DfrCall> &calls) {
+  if (!cs) return launch_dfr_batch_ns<NS, double, double, false, false>(s, st, calls);
+  if (fp32) {
+    return ar ? launch_dfr_batch_ns<NS, float, float, true, true>(s, st, calls)
+              : launch_dfr_batch_ns<NS, float, float, true, false>(s, st, calls);
+  }
+  return ar ? launch_dfr_batch_ns<NS, double, double, true, true>(s, st, calls)
+            : launch_dfr_batch_ns<NS, double, double, true, false>(s, st, calls);
+}
+
+int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool fp32, bool arnoldi,
+                     std::vector<DfrCall> &calls) {
+  if (calls.empty()) return DFR_OK;
+  switch (ns) {
+    case 2: return launch_dfr_batch_form<2>(s, st, complex_step, fp32, arnoldi, calls);
+    case 3: return launch_dfr_batch_form<3>(s, st, complex_step, fp32, arnoldi, calls);
+    case 4: return launch_dfr_batch_form<4>(s, st, complex_step, fp32, arnoldi, calls);
+    case 5: return launch_dfr_batch_form<5>(s, st, complex_step, fp32, arnoldi, calls);
+    case 6: return launch_dfr_batch_form<6>(s, st, complex_step, fp32, arnoldi, calls);
+    case 7: return launch_dfr_batch_form<7>(s, st, complex_step, fp32, arnoldi, calls);
+    case 8: return launch_dfr_batch_form<8>(s, st, complex_step, fp32, arnoldi, calls);
+    default: set_error("unsupported number of GL points"); return DFR_E_INVAL;
+  }
+}
+
+template <typename C, typename K>
+static int launch_calls(hipStream_t s, Stage &st, std::vector<C> &calls, K kernel) {
+  if (calls.empty()) return DFR_OK;
+  const int nb = set_b0(calls);
+  void *d = nullptr;
+  int rc = stage_put(st, s, calls.data(), sizeof(C) * calls.size(), &d);
+  if (rc) return rc;
+  hipLaunchKernelGGL(kernel, dim3(nb), dim3(BLOCK), 0, s, (const C *)d, (int)calls.size());
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_first_batch(hipStream_t s, Stage &st, std::vector<FirstCall> &calls) {
+  return launch_calls(s, st, calls, arnoldi_first_batch);
+}
+int launch_update_batch(hipStream_t s, Stage &st, std::vector<UpdateCall> &calls) {
+  return launch_calls(s, st, calls, arnoldi_update_batch);
+}
+int launch_start_batch(hipStream_t s, Stage &st, std::vector<StartCall> &calls) {
+  return launch_calls(s, st, calls, arnoldi_start_batch);
+}
+int launch_combine_batch(hipStream_t s, Stage &st, std::vector<CombineCall> &calls) {
+  return launch_calls(s, st, calls, arnoldi_combine_batch);
+}
+
+int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, size_t lds) {
+  if (calls.empty()) return DFR_OK;
+  void *d = nullptr;
+  int rc = stage_put(st, s, calls.data(), sizeof(ExpmCall) * calls.size(), &d);
+  if (rc) return rc;
+  hipLaunchKernelGGL(expm_batch, dim3((unsigned)calls.size()), dim3(EXPM_BLOCK), lds, s, (const ExpmCall *)d);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls) {
+  switch (kind) {
+    case VB_AXPBY: return launch_calls(s, st, calls, axpby_batch);
+    case VB_TO_F32: return launch_calls(s, st, calls, to_f32_batch);
+    case VB_NORM2: return launch_calls(s, st, calls, norm2_batch);
+    case VB_CHECK: return launch_calls(s, st, calls, check_state_batch);
+    case VB_SUM: {
+      if (calls.empty()) return DFR_OK;
+      void *d = nullptr;
+      int rc = stage_put(st, s, calls.data(), sizeof(AxpbyCall) * calls.size(), &d);
+      if (rc) return rc;
+      hipLaunchKernelGGL(sum_batch, dim3((unsigned)calls.size()), dim3(BLOCK), 0, s, (const AxpbyCall *)d);
+      DFR_HIP(hipGetLastError());
+      return DFR_OK;
+    }
+    default: set_error("unknown batched vector kernel"); return DFR_E_INVAL;
+  }
 }
 
 }  // namespace dfrsw

@@ -60,13 +60,7 @@ static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
   return DFR_OK;
 }
 
-struct KiopsRun {
-  int n_matvec = 0, n_substeps = 0, n_rejected = 0, m_last = 0, happy = 0, n_expm = 0;
-};
-
-static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out, int n_phi, const double *const *b,
-                      const kiops_opts &o, double eps, bool fp32, double *w, KiopsRun &st) {
-  const int64_t n3 = 3 * c.n;
+int kiops_validate(const Ctx &c, const kiops_opts &o, int n_phi, double tau_out) {
   if (!(tau_out > 0.0) || !(o.tol > 0.0) || o.m_max < 1 || o.m_max > MAX_M || o.m_min < 1 || o.iop < 1 ||
       o.iop > 2 || n_phi < 0 || n_phi > MAX_P) {
     set_error("kiops: invalid options (need tau > 0, tol > 0, 1 <= m_min, m_max <= 64, iop = 1 or 2, n_phi <= 8)");
@@ -76,191 +70,241 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
     set_error("kiops: m_max exceeds the Krylov dimension this device supports (" + std::to_string(c.max_m) + ")");
     return DFR_E_INVAL;
   }
-  const bool b0_absent = (b[0] == nullptr);
-  int p = n_phi;
+  return DFR_OK;
+}
+
+// Scaling of the augmented operator from the norms ||b_k||^2 (K1) and the
+// initial controller state.  Returns false if every b_k is zero (w = 0).
+bool km_init(KiopsMachine &k, const double *nrm2, const kiops_opts &o) {
+  double nb = 0.0;
+  for (int i = 1; i <= k.n_phi; ++i) nb = std::max(nb, std::sqrt(nrm2[i]));
+  if (nb == 0.0 && nrm2[0] == 0.0) return false;
+  k.nu = k.mu = 1.0;
+  if (nb > 0.0) {
+    const int e = (int)std::ceil(std::log2(nb));
+    k.nu = std::ldexp(1.0, -e);
+    k.mu = std::ldexp(1.0, e);
+  }
+  k.p = k.n_phi == 0 ? 1 : k.n_phi;
+  k.m_max = o.m_max;
+  k.m_min = std::min(o.m_min, o.m_max);
+  k.m = std::max(k.m_min, std::min(o.m_init, k.m_max));
+  k.t = 0.0;
+  k.tau = k.tau_out;
+  k.j = 0;
+  k.beta0 = -1.0;
+  k.ireject = 0;
+  k.old_tau = k.old_omega = 0.0;
+  k.old_m = -1;
+  k.attempts = 0;
+  k.phase = KiopsMachine::BEGIN;
+  return true;
+}
+
+// Start of an attempt (a sweep continued or begun, then one exponential).
+int km_begin_attempt(KiopsMachine &k, const kiops_opts &o) {
+  if (++k.attempts > o.max_attempts) {
+    set_error("kiops: no convergence within max_attempts");
+    return DFR_E_KIOPS;
+  }
+  k.j_sweep = k.j;
+  k.skipped = false;
+  k.need_start = (k.j == 0);
+  if (k.need_start) {
+    for (int i = 0; i < k.p; ++i) {
+      const int pw = k.p - 1 - i;
+      double f = 1.0;
+      for (int r = 2; r <= pw; ++r) f *= r;
+      k.ybot[i] = k.mu * std::pow(k.t, (double)pw) / f;
+    }
+  }
+  k.phase = k.j < k.m ? KiopsMachine::SWEEP : KiopsMachine::EXPM;
+  return DFR_OK;
+}
+
+// Arguments of the Krylov-form product for basis vector j.
+void km_arnoldi_args(const KiopsMachine &k, const kiops_opts &o, ArnoldiArgs &ar) {
+  const Ctx &c = *k.c;
+  const int64_t n3 = 3 * c.n;
+  ar = ArnoldiArgs{};
+  ar.on = 1;
+  ar.j = k.j;
+  ar.p = k.p;
+  ar.start = (k.j == 0);
+  for (int i = 0; i < k.p; ++i) {
+    ar.W[i] = c.d_W + i * n3;
+    ar.ybot[i] = k.ybot[i];
+  }
+  ar.vprev = (k.j >= 1 && o.iop >= 2) ? c.d_V + (int64_t)(k.j - 1) * n3 : nullptr;
+  ar.pin = c.d_partials2;
+  ar.np_in = k.npB;
+  ar.pout = c.d_partials;
+  ar.kd = c.d_kd;
+  ar.tol = o.tol;
+}
+
+// The controller after one exponential (K4-K7).  Sets *accept; the caller
+// forms the accepted sub-step's result (combination kernel) before the next
+// attempt.
+int km_decide(KiopsMachine &k, const KHost &r, const kiops_opts &o, bool *accept_out) {
+  const double DELTA = 1.2, GAMMA = 0.2, GAMMA_MMAX = 0.6;
+  k.st.n_expm++;
+  const int J = r.J;
+  k.st.n_matvec += (J - k.j_sweep) - (k.skipped ? 1 : 0);
+  if (k.beta0 < 0.0) k.beta0 = r.beta;
+  if (!std::isfinite(r.err) || !std::isfinite(r.beta)) {
+    set_error("kiops: non-finite Krylov quantities");
+    return DFR_E_NONFINITE;
+  }
+  const double tau = k.tau, tau_out = k.tau_out, t = k.t;
+  const int m = k.m;
+  bool accept;
+  double omega, tau_new;
+  int m_new;
+  if (r.happy) {
+    k.j = J;
+    omega = 0.0;
+    accept = true;
+    m_new = m;
+    tau_new = std::min(tau_out - (t + tau), tau);
+    k.st.happy = 1;
+  } else {
+    omega = (tau_out / tau) * r.err / (o.tol * k.beta0);
+    omega = std::max(omega, 1e-300);
+    accept = omega <= DELTA;
+    double order;
+    if (k.ireject >= 1 && m == k.old_m && tau != k.old_tau)
+      order = std::max(1.0, std::log(omega / k.old_omega) / std::log(tau / k.old_tau));
+    else
+      order = J / 4.0;
+    double kest;
+    if (k.ireject >= 1 && m != k.old_m && tau == k.old_tau)
+      kest = std::max(1.1, std::pow(omega / k.old_omega, 1.0 / (k.old_m - m)));
+    else
+      kest = 2.0;
+    const double remaining = accept ? tau_out - (t + tau) : tau_out - t;
+    double tau_opt = tau * std::pow(GAMMA / omega, 1.0 / order);
+    tau_opt = std::min(remaining, std::max(tau / 5.0, std::min(5.0 * tau, tau_opt)));
+    int m_opt = (int)std::ceil(J + std::log(omega / GAMMA) / std::log(kest));
+    m_opt = std::max(k.m_min, std::min(k.m_max, std::max((int)std::floor(0.75 * m),
+                                                          std::min(m_opt, (int)std::ceil(4.0 * m / 3.0)))));
+    if (J == k.m_max) {
+      if (omega > DELTA) {
+        m_new = J;
+        tau_new = tau * std::pow(GAMMA_MMAX / omega, 1.0 / order);
+        tau_new = std::min(remaining, std::max(tau / 5.0, tau_new));
+      } else {
+        m_new = m;
+        tau_new = tau_opt;
+      }
+    } else {
+      m_new = m_opt;
+      tau_new = std::min(remaining, tau);
+    }
+  }
+  if (accept) {
+    if (tau >= tau_out - t) k.t = tau_out;
+    else k.t = t + tau;
+    k.st.n_substeps++;
+    k.st.m_last = J;
+    k.j = 0;
+    k.ireject = 0;
+  } else {
+    k.ireject++;
+    k.st.n_rejected++;
+  }
+  k.old_tau = tau;
+  k.old_m = m;
+  k.old_omega = omega;
+  k.tau = tau_new;
+  k.m = m_new;
+  *accept_out = accept;
+  k.phase = k.t < tau_out ? KiopsMachine::BEGIN : KiopsMachine::DONE;
+  if (k.t < tau_out && !(k.tau > 0.0)) {
+    set_error("kiops: step size collapsed");
+    return DFR_E_KIOPS;
+  }
+  return DFR_OK;
+}
+
+static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out, int n_phi, const double *const *b,
+                      const kiops_opts &o, double eps, bool fp32, double *w, KiopsRun &st) {
+  const int64_t n3 = 3 * c.n;
+  int rc = kiops_validate(c, o, n_phi, tau_out);
+  if (rc) return rc;
+  KiopsMachine k;
+  k.c = &c;
+  k.q = q;
+  k.q32 = q32;
+  k.n_phi = n_phi;
+  for (int i = 0; i <= n_phi; ++i) k.b[i] = b[i];
+  k.b0_absent = (b[0] == nullptr);
+  k.w = w;
+  k.tau_out = tau_out;
+  k.eps = eps;
+  k.fp32 = fp32;
   // norms of b_0..b_p
   double nrm2[MAX_P + 1];
-  int rc = norms2(c, n_phi + 1, b, nrm2);
+  rc = norms2(c, n_phi + 1, b, nrm2);
   if (rc) return rc;
-  double nb = 0.0;
-  for (int k = 1; k <= n_phi; ++k) nb = std::max(nb, std::sqrt(nrm2[k]));
-  if (nb == 0.0 && nrm2[0] == 0.0) {
+  if (!km_init(k, nrm2, o)) {
     DFR_HIP(hipMemsetAsync(w, 0, sizeof(double) * n3, c.stream));
     DFR_HIP(hipStreamSynchronize(c.stream));
     return DFR_OK;
   }
-  double nu = 1.0, mu = 1.0;
-  if (nb > 0.0) {
-    const int e = (int)std::ceil(std::log2(nb));
-    nu = std::ldexp(1.0, -e);
-    mu = std::ldexp(1.0, e);
+  // W = nu [b_p, ..., b_1] (a zero column when there is no b_1); x = b_0
+  for (int i = 0; i < k.p; ++i) {
+    const double *bi = n_phi == 0 ? nullptr : b[k.p - i];
+    rc = launch_axpby(&c, n3, k.nu, bi, 0.0, nullptr, c.d_W + i * n3);
+    if (rc) return rc;
   }
-  if (p == 0) {
-    p = 1;
-    DFR_HIP(hipMemsetAsync(c.d_W, 0, sizeof(double) * n3, c.stream));
-  } else {
-    for (int k = 0; k < p; ++k) {
-      const double *bk = b[p - k];
-      if (bk) rc = launch_axpby(&c, n3, nu, bk, 0.0, nullptr, c.d_W + k * n3);
-      else {
-        DFR_HIP(hipMemsetAsync(c.d_W + k * n3, 0, sizeof(double) * n3, c.stream));
-        rc = DFR_OK;
-      }
-      if (rc) return rc;
-    }
-  }
-  c.kiops_p = p;
-  if (b0_absent) {
-    DFR_HIP(hipMemsetAsync(w, 0, sizeof(double) * n3, c.stream));
-  } else {
-    DFR_HIP(hipMemcpyAsync(w, b[0], sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
-  }
+  c.kiops_p = k.p;
+  c.kiops_mmax = k.m_max;
+  rc = launch_axpby(&c, n3, 1.0, b[0], 0.0, nullptr, w);
+  if (rc) return rc;
 
-  const double DELTA = 1.2, GAMMA = 0.2, GAMMA_MMAX = 0.6;
-  const int m_max = o.m_max, m_min = std::min(o.m_min, o.m_max);
-  c.kiops_mmax = m_max;
-  int m = std::max(m_min, std::min(o.m_init, m_max));
-  double t = 0.0, tau = tau_out;
-  int j = 0;
-  double beta0 = -1.0;
-  int ireject = 0;
-  double old_tau = 0.0, old_omega = 0.0;
-  int old_m = -1;
-  int attempts = 0;
   double *V = c.d_V;
-  KDev *kd = c.d_kd;
-
-  // partial-sum buffers: A = inner products of the J v kernels, B = norms
   double *pA = c.d_partials, *pB = c.d_partials2;
-  int npA = 0, npB = 0;
-  double ybot[MAX_P] = {0.0};
-  while (t < tau_out) {
-    if (++attempts > o.max_attempts) {
-      set_error("kiops: no convergence within max_attempts");
-      return DFR_E_KIOPS;
-    }
-    const int j_sweep = j;
-    bool skipped = false;
-    if (j == 0) {
-      for (int k = 0; k < p; ++k) {
-        const int pw = p - 1 - k;
-        double f = 1.0;
-        for (int i = 2; i <= pw; ++i) f *= i;
-        ybot[k] = mu * std::pow(t, (double)pw) / f;
-      }
-      rc = launch_start(&c, w, V, pB, &npB);
+  while (k.phase != KiopsMachine::DONE) {
+    rc = km_begin_attempt(k, o);
+    if (rc) return rc;
+    if (k.need_start) {
+      rc = launch_start(&c, w, V, pB, &k.npB);
       if (rc) return rc;
     }
-    while (j < m) {
-      ArnoldiArgs ar{};
-      ar.on = 1;
-      ar.j = j;
-      ar.p = p;
-      ar.start = (j == 0);
-      for (int k = 0; k < p; ++k) {
-        ar.W[k] = c.d_W + k * n3;
-        ar.ybot[k] = ybot[k];
-      }
-      ar.vprev = (j >= 1 && o.iop >= 2) ? V + (int64_t)(j - 1) * n3 : nullptr;
-      ar.pin = pB;
-      ar.np_in = npB;
-      ar.pout = pA;
-      ar.kd = kd;
-      ar.tol = o.tol;
-      double *out = V + (int64_t)(j + 1) * n3;
-      if (j == 0 && t == 0.0 && b0_absent) {
-        rc = launch_arnoldi_first(&c, ar, out, &npA);
-        skipped = true;
+    while (k.j < k.m) {
+      ArnoldiArgs ar;
+      km_arnoldi_args(k, o, ar);
+      double *out = V + (int64_t)(k.j + 1) * n3;
+      if (k.j == 0 && k.t == 0.0 && k.b0_absent) {
+        rc = launch_arnoldi_first(&c, ar, out, &k.npA);
+        k.skipped = true;
       } else {
-        rc = launch_dfr(&c, q, q32, V + (int64_t)j * n3, nullptr, eps, true, fp32, out, &ar);
-        npA = (int)dfr_num_tiles(&c, true);
+        rc = launch_dfr(&c, q, q32, V + (int64_t)k.j * n3, nullptr, eps, true, fp32, out, &ar);
+        k.npA = (int)dfr_num_tiles(&c, true);
       }
       if (rc) return rc;
-      rc = launch_update(&c, j, out, V + (int64_t)j * n3, ar.vprev, pA, npA, pB, &npB);
+      rc = launch_update(&c, k.j, out, V + (int64_t)k.j * n3, ar.vprev, pA, k.npA, pB, &k.npB);
       if (rc) return rc;
-      ++j;
+      ++k.j;
     }
-    rc = launch_expm(&c, tau, j, pB, npB, o.tol);
+    rc = launch_expm(&c, k.tau, k.j, pB, k.npB, o.tol);
     if (rc) return rc;
     DFR_HIP(hipMemcpyAsync(c.h_res, c.d_expm_scratch, sizeof(KHost), hipMemcpyDeviceToHost, c.stream));
     DFR_HIP(hipStreamSynchronize(c.stream));
-    st.n_expm++;
-    const KHost r = *c.h_res;
-    const int J = r.J;
-    st.n_matvec += (J - j_sweep) - (skipped ? 1 : 0);
-    if (beta0 < 0.0) beta0 = r.beta;
-    if (!std::isfinite(r.err) || !std::isfinite(r.beta)) {
-      set_error("kiops: non-finite Krylov quantities");
-      int le = latched_error(c);
-      return le ? le : DFR_E_NONFINITE;
+    bool accept = false;
+    rc = km_decide(k, *c.h_res, o, &accept);
+    if (rc == DFR_E_NONFINITE) {
+      const int le = latched_error(c);
+      return le ? le : rc;
     }
-    bool accept;
-    double omega, tau_new;
-    int m_new;
-    if (r.happy) {
-      j = J;
-      omega = 0.0;
-      accept = true;
-      m_new = m;
-      tau_new = std::min(tau_out - (t + tau), tau);
-      st.happy = 1;
-    } else {
-      omega = (tau_out / tau) * r.err / (o.tol * beta0);
-      omega = std::max(omega, 1e-300);
-      accept = omega <= DELTA;
-      double order;
-      if (ireject >= 1 && m == old_m && tau != old_tau)
-        order = std::max(1.0, std::log(omega / old_omega) / std::log(tau / old_tau));
-      else
-        order = J / 4.0;
-      double kest;
-      if (ireject >= 1 && m != old_m && tau == old_tau)
-        kest = std::max(1.1, std::pow(omega / old_omega, 1.0 / (old_m - m)));
-      else
-        kest = 2.0;
-      const double remaining = accept ? tau_out - (t + tau) : tau_out - t;
-      double tau_opt = tau * std::pow(GAMMA / omega, 1.0 / order);
-      tau_opt = std::min(remaining, std::max(tau / 5.0, std::min(5.0 * tau, tau_opt)));
-      int m_opt = (int)std::ceil(J + std::log(omega / GAMMA) / std::log(kest));
-      m_opt = std::max(m_min, std::min(m_max, std::max((int)std::floor(0.75 * m),
-                                                        std::min(m_opt, (int)std::ceil(4.0 * m / 3.0)))));
-      if (J == m_max) {
-        if (omega > DELTA) {
-          m_new = J;
-          tau_new = tau * std::pow(GAMMA_MMAX / omega, 1.0 / order);
-          tau_new = std::min(remaining, std::max(tau / 5.0, tau_new));
-        } else {
-          m_new = m;
-          tau_new = tau_opt;
-        }
-      } else {
-        m_new = m_opt;
-        tau_new = std::min(remaining, tau);
-      }
-    }
+    if (rc) return rc;
     if (accept) {
       rc = launch_combine(&c, w);
       if (rc) return rc;
-      if (tau >= tau_out - t) t = tau_out;
-      else t = t + tau;
-      st.n_substeps++;
-      st.m_last = J;
-      j = 0;
-      ireject = 0;
-    } else {
-      ireject++;
-      st.n_rejected++;
-    }
-    old_tau = tau;
-    old_m = m;
-    old_omega = omega;
-    tau = tau_new;
-    m = m_new;
-    if (t < tau_out && !(tau > 0.0)) {
-      set_error("kiops: step size collapsed");
-      return DFR_E_KIOPS;
     }
   }
+  st = k.st;
   DFR_HIP(hipStreamSynchronize(c.stream));
   return latched_error(c);
 }
@@ -269,23 +313,12 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
 // EPI
 }  // namespace dfrsw
 
-struct epi_state {
-  dfrsw::Ctx *c;
-  int order, P, M;
-  double dt;
-  int s;
-  double eps;
-  dfr_precision prec;
-  int64_t nsteps;
-  double *q, *F, *qs, *w, *d, *jd;
-  std::vector<double *> hq, hF, R, bm;
-  std::vector<std::vector<double>> A;   // alpha_{m,i}
-};
+
 
 namespace dfrsw {
 
 // Eq. (30) and Eqs. (36)-(38): rows m = 1..M, columns i = 1..P
-static void epi_table(int order, std::vector<std::vector<double>> &A) {
+void epi_table(int order, std::vector<std::vector<double>> &A) {
   A.clear();
   switch (order) {
     case 3: A = {{0.0}, {2.0 / 3.0}}; break;
@@ -303,7 +336,26 @@ static void epi_table(int order, std::vector<std::vector<double>> &A) {
   }
 }
 
-static void add_stats(kiops_stats *acc, const KiopsRun &r) {
+// history: (q_n, F_n) becomes entry 1; q_{n+1} (in qs) becomes current
+void epi_rotate(epi_state *st, double *q_new) {
+  if (st->P > 0) {
+    double *oq = st->hq.back(), *oF = st->hF.back();
+    for (int i = st->P - 1; i > 0; --i) {
+      st->hq[i] = st->hq[i - 1];
+      st->hF[i] = st->hF[i - 1];
+    }
+    st->hq[0] = st->q;
+    st->hF[0] = st->F;
+    st->q = q_new;
+    st->qs = oq;
+    st->F = oF;
+  } else {
+    std::swap(st->q, st->qs);
+  }
+  st->nsteps++;
+}
+
+void add_stats(kiops_stats *acc, const KiopsRun &r) {
   if (!acc) return;
   acc->n_matvec += r.n_matvec;
   acc->n_substeps += r.n_substeps;
@@ -497,42 +549,27 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
     rc = launch_axpby(&c, n3, 1.0, st->q, 1.0, st->w, st->qs);
     if (rc) return rc;
   }
-  // history: (q_n, F_n) becomes entry 1; q_{n+1} becomes current
-  if (st->P > 0) {
-    double *oq = st->hq.back(), *oF = st->hF.back();
-    for (int i = st->P - 1; i > 0; --i) {
-      st->hq[i] = st->hq[i - 1];
-      st->hF[i] = st->hF[i - 1];
-    }
-    st->hq[0] = st->q;
-    st->hF[0] = st->F;
-    st->q = q_new;
-    st->qs = oq;
-    st->F = oF;
-  } else {
-    std::swap(st->q, st->qs);
-  }
-  st->nsteps++;
+  epi_rotate(st, q_new);
   if (q_out) DFR_HIP(hipMemcpyAsync(q_out, st->q, sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
   DFR_HIP(hipStreamSynchronize(c.stream));
   return latched_error(c);
 }
 
-int epi_ensemble_step(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *o, int n_workers,
-                      kiops_stats *stats) {
+int epi_step_concurrent(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *o, int n_workers,
+                        kiops_stats *stats) {
   if (n < 1 || !ctxs || !states || !o) {
-    set_error("epi_ensemble_step: invalid argument");
+    set_error("epi_step_concurrent: invalid argument");
     return DFR_E_INVAL;
   }
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i] || !states[i] || states[i]->c != &ctxs[i]->c) {
-      set_error("epi_ensemble_step: member " + std::to_string(i) + " has no matching context and state");
+      set_error("epi_step_concurrent: member " + std::to_string(i) + " has no matching context and state");
       return DFR_E_INVAL;
     }
     for (int k = 0; k < i; ++k)
       if (ctxs[k] == ctxs[i]) {
-        set_error("epi_ensemble_step: members " + std::to_string(k) + " and " + std::to_string(i) +
+        set_error("epi_step_concurrent: members " + std::to_string(k) + " and " + std::to_string(i) +
                   " share a context");
         return DFR_E_INVAL;
       }
@@ -571,7 +608,7 @@ int epi_ensemble_step(int n, dfr_ctx *const *ctxs, epi_state *const *states, con
     for (auto &t : pool) t.join();
   }
   if (first_rc.load() != 0) {
-    set_error("epi_ensemble_step: " + first_msg);
+    set_error("epi_step_concurrent: " + first_msg);
     return first_rc.load();
   }
   return DFR_OK;

@@ -80,8 +80,17 @@ def lib():
             "epi_get_state": (i, [vp, vp]),
             "epi_num_steps": (i64, [vp]),
             "epi_destroy": (i, [vp]),
-            "epi_ensemble_step": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(KiopsOpts), i,
-                                      ctypes.POINTER(KiopsStats)]),
+            "epi_step_concurrent": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(KiopsOpts), i,
+                                        ctypes.POINTER(KiopsStats)]),
+            "dfr_ensemble_create": (i, [i, ctypes.POINTER(_GridDesc), vp, ctypes.POINTER(vp)]),
+            "dfr_ensemble_destroy": (i, [vp]),
+            "dfr_ensemble_size": (i, [vp]),
+            "dfr_ensemble_member": (vp, [vp, i]),
+            "dfr_ensemble_autotune": (i, [vp, i]),
+            "epi_ensemble_create": (i, [vp, i, d, i, ctypes.POINTER(vp), d, i, ctypes.POINTER(vp)]),
+            "epi_ensemble_step": (i, [vp, vp, ctypes.POINTER(KiopsOpts), ctypes.POINTER(KiopsStats)]),
+            "epi_ensemble_get_state": (i, [vp, i, vp]),
+            "epi_ensemble_destroy": (i, [vp]),
             "dfr_set_tile": (i, [vp, i, i]),
             "dfr_get_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_get_krylov_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
@@ -101,7 +110,9 @@ def lib():
 def exported_symbols():
     return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
-            "epi_num_steps", "epi_destroy", "epi_ensemble_step", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
+            "epi_num_steps", "epi_destroy", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
+            "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
+            "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_last_error"]
 
 
@@ -262,8 +273,9 @@ def epi_step(g: Grid, st: EpiState, opts=None, q_out=None):
     return s.as_dict()
 
 
-def epi_ensemble_step(grids, states, opts=None, n_workers=8):
-    """One step of every member (grids[i], states[i]); returns per-member stats."""
+def epi_step_concurrent(grids, states, opts=None, n_workers=8):
+    """One step of every member (grids[i], states[i]), several host threads;
+    returns per-member stats."""
     opts = opts or kiops_opts()
     n = len(grids)
     if n != len(states) or n == 0:
@@ -271,8 +283,115 @@ def epi_ensemble_step(grids, states, opts=None, n_workers=8):
     ca = (ctypes.c_void_p * n)(*[g.handle for g in grids])
     sa = (ctypes.c_void_p * n)(*[s.handle for s in states])
     st = (KiopsStats * n)()
-    _check(lib().epi_ensemble_step(n, ca, sa, ctypes.byref(opts), int(n_workers), st))
+    _check(lib().epi_step_concurrent(n, ca, sa, ctypes.byref(opts), int(n_workers), st))
     return [x.as_dict() for x in st]
+
+
+class _Member(Grid):
+    """A member context owned by an ensemble (not destroyed on its own)."""
+
+    def __init__(self, handle, ne, p):
+        self.ne, self.p, self.ns = int(ne), int(p), int(p) + 1
+        self._hb = None
+        self._h = ctypes.c_void_p(handle)
+        self.N = int(lib().dfr_num_nodes(self._h))
+
+    def close(self):
+        self._h = None
+
+
+class EnsembleGrid:
+    """A dfr_ensemble: members (ne_i, p_i) built from a list of dicts with the
+    keys of Grid (ne, p, radius, omega, gravity, rotation, hB=None)."""
+
+    def __init__(self, members):
+        n = len(members)
+        self._keep = []
+        descs = (_GridDesc * n)()
+        for k, m in enumerate(members):
+            hb = m.get("hB")
+            if hb is not None:
+                hb = np.ascontiguousarray(hb, dtype=np.float64)
+                self._keep.append(hb)
+            rot = m.get("rotation", (0.0, np.pi / 4, 0.0))
+            descs[k] = _GridDesc(int(m["ne"]), int(m["p"]), float(m.get("radius", 1.0)), float(m.get("omega", 1.0)),
+                                 float(m.get("gravity", 1.0)), *map(float, rot),
+                                 None if hb is None else hb.ctypes.data_as(ctypes.c_void_p))
+        h = ctypes.c_void_p()
+        _check(lib().dfr_ensemble_create(n, descs, _stream(), ctypes.byref(h)))
+        self._h = h
+        self.members = [_Member(lib().dfr_ensemble_member(h, k), m["ne"], m["p"]) for k, m in enumerate(members)]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for m in self.members:
+                m.close()
+            lib().dfr_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EpiEnsemble:
+    def __init__(self, eg: EnsembleGrid, order, dt, q0s, startup_substeps=10, eps=1e-150, prec="fp64"):
+        self.eg = eg
+        n = len(eg.members)
+        arr = (ctypes.c_void_p * n)(*[_dev(q).value for q in q0s])
+        h = ctypes.c_void_p()
+        _check(lib().epi_ensemble_create(eg.handle, int(order), float(dt), int(startup_substeps), arr, float(eps),
+                                         _PREC[prec], ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().epi_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dfr_ensemble_create(members):
+    return EnsembleGrid(members)
+
+
+def dfr_ensemble_autotune(eg: EnsembleGrid, prec="fp64"):
+    _check(lib().dfr_ensemble_autotune(eg.handle, _PREC[prec]))
+    return [dfr_get_krylov_tile(m) for m in eg.members]
+
+
+def epi_ensemble_create(eg, order, dt, q0s, startup_substeps=10, eps=1e-150, prec="fp64"):
+    return EpiEnsemble(eg, order, dt, q0s, startup_substeps, eps, prec)
+
+
+def epi_ensemble_step(eg: EnsembleGrid, x: EpiEnsemble, opts=None):
+    """One batched EPI step of every member; returns per-member stats."""
+    opts = opts or kiops_opts()
+    n = len(eg.members)
+    st = (KiopsStats * n)()
+    _check(lib().epi_ensemble_step(eg.handle, x.handle, ctypes.byref(opts), st))
+    return [v.as_dict() for v in st]
+
+
+def epi_ensemble_get_state(x: EpiEnsemble, i, q=None):
+    q = x.eg.members[i].empty() if q is None else q
+    _check(lib().epi_ensemble_get_state(x.handle, int(i), _dev(q)))
+    return q
 
 
 def epi_get_state(st: EpiState, q=None):

@@ -367,34 +367,76 @@ def test_mixed_precision_kiops_against_fp64():
     assert err < 1e-5
 
 
-def test_ensemble_step_matches_members_run_alone():
-    # epi_ensemble_step (members on their own streams, several host threads)
-    # gives exactly what epi_step gives member by member
+def test_ensemble_forms_match_members_run_alone():
+    # the batched form (one launch per operation for all members) and the
+    # concurrent form give what epi_step gives member by member, and the
+    # members agree with the oracle
     import torch
     from paper_2101_05617_amd import dfrsw
     from paper_2101_05617_amd.ensemble import Ensemble
-    ws = [small(C0, 2, 3), small(C0, 3, 4, u_amp=1.0), small(C0, 2, 2), small(C0, 4, 4)]
+    ws = [small(C0, 2, 3), small(C0, 3, 4, u_amp=1.0), small(C0, 2, 2), small(C0, 4, 4), small(C0, 1, 5)]
     frames = [oracle.OracleGrid(w.ne, w.ns, *w.constants()).node_frames() for w in ws]
     opts = _kopts(1e-10, 24)
-    ea = Ensemble(ws, prec="fp64", own_streams=True, autotune=False, frames=frames)
-    eb = Ensemble(ws, prec="fp64", own_streams=False, autotune=False, frames=frames)
+    ref = Ensemble(ws, prec="fp64", form="sequential", autotune=False, frames=frames)
+    bat = Ensemble(ws, prec="fp64", form="batched", autotune=False, frames=frames)
+    con = Ensemble(ws, prec="fp64", form="concurrent", autotune=False, frames=frames)
     for _ in range(4):
-        sa = ea.step(opts, n_workers=3)
-        sb = eb.step_sequential(opts)
-        assert [x["n_matvec"] for x in sa] == [x["n_matvec"] for x in sb]
+        sr = ref.step(opts)
+        sb = bat.step(opts)
+        sc = con.step(opts, n_workers=3)
+        assert [x["n_matvec"] for x in sb] == [x["n_matvec"] for x in sr]
+        assert [x["n_matvec"] for x in sc] == [x["n_matvec"] for x in sr]
     for k, w in enumerate(ws):
-        a, b = ea.state(k), eb.state(k)
-        assert np.array_equal(a, b), (k, np.abs(a - b).max())
-        # and the members agree with the oracle
+        a, b, c = ref.state(k), bat.state(k), con.state(k)
+        assert np.array_equal(a, c), (k, np.abs(a - c).max())
+        eb = rel_fields(b, a, len(a) // 3)
+        record(f"ensemble_batched_vs_single_member{k}", eb)
+        assert eb <= 1e-14, (k, eb)
         G = oracle.OracleGrid(w.ne, w.ns, *w.constants())
         Q, _ = inputs.initial_state(w, *frames[k])
         E = oepi.EPI(G.rhs, lambda q, v: G.jvp(q, v), w.order, w.dt_nd, Q, startup_substeps=w.startup_substeps,
                      kiops_opts=dict(tol=1e-10, m_max=24))
         for _ in range(4):
             E.step()
-        assert rel_fields(a, E.q, G.N) < 1e-11
+        assert rel_fields(b, E.q, G.N) < 1e-11
     with pytest.raises(dfrsw.DfrError):
-        dfrsw.epi_ensemble_step([ea.grids[0], ea.grids[0]], [ea.states[0], ea.states[0]], opts, 2)
-    ea.close()
-    eb.close()
+        dfrsw.epi_step_concurrent([con.grids[0], con.grids[0]], [con.states[0], con.states[0]], opts, 2)
+    for e in (ref, bat, con):
+        e.close()
+    torch.cuda.synchronize()
+
+
+def test_batched_ensemble_mixed_precision_and_errors():
+    # FP32 products in the batched form against FP64 member by member; a bad
+    # member state is reported with the member's index
+    import torch
+    from paper_2101_05617_amd import dfrsw
+    from paper_2101_05617_amd.ensemble import Ensemble
+    ws = [small(C2, 2, 4), small(C2, 3, 5), small(C2, 2, 6)]
+    ws = [replace(w, order=4, dt_s=900.0, m_max=32) for w in ws]
+    opts = _kopts(1e-10, 32)
+    ref = Ensemble(ws, prec="fp64", form="sequential", autotune=False)
+    bat = Ensemble(ws, prec="fp32_jv", form="batched", autotune=True)
+    for _ in range(5):
+        ref.step(opts)
+        bat.step(opts)
+    for k in range(len(ws)):
+        a, b = ref.state(k), bat.state(k)
+        N = len(a) // 3
+        eh = np.linalg.norm(b[:N] - a[:N]) / np.linalg.norm(a[:N])
+        record(f"ensemble_fp32_member{k}_h", eh)
+        assert eh < 1e-6, (k, eh)
+    # a non-positive depth in member 1
+    eg = dfrsw.dfr_ensemble_create([dict(ne=w.ne, p=w.p, radius=w.constants()[0], omega=w.constants()[1],
+                                         gravity=w.constants()[2]) for w in ws])
+    qs = [torch.from_numpy(ref.state(k)).cuda() for k in range(len(ws))]
+    qs[1][5] = -1.0
+    x = dfrsw.epi_ensemble_create(eg, ws[0].order, ws[0].dt_nd, qs, prec="fp64")
+    with pytest.raises(dfrsw.DfrError) as e:
+        dfrsw.epi_ensemble_step(eg, x, opts)
+    assert e.value.code == -5 and "member 1" in str(e.value)
+    x.close()
+    eg.close()
+    for z in (ref, bat):
+        z.close()
     torch.cuda.synchronize()
