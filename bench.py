@@ -256,6 +256,57 @@ def ensemble_study(n_members, steps, n_workers):
             "simulated_days": (n_start + steps) * w0.dt_s / 86400.0}
 
 
+def c4_study(steps, reps):
+    """c4_ne120_p6_mountain (4,233,600 nodes, orography): the J*v kernel in
+    FP64 and complex FP32 (three rotating buffers, beyond the last-level
+    cache), and EPI6 with each product form: the start-up steps untimed, then
+    `steps` timed steps; relative L2 difference in h between the two forms."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    w = inputs.WORKLOADS["c4_ne120_p6_mountain"]
+    N = w.n_nodes
+    opts = dfrsw.kiops_opts(tol=w.tol, m_max=w.m_max)
+    out = {"workload": f"{w.name}: ne={w.ne}, p={w.p} ({N} nodes), Gaussian mountain, EPI6, dt={w.dt_s:g}s, "
+                       f"tol {w.tol:g}, m<={w.m_max}; {w.order - 2} start-up steps untimed, {steps} timed"}
+    finals = {}
+    for prec, eps in (("fp64", 1e-150), ("fp32_jv", 1e-20)):
+        g0 = dfrsw.Grid(w.ne, w.p, *w.constants())
+        P, B1, B2 = g0.node_frames()
+        g0.close()
+        Q, hB = inputs.initial_state(w, P, B1, B2)
+        g = dfrsw.Grid(w.ne, w.p, *w.constants(), hB=hB)
+        tile = dfrsw.dfr_autotune(g, prec)
+        q = torch.from_numpy(Q).cuda()
+        vs = [torch.randn(3 * N, dtype=torch.float64, device="cuda") * 1e-3 for _ in range(3)]
+        outs = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(3)]
+        t_jv = time_jv(g, q, vs, outs, eps, prec, reps)
+        bpn = jv_bytes_per_node(prec)
+        del vs, outs
+        st = dfrsw.epi_create(g, w.order, w.dt_nd, q, startup_substeps=w.startup_substeps, eps=eps, prec=prec)
+        for _ in range(w.order - 2):
+            dfrsw.epi_step(g, st, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nmv = 0
+        for _ in range(steps):
+            nmv += dfrsw.epi_step(g, st, opts)["n_matvec"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        finals[prec] = dfrsw.epi_get_state(st).cpu().numpy()
+        out[prec] = {"tile": tile, "jv_us": t_jv * 1e3, "jv_per_s": 1e3 / t_jv,
+                     "jv_GBs": bpn * N / (t_jv * 1e-3) / 1e9, "jv_frac_hbm": bpn * N / (t_jv * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "epi6_steps_per_s": steps / dt, "jv_per_step": nmv / steps,
+                     "sim_days_per_wall_hour": (steps * w.dt_s / 86400.0) / (dt / 3600.0)}
+        log(f"c4 {prec}: J*v {t_jv * 1e3:.1f} us, {steps} EPI6 steps in {dt:.2f}s")
+        del st, g, q
+        torch.cuda.synchronize()
+    a, b = finals["fp32_jv"], finals["fp64"]
+    out["rel_l2_error_h_fp32_vs_fp64"] = float(np.linalg.norm(a[:N] - b[:N]) / np.linalg.norm(b[:N]))
+    return out
+
+
 def cpu_baseline_leg(workload_name):
     """Time the oracle on this host: one steady-state EPI step after the
     start-up steps (untimed, one EPI2 sub-step each)."""
@@ -320,6 +371,8 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the ne=60, p=6 J*v roofline figures")
     ap.add_argument("--no-mixed", action="store_true", help="skip the ne=60, p=6 mixed-precision EPI6 day")
     ap.add_argument("--mixed-steps", type=int, default=72)
+    ap.add_argument("--no-c4", action="store_true", help="skip the ne=120, p=6 mountain figures")
+    ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member ensemble comparison")
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
@@ -505,6 +558,10 @@ def main():
     # FP64 Krylov / EPI6 machinery against the plain FP64 path, one simulated day
     if not args.no_mixed:
         out["mixed_c2"] = mixed_study(args.mixed_steps)
+
+    # ---- the largest grid (ne = 120, p = 6, orography)
+    if not args.no_c4:
+        out["c4_ne120_p6"] = c4_study(args.c4_steps, 50)
 
     # ---- the ensemble workload: batched mixed form against plain FP64 one
     # member after another

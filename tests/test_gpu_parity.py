@@ -34,6 +34,7 @@ pytestmark = pytest.mark.gpu
 C0 = inputs.WORKLOADS["c0_ne4_p4"]
 C1 = inputs.WORKLOADS["c1_ne30_p5"]
 C2 = inputs.WORKLOADS["c2_ne60_p6_jet"]
+C4 = inputs.WORKLOADS["c4_ne120_p6_mountain"]
 
 # (ne, p): single-element panels, every supported degree, ragged last blocks
 GRIDS = [(1, 1), (2, 2), (3, 4), (4, 4), (2, 5), (3, 6), (5, 6), (2, 7), (3, 3)]
@@ -265,6 +266,26 @@ def test_c1_full_size_rhs_jvp_parity():
     assert rel_fields(got, ref, G.N) < 1e-12
     got32 = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
     record("c1_jvp_fp32", rel_fields(got32, ref, G.N))
+    assert rel_fields(got32, ref, G.N) < 2e-5
+
+
+def test_c4_full_size_rhs_jvp_parity():
+    # ne = 120, p = 6 (4,233,600 nodes), Gaussian mountain (orography): every
+    # element of F and J v, FP64 and complex-FP32, in the autotuned tiles
+    G, D, Q = pair(C4)
+    from paper_2101_05617_amd import dfrsw
+    dfrsw.dfr_autotune(D, "fp64")
+    e_rhs = rel_fields(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G.rhs(Q), G.N)
+    record("c4_rhs_fp64", e_rhs)
+    assert e_rhs < rhs_bar(G, Q)
+    V = inputs.random_direction(3 * G.N, 41)
+    ref = G.jvp(Q, V)
+    got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V)))
+    record("c4_jvp_fp64", rel_fields(got, ref, G.N))
+    assert rel_fields(got, ref, G.N) < 1e-12
+    dfrsw.dfr_autotune(D, "fp32_jv")
+    got32 = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
+    record("c4_jvp_fp32", rel_fields(got32, ref, G.N))
     assert rel_fields(got32, ref, G.N) < 2e-5
 
 
