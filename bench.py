@@ -377,6 +377,8 @@ def main():
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
     ap.add_argument("--ensemble-workers", type=int, default=8)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline EPI run of --workload and its J*v figures (for profiling)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--jv-only", action="store_true",
                     help="only time the plain complex-step J*v kernel of --workload (for profiling)")
@@ -392,6 +394,8 @@ def main():
 
     if args.summarize_profile:
         return summarize_profile(args)
+    if args.headline_only:
+        args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_cpu_baseline = True
 
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)

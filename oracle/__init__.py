@@ -70,6 +70,9 @@ def lib():
         L.orc_panel_angles.argtypes = [d, d, d, vp, vp, vp]
         L.orc_appc_matrix.argtypes = [ctypes.c_int, ctypes.c_int, d, vp]
         L.orc_connectivity.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.orc_ausm_split.argtypes = [d, vp, vp, vp, vp]
+        L.orc_common_flux.argtypes = [vp, vp, vp, d, vp, ctypes.c_int, vp]
+        L.orc_set_riemann.argtypes = [vp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -93,10 +96,13 @@ def _check(rc):
 
 class OracleGrid:
     """One rotated cubed-sphere DFR discretisation (ne elements per panel edge,
-    ns = p+1 Gauss-Legendre points per element edge)."""
+    ns = p+1 Gauss-Legendre points per element edge).  riemann: "rusanov"
+    (Sec. 3.1) or "ausm" (App. D) for the common flux at element faces."""
+
+    RIEMANN = {"rusanov": 0, "ausm": 1}
 
     def __init__(self, ne, ns, radius=1.0, omega=1.0, gravity=1.0,
-                 rotation=(0.0, np.pi / 4, 0.0), hB=None):
+                 rotation=(0.0, np.pi / 4, 0.0), hB=None, riemann="rusanov"):
         self.ne, self.ns = int(ne), int(ns)
         self.radius, self.omega, self.gravity = float(radius), float(omega), float(gravity)
         self.rotation = tuple(float(r) for r in rotation)
@@ -111,6 +117,8 @@ class OracleGrid:
             raise OracleError("orc_create failed")
         self._h = h
         self.N = int(L.orc_num_nodes(h))
+        self.riemann = riemann
+        L.orc_set_riemann(h, self.RIEMANN[riemann])
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -163,6 +171,16 @@ class OracleGrid:
         lib().orc_get_operators(self._h, _ptr(xi), _ptr(w), _ptr(lm), _ptr(lp), _ptr(Dt))
         return xi, w, lm, lp, Dt
 
+    def common_flux(self, qL, qR, sg, h, n):
+        """The grid's common flux sqrt(g) T^{mu n} at one face point from real
+        tensor densities qL (low side) and qR (high side); h: 2x2 h^{ij}."""
+        qL = np.ascontiguousarray(qL, dtype=np.float64)
+        qR = np.ascontiguousarray(qR, dtype=np.float64)
+        h4 = np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(4))
+        F = np.empty(3)
+        lib().orc_common_flux(self._h, _ptr(qL), _ptr(qR), float(sg), _ptr(h4), int(n), _ptr(F))
+        return F
+
     def panels(self):
         out = np.empty(18)
         lib().orc_get_panels(self._h, _ptr(out))
@@ -173,6 +191,13 @@ def panel_angles(l0, f0, a0):
     lam, phi, alp = np.empty(6), np.empty(6), np.empty(6)
     lib().orc_panel_angles(l0, f0, a0, _ptr(lam), _ptr(phi), _ptr(alp))
     return lam, phi, alp
+
+
+def ausm_split(M):
+    """AUSM split functions at a real Froude number M: (M+, M-, P+/P, P-/P)."""
+    out = [ctypes.c_double() for _ in range(4)]
+    lib().orc_ausm_split(float(M), *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)
 
 
 def appc_matrix(dst, src, s):

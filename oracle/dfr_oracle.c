@@ -17,6 +17,8 @@
  *   - tensor-product extension .................... Sec. 3.2
  *   - Riemann solver: Rusanov (named in Sec. 3.1); wave speeds from
  *     the flux-Jacobian eigenvalues ............... App. E, Eqs. (147)-(148)
+ *   - Riemann solver: AUSM with double Froude-number
+ *     splitting (the paper's choice) .............. App. D, Eqs. (136)-(143)
  *   - metric terms, Christoffel symbols ........... App. B, Eqs. (59)-(80)
  *   - rotated panel angles ....................... App. B, Eqs. (81)-(95)
  *   - panel-interface vector relations ........... App. C, Eqs. (100)-(135)
@@ -44,6 +46,18 @@
  *   R6  Panel connectivity and edge orientation are those of the unrotated
  *       layout implied by App. B/C (panels 0-3 equatorial west->east,
  *       4 north, 5 south); rotation does not change them.
+ *   A1  AUSM split functions (App. D defers them to the original AUSM of
+ *       Liou and Steffen, J. Comput. Phys. 107, 1993): the Froude-number
+ *       split M^+- = +-(M +- 1)^2/4 for |M| <= 1, (M +- |M|)/2 otherwise,
+ *       and the pressure weights P^+- / P = (M +- 1)^2 (2 -+ M)/4 for
+ *       |M| <= 1, (1 +- sign M)/2 otherwise (the cubic form of that paper).
+ *   A2  The "+" parts are taken on the low-coordinate side of the face and
+ *       the "-" parts on the high side, each with its own Froude number
+ *       M = u^n / a^n and gravity-wave speed a^n = sqrt(h^nn g_r H) (App. E).
+ *   A3  Branches (|M| <= 1, sign M, max/min of Eqs. 142-143) follow the real
+ *       evaluation, as in R3; when the split Froude number is exactly zero
+ *       the advective part is taken from the low side.
+ *   A4  The pressure component of the mass flux vanishes (h^{0n} = 0).
  */
 #include <complex.h>
 #include <math.h>
@@ -67,6 +81,7 @@ typedef struct orc_grid {
   double Dt[ORC_MAXNS][ORC_MAXNS + 2];          /* l~'_n(xi_k), Eq. (13) */
   double Dgl[ORC_MAXNS][ORC_MAXNS];             /* l'_k(xi_m) on GL points (R5) */
   double *dhb;                                  /* NULL or 2*N: dh_B/dx^1, dh_B/dx^2 */
+  int riemann;                                  /* 0: Rusanov, 1: AUSM */
 } orc_grid;
 
 /* ------------------------------------------------------------------------ */
@@ -449,6 +464,86 @@ static void rusanov(const orc_grid *G, const cplx qL[3], const cplx qR[3], doubl
   for (int m = 0; m < 3; ++m) Fs[m] = 0.5 * (FL[m] + FR[m]) - 0.5 * lam * (qR[m] - qL[m]);
 }
 
+/* AUSM split functions of the Froude number and of the pressure weight      */
+/* (reading A1), on a real M.                                                */
+void orc_ausm_split(double M, double *Mp, double *Mm, double *Pp, double *Pm) {
+  if (fabs(M) <= 1.0) {
+    *Mp = 0.25 * (M + 1.0) * (M + 1.0);
+    *Mm = -0.25 * (M - 1.0) * (M - 1.0);
+    *Pp = 0.25 * (M + 1.0) * (M + 1.0) * (2.0 - M);
+    *Pm = 0.25 * (M - 1.0) * (M - 1.0) * (2.0 + M);
+  } else {
+    *Mp = 0.5 * (M + fabs(M));
+    *Mm = 0.5 * (M - fabs(M));
+    *Pp = M > 0.0 ? 1.0 : 0.0;
+    *Pm = M > 0.0 ? 0.0 : 1.0;
+  }
+}
+
+/* The same split on a complex M whose real part Mr (computed in real         */
+/* arithmetic, reading A3) picks the branch: "+" parts (low side) or "-".      */
+static void ausm_split_c(cplx M, double Mr, int plus, cplx *Ms, cplx *Ps) {
+  if (fabs(Mr) <= 1.0) {
+    if (plus) { *Ms = 0.25 * (M + 1.0) * (M + 1.0); *Ps = 0.25 * (M + 1.0) * (M + 1.0) * (2.0 - M); }
+    else { *Ms = -0.25 * (M - 1.0) * (M - 1.0); *Ps = 0.25 * (M - 1.0) * (M - 1.0) * (2.0 + M); }
+  } else if (Mr > 0.0) {
+    *Ms = plus ? M : 0.0;
+    *Ps = plus ? 1.0 : 0.0;
+  } else {
+    *Ms = plus ? 0.0 : M;
+    *Ps = plus ? 0.0 : 1.0;
+  }
+}
+
+/* AUSM common flux with double Froude-number splitting, Eqs. (137)-(143):   */
+/* sqrt(g) T^{mu n} = M^n A^{mu n} + P^{mu n}, A^{mu n} = q^mu a^n,            */
+/* P^{mu n} = g_r h^{mu n} (q^0)^2 / (2 sqrt g).  qL: low side ("+"), qR:      */
+/* high side ("-"), both in the receiving panel's basis.                      */
+static void ausm(const orc_grid *G, const cplx qL[3], const cplx qR[3], double sg, const double h[2][2], int n, cplx Fs[3]) {
+  cplx HL = qL[0] / sg, HR = qR[0] / sg;
+  cplx aL = csqrt(h[n][n] * G->g * HL), aR = csqrt(h[n][n] * G->g * HR);   /* App. E */
+  cplx ML = (qL[1 + n] / qL[0]) / aL, MR = (qR[1 + n] / qR[0]) / aR;
+  double MLr = (creal(qL[1 + n]) / creal(qL[0])) / sqrt(h[n][n] * G->g * (creal(qL[0]) / sg));
+  double MRr = (creal(qR[1 + n]) / creal(qR[0])) / sqrt(h[n][n] * G->g * (creal(qR[0]) / sg));
+  cplx Mp, Mm, Pp, Pm;
+  ausm_split_c(ML, MLr, 1, &Mp, &Pp);
+  ausm_split_c(MR, MRr, 0, &Mm, &Pm);
+  double sL[4], sR[4];                 /* real splits: M+, M-, P+, P- */
+  orc_ausm_split(MLr, &sL[0], &sL[1], &sL[2], &sL[3]);
+  orc_ausm_split(MRr, &sR[0], &sR[1], &sR[2], &sR[3]);
+  cplx m = Mp + Mm;                    /* Eq. (138) on the two sides */
+  double mr = sL[0] + sR[1];
+  for (int mu = 0; mu < 3; ++mu) {
+    cplx AL = qL[mu] * aL, AR = qR[mu] * aR;
+    cplx PL = 0.0, PR = 0.0;
+    if (mu > 0) {
+      PL = G->g * h[mu - 1][n] * qL[0] * qL[0] / (2.0 * sg);
+      PR = G->g * h[mu - 1][n] * qR[0] * qR[0] / (2.0 * sg);
+    }
+    /* Eqs. (140)-(143): max[0, m] A^+ + min[0, m] A^- + P^+ + P^- */
+    cplx adv = mr >= 0.0 ? m * AL : m * AR;
+    Fs[mu] = adv + Pp * PL + Pm * PR;
+  }
+}
+
+/* Common flux of the grid's Riemann solver; qL on the low side.             */
+static void common_flux(const orc_grid *G, const cplx qL[3], const cplx qR[3], double sg, const double h[2][2], int n, cplx Fs[3]) {
+  if (G->riemann == 1) ausm(G, qL, qR, sg, h, n, Fs);
+  else rusanov(G, qL, qR, sg, h, n, Fs);
+}
+
+/* Real common flux at one face point, for the tests: qL, qR tensor          */
+/* densities, h4 = (h^11, h^12, h^21, h^22), n the normal direction.          */
+void orc_common_flux(const orc_grid *G, const double *qL, const double *qR, double sg, const double *h4, int n, double *F) {
+  cplx a[3], b[3], Fs[3];
+  double h[2][2] = { { h4[0], h4[1] }, { h4[2], h4[3] } };
+  for (int k = 0; k < 3; ++k) { a[k] = qL[k]; b[k] = qR[k]; }
+  common_flux(G, a, b, sg, h, n, Fs);
+  for (int k = 0; k < 3; ++k) F[k] = creal(Fs[k]);
+}
+
+void orc_set_riemann(orc_grid *G, int solver) { G->riemann = solver; }
+
 /* Common flux on face `edge` of element (p,ej,ei) at face point t, in the    */
 /* element's own coordinates.                                                */
 static void face_flux(const orc_grid *G, const cplx *Q, int p, int ej, int ei, int edge, int t, cplx Fs[3]) {
@@ -512,8 +607,8 @@ static void face_flux(const orc_grid *G, const cplx *Q, int p, int ej, int ei, i
   cplx qo[3], qn[3];
   for (int f = 0; f < 3; ++f) { qo[f] = m.sg * own[f]; qn[f] = m.sg * nbv[f]; }
   int n = (edge == EW || edge == EE) ? 0 : 1;
-  if (edge == EW || edge == ES) rusanov(G, qn, qo, m.sg, h, n, Fs);
-  else rusanov(G, qo, qn, m.sg, h, n, Fs);
+  if (edge == EW || edge == ES) common_flux(G, qn, qo, m.sg, h, n, Fs);
+  else common_flux(G, qo, qn, m.sg, h, n, Fs);
 }
 
 /* Complex right-hand side dQ/dt = F(Q) for Q = (H, H u^1, H u^2).           */
