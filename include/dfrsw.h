@@ -111,18 +111,32 @@ int dfr_get_tile(const dfr_ctx *ctx, int *tile_tx, int *tile_ty);
 int dfr_get_krylov_tile(const dfr_ctx *ctx, int *tile_tx, int *tile_ty);
 int dfr_autotune(dfr_ctx *ctx, dfr_precision prec, int *tile_tx, int *tile_ty);
 
+/* Common flux at element faces (the Riemann problem of Sec. 3.1).
+ * DFR_RUSANOV (default): local Lax-Friedrichs with the largest wave speed of
+ * Eqs. (147)-(148) of the two sides.  DFR_AUSM: the AUSM flux with double
+ * Froude-number splitting of App. D, Eqs. (137)-(143), with the split
+ * functions of the original AUSM (Liou and Steffen 1993; cubic pressure
+ * weights) and the gravity-wave speeds of App. E.  The setting belongs to the
+ * context and applies to every later call on it (F, J*v, KIOPS, EPI, the
+ * concurrent ensemble form).  The batched ensemble form carries the Rusanov
+ * flux only: its calls return DFR_E_INVAL, naming the member, if a member
+ * context is set to another.  DFR_E_INVAL for an unknown solver. */
+typedef enum { DFR_RUSANOV = 0, DFR_AUSM = 1 } dfr_riemann;
+int dfr_set_riemann(dfr_ctx *ctx, int solver);
+int dfr_get_riemann(const dfr_ctx *ctx, int *solver);
+
 /* dqdt = F(q): the DFR right-hand side of the covariant shallow-water
  * equations, Eqs. (1)-(2) with the flux reconstruction of Eqs. (10)-(14),
- * Rusanov interface fluxes with the wave speeds of Eqs. (147)-(148), panel
- * interfaces per App. C.  q, dqdt: device, 3N doubles each, may not alias. */
+ * the context's interface fluxes (dfr_set_riemann), panel interfaces per
+ * App. C.  q, dqdt: device, 3N doubles each, may not alias. */
 int dfr_rhs(dfr_ctx *ctx, const double *q, double *dqdt);
 
 /* jv = Im F(q + i eps v) / eps (Eq. 28), one complex evaluation of the same
  * right-hand side.  prec = DFR_FP64: complex FP64.  prec = DFR_FP32_JV: the
  * complex evaluation runs in FP32 on FP32 roundings of q and v (eps must
  * keep eps*|v| far above 1e-38 on the caller's scale); jv is written in FP64.
- * Branches of |.| and max(.,.) in the Rusanov flux are those of the real
- * evaluation at q.  q, v, jv: device, 3N doubles; jv may not alias q or v. */
+ * Branches of the interface flux (|.|, max(.,.), the AUSM split ranges)
+ * are those of the real evaluation at q.  q, v, jv: device, 3N doubles; jv may not alias q or v. */
 int dfr_jvp_complex_step(dfr_ctx *ctx, const double *q, const double *v, double eps,
                          dfr_precision prec, double *jv);
 

@@ -646,6 +646,21 @@ int dfr_set_tile(dfr_ctx *h, int tx, int ty) {
   return DFR_E_INVAL;
 }
 
+int dfr_set_riemann(dfr_ctx *h, int solver) {
+  if (!h || (solver != DFR_RUSANOV && solver != DFR_AUSM)) {
+    set_error("dfr_set_riemann: solver must be DFR_RUSANOV or DFR_AUSM");
+    return DFR_E_INVAL;
+  }
+  h->c.ga.riemann = solver;
+  return DFR_OK;
+}
+
+int dfr_get_riemann(const dfr_ctx *h, int *solver) {
+  if (!h || !solver) return DFR_E_INVAL;
+  *solver = h->c.ga.riemann;
+  return DFR_OK;
+}
+
 int dfr_get_tile(const dfr_ctx *h, int *tx, int *ty) {
   if (!h || !tx || !ty) return DFR_E_INVAL;
   *tx = h->c.tile_tx;

@@ -72,9 +72,16 @@ static DfrCall make_call(dfr_ensemble &E, int i, bool arnoldi, const void *q, co
   return d;
 }
 
-// one launch per (number of GL points) group of the calls
+// one launch per (number of GL points) group of the calls; the batched
+// kernels carry the Rusanov flux only
 static int launch_dfr_groups(dfr_ensemble &E, const std::vector<int> &member, std::vector<DfrCall> &calls, bool cs,
                              bool fp32, bool arnoldi) {
+  for (int m : member)
+    if (E.mem[m]->c.ga.riemann != DFR_RUSANOV) {
+      set_error("member " + std::to_string(m) + ": the batched ensemble form uses the Rusanov flux "
+                "(epi_step_concurrent runs members with other fluxes)");
+      return DFR_E_INVAL;
+    }
   for (int ns = 2; ns <= MAX_NS; ++ns) {
     std::vector<DfrCall> grp;
     for (size_t k = 0; k < calls.size(); ++k)

@@ -56,6 +56,7 @@ struct GridArgs {
   const double *xform;    // [6][4][ne*ns][4]: own <- neighbour contravariant map at panel edges
   const double *orog;     // NULL or [2][N]: (g/a^2) (h^{i1} dhB_1 + h^{i2} dhB_2) * a^2 ... per node
   int *err_flag;          // latched kernel error (vector atomics only)
+  int riemann;            // common flux at element faces: 0 Rusanov, 1 AUSM
 };
 
 // Optional Arnoldi prologue/epilogue of the J*v kernel (one KIOPS iteration).

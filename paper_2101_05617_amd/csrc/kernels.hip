@@ -258,6 +258,53 @@ __device__ __forceinline__ void side_flux1(cx<T> H, cx<T> M1, cx<T> M2, cx<T> Mn
   c = au + csqrt1((eta_nn * gred) * H);
 }
 
+// AUSM common flux with double Froude-number splitting (App. D, Eqs.
+// 137-143) per unit sqrt(g)/a^2: sqrt(g) T^{mu n} = M^n A^{mu n} + P^{mu n}
+// with A^{mu n} = q^mu a^n, a^n = sqrt(h^nn g H) (App. E), P^{0n} = 0 and
+// P^{in} = g h^{in} H^2 / 2 (per unit sqrt(g)).  The split functions are the
+// original AUSM's (Liou and Steffen 1993): for |M| <= 1, M+- = +-(M +- 1)^2/4
+// and pressure weights (M +- 1)^2 (2 -+ M)/4; beyond, the upwind values.
+// "+" parts come from the low side L, "-" parts from the high side R; every
+// branch follows the real parts, and a split Froude number of exactly zero
+// takes the advective part from L.
+template <typename T>
+__device__ __forceinline__ void ausm_flux(cx<T> HL, cx<T> L1, cx<T> L2, cx<T> HR, cx<T> R1, cx<T> R2, int n,
+                                          T eta1n, T eta2n, T etann, T gred, cx<T> &F0, cx<T> &F1, cx<T> &F2) {
+  const cx<T> one{T(1), T(0)};
+  // low side: Froude number, wave speed, "+" splits
+  const cx<T> aL = csqrt1((etann * gred) * HL);
+  const cx<T> ML = cmul1(cmul1(n == 0 ? L1 : L2, crcp1(HL)), crcp1(aL));
+  cx<T> Mp, Wp;
+  if (ML.r > T(1)) { Mp = ML; Wp = one; }
+  else if (ML.r < T(-1)) { Mp = cx<T>{T(0), T(0)}; Wp = cx<T>{T(0), T(0)}; }
+  else {
+    const cx<T> s = ML + one;
+    Mp = T(0.25) * cmul1(s, s);
+    Wp = cmul1(Mp, T(2) * one - ML);
+  }
+  // high side: "-" splits
+  const cx<T> aR = csqrt1((etann * gred) * HR);
+  const cx<T> MR = cmul1(cmul1(n == 0 ? R1 : R2, crcp1(HR)), crcp1(aR));
+  cx<T> Mm, Wm;
+  if (MR.r < T(-1)) { Mm = MR; Wm = one; }
+  else if (MR.r > T(1)) { Mm = cx<T>{T(0), T(0)}; Wm = cx<T>{T(0), T(0)}; }
+  else {
+    const cx<T> s = MR - one;
+    Mm = T(-0.25) * cmul1(s, s);
+    Wm = cmul1(-Mm, T(2) * one + MR);
+  }
+  const cx<T> m = Mp + Mm;   // Eq. (138) across the face
+  // Eqs. (140)-(143): max[0, m] A^+ + min[0, m] A^- + P^+ + P^-
+  const bool low = m.r >= T(0);
+  const cx<T> a = low ? aL : aR;
+  const cx<T> ma = cmul1(m, a);
+  const cx<T> PL = (T(0.5) * gred) * cmul1(HL, HL), PR = (T(0.5) * gred) * cmul1(HR, HR);
+  const cx<T> wP = cmul1(Wp, PL), wQ = cmul1(Wm, PR);
+  F0 = cmul1(ma, low ? HL : HR);
+  F1 = cmul1(ma, low ? L1 : R1) + eta1n * (wP + wQ);
+  F2 = cmul1(ma, low ? L2 : R2) + eta2n * (wP + wQ);
+}
+
 // ---------------------------------------------------------------------------
 // The fused DFR kernel.  A block takes a tile of TX x TY elements of one panel
 // (TX, TY divide ne), one thread per GL node.
@@ -319,7 +366,7 @@ __device__ __forceinline__ T lin(cx<T> z) {
 // The kernel body: tile `lb` (0 <= lb < 6 (ne/TX)(ne/TY)) of the grid
 // described by g.  Its partial inner products (Krylov form) go to
 // ar.pout[2 lb], ar.pout[2 lb + 1]; tile 0 records the prologue's values.
-template <int NS, typename T, typename TQ, bool CS, bool AR>
+template <int NS, typename T, typename TQ, bool CS, bool AR, int RS>
 __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, const int TX, const int TY, const int lb,
                                          const TQ *__restrict__ q, const double *__restrict__ v,
                                          const double *__restrict__ vscale, double eps, double *__restrict__ out,
@@ -644,15 +691,23 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     const T sg = ax * ay * rd * rd * rd;
     const T e11 = d2 * rax, e22 = d2 * ray, e12 = X * Y * e11 * ray;
     const T eta1n = n == 0 ? e11 : e12, eta2n = n == 0 ? e12 : e22, etann = n == 0 ? e11 : e22;
-    cx<T> fL0, fL1, fL2, fR0, fR1, fR2, cL, cR;
-    side_flux1(HL, L1, L2, n == 0 ? L1 : L2, eta1n, eta2n, etann, gred, fL0, fL1, fL2, cL);
-    side_flux1(HR, R1, R2, n == 0 ? R1 : R2, eta1n, eta2n, etann, gred, fR0, fR1, fR2, cR);
-    const cx<T> lam = (cL.r >= cR.r) ? cL : cR;
-    const T hs = T(0.5) * sg;
     T *cf = Fl + task * 3;
-    cf[0] = hs * lin<T, CS>((fL0 + fR0) - cmul1(lam, HR - HL));
-    cf[1] = hs * lin<T, CS>((fL1 + fR1) - cmul1(lam, R1 - L1));
-    cf[2] = hs * lin<T, CS>((fL2 + fR2) - cmul1(lam, R2 - L2));
+    if constexpr (RS == 1) {   // AUSM
+      cx<T> F0, F1, F2;
+      ausm_flux(HL, L1, L2, HR, R1, R2, n, eta1n, eta2n, etann, gred, F0, F1, F2);
+      cf[0] = sg * lin<T, CS>(F0);
+      cf[1] = sg * lin<T, CS>(F1);
+      cf[2] = sg * lin<T, CS>(F2);
+    } else {
+      cx<T> fL0, fL1, fL2, fR0, fR1, fR2, cL, cR;
+      side_flux1(HL, L1, L2, n == 0 ? L1 : L2, eta1n, eta2n, etann, gred, fL0, fL1, fL2, cL);
+      side_flux1(HR, R1, R2, n == 0 ? R1 : R2, eta1n, eta2n, etann, gred, fR0, fR1, fR2, cR);
+      const cx<T> lam = (cL.r >= cR.r) ? cL : cR;
+      const T hs = T(0.5) * sg;
+      cf[0] = hs * lin<T, CS>((fL0 + fR0) - cmul1(lam, HR - HL));
+      cf[1] = hs * lin<T, CS>((fL1 + fR1) - cmul1(lam, R1 - L1));
+      cf[2] = hs * lin<T, CS>((fL2 + fR2) - cmul1(lam, R2 - L2));
+    }
   }
   __syncthreads();
 
@@ -703,8 +758,10 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
 }
 
 // one grid: the logical blocks are its tiles (XCD-aware order), the grid
-// rounded up to whole groups of eight workgroups
-template <int NS, typename T, typename TQ, bool CS, bool AR>
+// rounded up to whole groups of eight workgroups; RS: the common flux
+// (0 Rusanov, 1 AUSM), a template argument so that each kernel keeps the
+// registers of its own flux
+template <int NS, typename T, typename TQ, bool CS, bool AR, int RS>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
                                                                const int TY, const TQ *__restrict__ q,
                                                                const double *__restrict__ v,
@@ -712,11 +769,11 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
                                                                double *__restrict__ out, const ArnoldiArgs ar) {
   const int lb = (int)logical_block(6 * (g.ne / TX) * (g.ne / TY));
   if (lb < 0) return;   // uniform: padding workgroup of the XCD mapping
-  dfr_body<NS, T, TQ, CS, AR>(g, ops, TX, TY, lb, q, v, vscale, eps, out, ar);
+  dfr_body<NS, T, TQ, CS, AR, RS>(g, ops, TX, TY, lb, q, v, vscale, eps, out, ar);
 }
 
 // several grids (ensemble members) in one launch: member m owns the logical
-// blocks [b0, b0 + ntiles)
+// blocks [b0, b0 + ntiles); Rusanov fluxes
 template <int NS, typename T, typename TQ, bool CS, bool AR>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCall *__restrict__ calls, int ncalls,
                                                                      int nlogical) {
@@ -729,8 +786,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCal
   }
   __syncthreads();
   const DfrCall &c = calls[s_m];
-  dfr_body<NS, T, TQ, CS, AR>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q), c.v,
-                              c.vscale, c.eps, c.out, c.ar);
+  dfr_body<NS, T, TQ, CS, AR, 0>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q), c.v,
+                                 c.vscale, c.eps, c.out, c.ar);
 }
 
 // ---------------------------------------------------------------------------
@@ -1239,16 +1296,25 @@ static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale
   const size_t lds = (size_t)dfr_lds_layout(NS, tx, ty, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T);
   const int threads = std::max(256, ((tx * ty * NS * NS + 63) / 64) * 64);
   const int64_t nb = dfr_grid_blocks(c, ar.on != 0);
-  dfr_launch(c, !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV), (dfr_kernel<NS, T, TQ, CS, AR>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
+  const int kind = !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV);
+  if (c->ga.riemann == DFR_AUSM)
+    dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 1>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
+  else
+    dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 0>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
 }
 
 template <int NS>
 static int set_lds_attr(size_t bytes) {
-  const void *fns[] = {(const void *)dfr_kernel<NS, double, double, false, false>,
-                       (const void *)dfr_kernel<NS, double, double, true, false>,
-                       (const void *)dfr_kernel<NS, float, float, true, false>,
-                       (const void *)dfr_kernel<NS, double, double, true, true>,
-                       (const void *)dfr_kernel<NS, float, float, true, true>,
+  const void *fns[] = {(const void *)dfr_kernel<NS, double, double, false, false, 0>,
+                       (const void *)dfr_kernel<NS, double, double, true, false, 0>,
+                       (const void *)dfr_kernel<NS, float, float, true, false, 0>,
+                       (const void *)dfr_kernel<NS, double, double, true, true, 0>,
+                       (const void *)dfr_kernel<NS, float, float, true, true, 0>,
+                       (const void *)dfr_kernel<NS, double, double, false, false, 1>,
+                       (const void *)dfr_kernel<NS, double, double, true, false, 1>,
+                       (const void *)dfr_kernel<NS, float, float, true, false, 1>,
+                       (const void *)dfr_kernel<NS, double, double, true, true, 1>,
+                       (const void *)dfr_kernel<NS, float, float, true, true, 1>,
                        (const void *)dfr_kernel_batch<NS, double, double, false, false>,
                        (const void *)dfr_kernel_batch<NS, double, double, true, false>,
                        (const void *)dfr_kernel_batch<NS, float, float, true, false>,

@@ -92,6 +92,8 @@ def lib():
             "epi_ensemble_get_state": (i, [vp, i, vp]),
             "epi_ensemble_destroy": (i, [vp]),
             "dfr_set_tile": (i, [vp, i, i]),
+            "dfr_set_riemann": (i, [vp, i]),
+            "dfr_get_riemann": (i, [vp, ctypes.POINTER(i)]),
             "dfr_get_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_get_krylov_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_autotune": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
@@ -112,7 +114,7 @@ def exported_symbols():
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
             "epi_num_steps", "epi_destroy", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
-            "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
+            "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_last_error"]
 
 
@@ -227,6 +229,21 @@ class EpiState:
 
 
 KERNEL_KINDS = {"jv_arnoldi": 0, "jv": 1, "rhs": 2, "update": 3, "expm": 4, "other": 5, "finalize": 6}
+
+
+RIEMANN = {"rusanov": 0, "ausm": 1}
+
+
+def dfr_set_riemann(g, solver):
+    """Common flux at element faces of the grid (or ensemble member):
+    "rusanov" or "ausm"."""
+    _check(lib().dfr_set_riemann(g.handle, RIEMANN[solver]))
+
+
+def dfr_get_riemann(g):
+    r = ctypes.c_int()
+    _check(lib().dfr_get_riemann(g.handle, ctypes.byref(r)))
+    return {v: k for k, v in RIEMANN.items()}[r.value]
 
 
 def dfr_set_tile(g: Grid, tx, ty):

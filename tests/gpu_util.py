@@ -16,17 +16,20 @@ def torch_dev():
     return torch
 
 
-def pair(w, hB=None, rotation=inputs.ROTATION):
-    """(oracle grid, library grid, Q as numpy) for workload w."""
+def pair(w, hB=None, rotation=inputs.ROTATION, riemann="rusanov"):
+    """(oracle grid, library grid, Q as numpy) for workload w, both with the
+    given interface flux."""
     from paper_2101_05617_amd import dfrsw
-    G = oracle.OracleGrid(w.ne, w.ns, *w.constants(), rotation=rotation)
+    G = oracle.OracleGrid(w.ne, w.ns, *w.constants(), rotation=rotation, riemann=riemann)
     P, B1, B2 = G.node_frames()
     Q, hb = inputs.initial_state(w, P, B1, B2)
     if hB is None:
         hB = hb
     if hB is not None:
-        G = oracle.OracleGrid(w.ne, w.ns, *w.constants(), rotation=rotation, hB=hB)
+        G = oracle.OracleGrid(w.ne, w.ns, *w.constants(), rotation=rotation, hB=hB, riemann=riemann)
     D = dfrsw.Grid(w.ne, w.p, *w.constants(), rotation=rotation, hB=hB)
+    if riemann != "rusanov":
+        dfrsw.dfr_set_riemann(D, riemann)
     return G, D, Q
 
 
