@@ -307,6 +307,64 @@ def c4_study(steps, reps):
     return out
 
 
+def ausm_study(steps, reps):
+    """The AUSM interface flux (App. D): the FP64 J*v kernel at ne = 60, p = 6
+    (eight rotating buffers, beyond the last-level cache) and EPI5 at
+    ne = 30, p = 5 (start-up untimed, then `steps` timed steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    out = {}
+    w2 = inputs.WORKLOADS["c2_ne60_p6_jet"]
+    g2 = dfrsw.Grid(w2.ne, w2.p, *w2.constants())
+    dfrsw.dfr_set_riemann(g2, "ausm")
+    tile = dfrsw.dfr_autotune(g2, "fp64")
+    P, B1, B2 = g2.node_frames()
+    Q2, _ = inputs.initial_state(w2, P, B1, B2)
+    q2 = torch.from_numpy(Q2).cuda()
+    N2 = w2.n_nodes
+    vs = [torch.randn(3 * N2, dtype=torch.float64, device="cuda") * 1e-3 for _ in range(8)]
+    outs = [torch.empty(3 * N2, dtype=torch.float64, device="cuda") for _ in range(8)]
+    t = time_jv(g2, q2, vs, outs, 1e-150, "fp64", reps)
+    out["jv_ne60_p6_fp64"] = {"tile": tile, "us": t * 1e3, "jv_per_s": 1e3 / t,
+                              "GBs": 72 * N2 / (t * 1e-3) / 1e9, "frac_hbm": 72 * N2 / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"AUSM ne=60 p=6 J*v fp64 {t * 1e3:.1f} us")
+    del vs, outs, q2, g2
+    torch.cuda.synchronize()
+
+    w = inputs.WORKLOADS["c1_ne30_p5"]
+    opts = dfrsw.kiops_opts(tol=w.tol, m_max=w.m_max)
+    finals = {}
+    for flux in ("rusanov", "ausm"):
+        g = dfrsw.Grid(w.ne, w.p, *w.constants())
+        dfrsw.dfr_set_riemann(g, flux)
+        dfrsw.dfr_autotune(g, "fp64")
+        P, B1, B2 = g.node_frames()
+        Q, _ = inputs.initial_state(w, P, B1, B2)
+        st = dfrsw.epi_create(g, w.order, w.dt_nd, torch.from_numpy(Q).cuda(), startup_substeps=w.startup_substeps)
+        for _ in range(w.order - 2):
+            dfrsw.epi_step(g, st, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nmv = 0
+        for _ in range(steps):
+            nmv += dfrsw.epi_step(g, st, opts)["n_matvec"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        finals[flux] = dfrsw.epi_get_state(st).cpu().numpy()
+        if flux == "ausm":
+            out["epi5_c1_ne30_p5"] = {"steps_per_s": steps / dt, "jv_per_step": nmv / steps,
+                                      "sim_days_per_wall_hour": (steps * w.dt_s / 86400.0) / (dt / 3600.0)}
+        log(f"c1 EPI5 {flux}: {steps} steps in {dt:.3f}s, {nmv / steps:.0f} J*v/step")
+        del st, g
+        torch.cuda.synchronize()
+    N = w.n_nodes
+    a, b = finals["ausm"], finals["rusanov"]
+    out["epi5_c1_ne30_p5"]["rel_l2_diff_h_vs_rusanov"] = float(np.linalg.norm(a[:N] - b[:N]) / np.linalg.norm(b[:N]))
+    return out
+
+
 def cpu_baseline_leg(workload_name):
     """Time the oracle on this host: one steady-state EPI step after the
     start-up steps (untimed, one EPI2 sub-step each)."""
@@ -374,6 +432,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the ne=120, p=6 mountain figures")
     ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member ensemble comparison")
+    ap.add_argument("--no-ausm", action="store_true", help="skip the AUSM-flux figures")
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
     ap.add_argument("--ensemble-workers", type=int, default=8)
@@ -395,7 +454,7 @@ def main():
     if args.summarize_profile:
         return summarize_profile(args)
     if args.headline_only:
-        args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_cpu_baseline = True
+        args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_ausm = args.no_cpu_baseline = True
 
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)
@@ -571,6 +630,10 @@ def main():
     # member after another
     if not args.no_ensemble:
         out["ensemble_c3"] = ensemble_study(args.ensemble_members, args.ensemble_steps, args.ensemble_workers)
+
+    # ---- the AUSM interface flux (App. D) on the same path
+    if not args.no_ausm:
+        out["ausm"] = ausm_study(args.steps, 50)
 
     # ---- the oracle on this host's cores (bounded sample, one thread)
     if not args.no_cpu_baseline:

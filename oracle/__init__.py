@@ -73,6 +73,8 @@ def lib():
         L.orc_ausm_split.argtypes = [d, vp, vp, vp, vp]
         L.orc_common_flux.argtypes = [vp, vp, vp, d, vp, ctypes.c_int, vp]
         L.orc_set_riemann.argtypes = [vp, ctypes.c_int]
+        L.orc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_diagnostics.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -147,6 +149,18 @@ class OracleGrid:
         ore, oim = np.empty_like(re), np.empty_like(im)
         _check(lib().orc_rhs_split(self._h, _ptr(re), _ptr(im), _ptr(ore), _ptr(oim)))
         return ore + 1j * oim
+
+    def diagnostics(self, Q, hB=None):
+        """Sec. 5.4: (zeta, f, (mass, energy, potential enstrophy)) -- nodal
+        relative vorticity (Eq. 43), Coriolis parameter (Eq. 46) and the
+        integrals over the sphere of H, the total energy and the potential
+        enstrophy.  hB: the nodal orography (energy term), or None."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(-1)
+        hb = None if hB is None else np.ascontiguousarray(hB, dtype=np.float64)
+        z, f, out = np.empty(self.N), np.empty(self.N), np.empty(3)
+        _check(lib().orc_diagnostics(self._h, _ptr(Q), None if hb is None else _ptr(hb), _ptr(z), _ptr(f),
+                                     _ptr(out)))
+        return z, f, tuple(out)
 
     # -- geometry accessors (for pins and for building inputs) ------------
     def node_frames(self):

@@ -23,6 +23,9 @@
  *   - rotated panel angles ....................... App. B, Eqs. (81)-(95)
  *   - panel-interface vector relations ........... App. C, Eqs. (100)-(135)
  *   - complex-step Jacobian-vector product ........ Sec. 4, Eq. (28)
+ *   - relative vorticity, Coriolis parameter and the
+ *     integrals of mass, total energy and potential
+ *     enstrophy ................................. Sec. 5.4, Eqs. (43)-(46)
  *
  * Everything is written out element by element with no blocking or fusion.
  * Complex arithmetic is C99 `double complex` (the literal complex step).
@@ -58,6 +61,10 @@
  *       evaluation, as in R3; when the split Froude number is exactly zero
  *       the advective part is taken from the low side.
  *   A4  The pressure component of the mass flux vanishes (h^{0n} = 0).
+ *   D1  The derivatives of Eq. (43) are element-local collocation derivatives
+ *       of the nodal covariant velocity g_jk u^k (as in R5); integrals over
+ *       the sphere use the GL quadrature of each element with the area
+ *       element sqrt(g) dx^1 dx^2.
  */
 #include <complex.h>
 #include <math.h>
@@ -749,4 +756,69 @@ void orc_mass_weights(const orc_grid *G, double *wq) {
             metric_t m = metric_at(G, X, Y);
             wq[orc_idx(G, 0, p, ej, ei, nj, ni)] = G->w[ni] * G->w[nj] * m.sg * 0.25 * D * D;
           }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics of Sec. 5.4.  Per node: relative vorticity zeta (Eq. 43),     */
+/* Coriolis parameter f (Eq. 46); integrals over the sphere of H, of the      */
+/* total energy (1/2)[H g_ij u^i u^j + g_r((H + h_B)^2 - h_B^2)] and of the   */
+/* potential enstrophy (zeta + f)^2 / (2H).  hB: NULL or N nodal values;     */
+/* zeta, fcor: NULL or N values; out3: mass, energy, potential enstrophy.    */
+int orc_diagnostics(const orc_grid *G, const double *Q, const double *hB, double *zeta, double *fcor, double *out3) {
+  int ne = G->ne, ns = G->ns;
+  int64_t N = orc_num_nodes(G);
+  for (int64_t i = 0; i < 3 * N; ++i)
+    if (!isfinite(Q[i])) return ORC_ENONFINITE;
+  for (int64_t i = 0; i < N; ++i)
+    if (!(Q[i] > 0.0)) return ORC_EDEPTH;
+  double D = orc_delta(G), a2 = G->a * G->a;
+  double v1[ORC_MAXNS][ORC_MAXNS], v2[ORC_MAXNS][ORC_MAXNS];   /* covariant g_jk u^k, [nj][ni] */
+  double mass = 0.0, energy = 0.0, enstrophy = 0.0;
+  for (int p = 0; p < 6; ++p)
+    for (int ej = 0; ej < ne; ++ej)
+      for (int ei = 0; ei < ne; ++ei) {
+        for (int nj = 0; nj < ns; ++nj)
+          for (int ni = 0; ni < ns; ++ni) {
+            double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
+            double d2 = 1.0 + X * X + Y * Y;
+            double g11 = a2 * (1.0 + X * X) * (1.0 + X * X) * (1.0 + Y * Y) / (d2 * d2);   /* (64) */
+            double g12 = -a2 * X * Y * (1.0 + X * X) * (1.0 + Y * Y) / (d2 * d2);          /* (65) */
+            double g22 = a2 * (1.0 + X * X) * (1.0 + Y * Y) * (1.0 + Y * Y) / (d2 * d2);   /* (66) */
+            int64_t i0 = orc_idx(G, 0, p, ej, ei, nj, ni);
+            double H = Q[i0], u1 = Q[N + i0] / H, u2 = Q[2 * N + i0] / H;
+            v1[nj][ni] = g11 * u1 + g12 * u2;
+            v2[nj][ni] = g12 * u1 + g22 * u2;
+          }
+        for (int nj = 0; nj < ns; ++nj)
+          for (int ni = 0; ni < ns; ++ni) {
+            double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
+            metric_t m = metric_at(G, X, Y);
+            double d2 = 1.0 + X * X + Y * Y;
+            /* element-local derivatives (reading D1) */
+            double d1v2 = 0.0, d2v1 = 0.0;
+            for (int k = 0; k < ns; ++k) {
+              d1v2 += G->Dgl[ni][k] * v2[nj][k];
+              d2v1 += G->Dgl[nj][k] * v1[k][ni];
+            }
+            double z = (2.0 / D) * (d1v2 - d2v1) / m.sg;                               /* (43) */
+            double fac = sin(G->phi[p]) - X * cos(G->phi[p]) * sin(G->alp[p]) + Y * cos(G->phi[p]) * cos(G->alp[p]);
+            double f = 2.0 * G->omega / sqrt(d2) * fac;                                 /* (46) */
+            int64_t i0 = orc_idx(G, 0, p, ej, ei, nj, ni);
+            double H = Q[i0], u1 = Q[N + i0] / H, u2 = Q[2 * N + i0] / H;
+            double hb = hB ? hB[i0] : 0.0;
+            double ke = H * (u1 * v1[nj][ni] + u2 * v2[nj][ni]);
+            double e = 0.5 * (ke + G->g * ((H + hb) * (H + hb) - hb * hb));
+            double zs = (z + f) * (z + f) / (2.0 * H);
+            double wgt = G->w[ni] * G->w[nj] * m.sg * 0.25 * D * D;
+            mass += wgt * H;
+            energy += wgt * e;
+            enstrophy += wgt * zs;
+            if (zeta) zeta[i0] = z;
+            if (fcor) fcor[i0] = f;
+          }
+      }
+  out3[0] = mass;
+  out3[1] = energy;
+  out3[2] = enstrophy;
+  return ORC_OK;
 }
