@@ -131,6 +131,20 @@ int dfr_get_riemann(const dfr_ctx *ctx, int *solver);
  * App. C.  q, dqdt: device, 3N doubles each, may not alias. */
 int dfr_rhs(dfr_ctx *ctx, const double *q, double *dqdt);
 
+/* Diagnostics of Sec. 5.4 on the state q (device, 3N doubles):
+ *   zeta: relative vorticity, Eq. (43), with element-local collocation
+ *         derivatives of the covariant velocity g_jk u^k (Eqs. 64-66);
+ *   fcor: Coriolis parameter f, Eq. (46);
+ *   host_out3: the integrals over the sphere (GL quadrature of each element,
+ *         area element sqrt(g) dx^1 dx^2) of the mass H, of the total energy
+ *         (1/2)[H g_ij u^i u^j + g_r((H + h_B)^2 - h_B^2)] and of the
+ *         potential enstrophy (zeta + f)^2 / (2H), in the units of the grid's
+ *         constants; Eq. (44) normalises their changes in time.
+ * zeta, fcor: device, N doubles each, or NULL; host_out3: host, 3 doubles.
+ * Synchronises the context's stream.  DFR_E_NONFINITE / DFR_E_DEPTH for an
+ * invalid state; DFR_E_INVAL for NULL q or host_out3 or aliased outputs. */
+int dfr_diagnostics(dfr_ctx *ctx, const double *q, double *zeta, double *fcor, double *host_out3);
+
 /* jv = Im F(q + i eps v) / eps (Eq. 28), one complex evaluation of the same
  * right-hand side.  prec = DFR_FP64: complex FP64.  prec = DFR_FP32_JV: the
  * complex evaluation runs in FP32 on FP32 roundings of q and v (eps must

@@ -312,6 +312,19 @@ static int setup_geometry(Ctx &c, const double *hB) {
   g.tedge = c.d_tedge;
   g.xform = c.d_xform;
 
+  // collocation data of the diagnostics
+  {
+    const std::vector<double> D = gl_deriv(ns, c.xi);
+    std::memset(&c.dops, 0, sizeof(c.dops));
+    for (int k = 0; k < ns; ++k) {
+      c.dops.w[k] = c.wgl[k];
+      for (int j = 0; j < ns; ++j) c.dops.Dg[k][j] = D[k * ns + j];
+    }
+  }
+  if (hB) {
+    DFR_HIP(hipMalloc(&c.d_hB, sizeof(double) * c.n));
+    DFR_HIP(hipMemcpy(c.d_hB, hB, sizeof(double) * c.n, hipMemcpyHostToDevice));
+  }
   if (hB) {
     // orography source (g/a^2) a^2 h^ij d_j h_B per node, derivative by GL collocation
     const std::vector<double> D = gl_deriv(ns, c.xi);
@@ -389,6 +402,7 @@ static void default_tile(Ctx &c) {
 
 static int alloc_workspace(Ctx &c) {
   const int64_t n3 = 3 * c.n;
+  DFR_HIP(hipMalloc(&c.d_diag, sizeof(double) * (3 * diag_blocks(&c) + 3)));
   // largest grid of any tile (1 x 1 tiles) or of the vector kernels
   const int64_t nb = std::max<int64_t>(6LL * c.ne * c.ne + 8, 8192);
   DFR_HIP(hipMalloc(&c.d_partials, sizeof(double) * 2 * nb));
@@ -431,6 +445,8 @@ static void free_ctx(Ctx &c) {
   (void)hipFree(c.d_tedge);
   (void)hipFree(c.d_xform);
   (void)hipFree(c.d_orog);
+  (void)hipFree(c.d_hB);
+  (void)hipFree(c.d_diag);
   (void)hipFree(c.d_err);
   (void)hipFree(c.d_partials);
   (void)hipFree(c.d_partials2);
@@ -753,6 +769,21 @@ int dfr_sync(dfr_ctx *h) {
   if (!h) return DFR_E_INVAL;
   DFR_HIP(hipStreamSynchronize(h->c.stream));
   return latched_error(h->c);
+}
+
+int dfr_diagnostics(dfr_ctx *h, const double *q, double *zeta, double *fcor, double *host_out3) {
+  if (!h || !q || !host_out3 || zeta == q || fcor == q || (zeta && zeta == fcor)) {
+    set_error("invalid argument");
+    return DFR_E_INVAL;
+  }
+  Ctx &c = h->c;
+  int rc = launch_check_state(&c, q);
+  if (!rc) rc = launch_diagnostics(&c, q, zeta, fcor);
+  if (rc) return rc;
+  DFR_HIP(hipMemcpyAsync(host_out3, c.d_diag + 3 * diag_blocks(&c), 3 * sizeof(double), hipMemcpyDeviceToHost,
+                         c.stream));
+  DFR_HIP(hipStreamSynchronize(c.stream));
+  return latched_error(c);
 }
 
 int dfr_rhs(dfr_ctx *h, const double *q, double *dqdt) {

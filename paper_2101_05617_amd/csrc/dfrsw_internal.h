@@ -36,6 +36,13 @@ struct Ops1D {
   double lm[MAX_NS], lp[MAX_NS];   // Lagrange basis at xi = -1, +1
 };
 
+// Collocation data of the diagnostics: GL weights and the derivative of the
+// GL Lagrange basis at the GL points, Dg[m][k] = l'_k(xi_m).
+struct DiagOps {
+  double w[MAX_NS];
+  double Dg[MAX_NS][MAX_NS];
+};
+
 // Per-abscissa tangent data: X = tan x, 1 + X^2, 1/(1 + X^2).
 struct Tan3 {
   double x, ax, rax, pad;
@@ -179,6 +186,9 @@ struct Ctx {
   // device buffers
   Tan3 *d_tnode = nullptr;
   double *d_tedge = nullptr, *d_xform = nullptr, *d_orog = nullptr;
+  double *d_hB = nullptr;         // nodal orography (N) or NULL
+  DiagOps dops;
+  double *d_diag = nullptr;       // diagnostics: 3 partial sums per workgroup, then the 3 totals
   int *d_err = nullptr;
   // KIOPS workspace
   int kiops_mmax = 0, kiops_p = 0;
@@ -234,6 +244,8 @@ int launch_combine(Ctx *c, double *x);
 int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol);
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
+int64_t diag_blocks(const Ctx *c);
+int launch_diagnostics(Ctx *c, const double *q, double *zeta, double *fcor);
 int launch_check_state(Ctx *c, const double *q);
 int launch_fill(Ctx *c, double *q, double *v);
 int latched_error(Ctx &c);

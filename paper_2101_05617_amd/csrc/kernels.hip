@@ -1252,6 +1252,107 @@ __global__ __launch_bounds__(BLOCK) void check_state_batch(const AxpbyCall *__re
 }
 
 // ---------------------------------------------------------------------------
+// Diagnostics of Sec. 5.4.  A workgroup holds EPB = 256 / NN whole elements,
+// one thread per node.  Per node: the covariant velocity v_j = g_jk u^k
+// (Eqs. 64-66), the relative vorticity zeta = (d_1 v_2 - d_2 v_1)/sqrt(g)
+// (Eq. 43, element-local collocation derivatives), the Coriolis parameter
+// f (Eq. 46); per workgroup the GL-quadrature sums (area element sqrt(g)
+// dx^1 dx^2) of H, of the total energy (1/2)[H g_ij u^i u^j + g_r((H +
+// h_B)^2 - h_B^2)] and of the potential enstrophy (zeta + f)^2/(2H), in a
+// fixed order; diag_sum_kernel adds the partial sums.
+template <int NS>
+__global__ __launch_bounds__(256) void diag_kernel(const GridArgs g, const DiagOps d, double a2, double gr,
+                                                   const double *__restrict__ q, const double *__restrict__ hB,
+                                                   double *__restrict__ zeta, double *__restrict__ fcor,
+                                                   double *__restrict__ part) {
+  constexpr int NN = NS * NS;
+  constexpr int EPB = 256 / NN;
+  __shared__ double sv[2][EPB * NN];
+  __shared__ double red[3 * 4];
+  const int tid = threadIdx.x;
+  const int le = tid / NN, node = tid - le * NN;
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool active = le < EPB && e < g.nelem;
+  const int64_t N = g.n;
+  const int ne = g.ne;
+  const int ni = node % NS, nj = node / NS;
+  double sm = 0.0, se = 0.0, sz = 0.0;
+  double H = 1.0, u1 = 0.0, u2 = 0.0, v1 = 0.0, v2 = 0.0, X = 0.0, Y = 0.0, ax = 1.0, ay = 1.0;
+  int64_t gidx = 0;
+  int p = 0;
+  if (active) {
+    const int ei = (int)(e % ne), ej = (int)((e / ne) % ne);
+    p = (int)(e / ((int64_t)ne * ne));
+    gidx = e * NN + node;
+    const Tan3 tx = g.tnode[ei * NS + ni], ty = g.tnode[ej * NS + nj];
+    X = tx.x;
+    ax = tx.ax;
+    Y = ty.x;
+    ay = ty.ax;
+    const double d2 = ax + Y * Y, rd4 = 1.0 / (d2 * d2);
+    const double g11 = a2 * ax * ax * ay * rd4, g12 = -a2 * X * Y * ax * ay * rd4, g22 = a2 * ax * ay * ay * rd4;
+    H = q[gidx];
+    u1 = q[N + gidx] / H;
+    u2 = q[2 * N + gidx] / H;
+    v1 = g11 * u1 + g12 * u2;
+    v2 = g12 * u1 + g22 * u2;
+    sv[0][le * NN + node] = v1;
+    sv[1][le * NN + node] = v2;
+  }
+  __syncthreads();
+  if (active) {
+    const double *w1 = sv[0] + le * NN, *w2 = sv[1] + le * NN;
+    double d1v2 = 0.0, d2v1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      d1v2 += d.Dg[ni][k] * w2[nj * NS + k];
+      d2v1 += d.Dg[nj][k] * w1[k * NS + ni];
+    }
+    const double d2 = ax + Y * Y, sd = sqrt(d2);
+    const double sg = a2 * ax * ay / (d2 * sd);                                   // Eq. (70)
+    const double z = g.two_over_delta * (d1v2 - d2v1) / sg;                      // Eq. (43)
+    const double f = 2.0 * g.omega / sd * (g.cA[p] + X * g.cB[p] + Y * g.cC[p]);   // Eq. (46)
+    const double hb = hB ? hB[gidx] : 0.0;
+    const double en = 0.5 * (H * (u1 * v1 + u2 * v2) + gr * ((H + hb) * (H + hb) - hb * hb));
+    const double zs = (z + f) * (z + f) / (2.0 * H);
+    const double wgt = d.w[ni] * d.w[nj] * sg / (g.two_over_delta * g.two_over_delta);
+    sm = wgt * H;
+    se = wgt * en;
+    sz = wgt * zs;
+    if (zeta) zeta[gidx] = z;
+    if (fcor) fcor[gidx] = f;
+  }
+  sm = wave_sum(sm);
+  se = wave_sum(se);
+  sz = wave_sum(sz);
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) {
+    red[3 * wv + 0] = sm;
+    red[3 * wv + 1] = se;
+    red[3 * wv + 2] = sz;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[3 * k + tid];
+    part[(int64_t)blockIdx.x * 3 + tid] = s;
+  }
+}
+
+// the three totals from the partial sums of nb workgroups, in a fixed order
+__global__ __launch_bounds__(BLOCK) void diag_sum_kernel(int64_t nb, const double *__restrict__ part,
+                                                         double *__restrict__ out) {
+  __shared__ double red[BLOCK / 64];
+  for (int k = 0; k < 3; ++k) {
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += BLOCK) acc += part[b * 3 + k];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) out[k] = s;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 static inline int grid_for(int64_t n) {
   int64_t b = (n + BLOCK - 1) / BLOCK;
@@ -1580,6 +1681,38 @@ int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> 
     }
     default: set_error("unknown batched vector kernel"); return DFR_E_INVAL;
   }
+}
+
+int64_t diag_blocks(const Ctx *c) {
+  const int epb = 256 / (c->ns * c->ns);
+  return (c->nelem + epb - 1) / epb;
+}
+
+int launch_diagnostics(Ctx *c, const double *q, double *zeta, double *fcor) {
+  const int64_t nb = diag_blocks(c);
+  const double a2 = c->radius * c->radius;
+  double *part = c->d_diag;
+  const int threads = ((256 / (c->ns * c->ns)) * c->ns * c->ns + 63) / 64 * 64;
+#define DIAG_CASE(K)                                                                                              \
+  case K:                                                                                                       \
+    dfr_launch(c, DFR_K_OTHER, diag_kernel<K>, dim3((unsigned)nb), dim3(threads), 0, c->ga, c->dops, a2, c->gravity, \
+               q, (const double *)c->d_hB, zeta, fcor, part);                                                    \
+    break;
+  switch (c->ns) {
+    DIAG_CASE(2)
+    DIAG_CASE(3)
+    DIAG_CASE(4)
+    DIAG_CASE(5)
+    DIAG_CASE(6)
+    DIAG_CASE(7)
+    DIAG_CASE(8)
+    default: set_error("unsupported number of GL points"); return DFR_E_INVAL;
+  }
+#undef DIAG_CASE
+  DFR_HIP(hipGetLastError());
+  dfr_launch(c, DFR_K_FINALIZE, diag_sum_kernel, dim3(1), dim3(BLOCK), 0, nb, (const double *)part, part + 3 * nb);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
 }
 
 }  // namespace dfrsw

@@ -93,6 +93,7 @@ def lib():
             "epi_ensemble_destroy": (i, [vp]),
             "dfr_set_tile": (i, [vp, i, i]),
             "dfr_set_riemann": (i, [vp, i]),
+            "dfr_diagnostics": (i, [vp, vp, vp, vp, ctypes.POINTER(d)]),
             "dfr_get_riemann": (i, [vp, ctypes.POINTER(i)]),
             "dfr_get_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_get_krylov_tile": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
@@ -114,7 +115,7 @@ def exported_symbols():
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
             "epi_num_steps", "epi_destroy", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
-            "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
+            "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_diagnostics", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_last_error"]
 
 
@@ -244,6 +245,18 @@ def dfr_get_riemann(g):
     r = ctypes.c_int()
     _check(lib().dfr_get_riemann(g.handle, ctypes.byref(r)))
     return {v: k for k, v in RIEMANN.items()}[r.value]
+
+
+def dfr_diagnostics(g, q, zeta=True, fcor=False):
+    """Sec. 5.4 diagnostics of the device state q: (zeta or None, f or None,
+    (mass, total energy, potential enstrophy))."""
+    import torch
+    z = torch.empty(g.N, dtype=torch.float64, device="cuda") if zeta else None
+    f = torch.empty(g.N, dtype=torch.float64, device="cuda") if fcor else None
+    out = (ctypes.c_double * 3)()
+    _check(lib().dfr_diagnostics(g.handle, _dev(q), None if z is None else _dev(z),
+                                 None if f is None else _dev(f), out))
+    return z, f, (out[0], out[1], out[2])
 
 
 def dfr_set_tile(g: Grid, tx, ty):
