@@ -365,6 +365,84 @@ def ausm_study(steps, reps):
     return out
 
 
+def diagnostics_study(reps):
+    """dfr_diagnostics at ne = 60, p = 6: the state check, the per-node
+    vorticity / density kernel and the final sums, per call (library kernel
+    timing), and the algorithmic bytes of the first two (read q twice, write
+    zeta: 56 B per node)."""
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    w = inputs.WORKLOADS["c2_ne60_p6_jet"]
+    g = dfrsw.Grid(w.ne, w.p, *w.constants())
+    P, B1, B2 = g.node_frames()
+    Q, _ = inputs.initial_state(w, P, B1, B2)
+    q = torch.from_numpy(Q).cuda()
+    for _ in range(3):
+        dfrsw.dfr_diagnostics(g, q)
+    dfrsw.dfr_timing_enable(g, True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, _, it = dfrsw.dfr_diagnostics(g, q)
+    wall = (time.perf_counter() - t0) / reps
+    k_ms = sum(dfrsw.dfr_timing_read(g, k)[0] for k in ("other", "finalize")) / reps
+    dfrsw.dfr_timing_enable(g, False)
+    N = w.n_nodes
+    log(f"diagnostics ne=60 p=6: {k_ms * 1e3:.1f} us kernels, {wall * 1e6:.0f} us per call")
+    out = {"nodes": N, "kernel_us_per_call": k_ms * 1e3, "wall_us_per_call": wall * 1e6,
+           "bytes_per_node": 56, "GBs": 56 * N / (k_ms * 1e-3) / 1e9,
+           "frac_hbm": 56 * N / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "mass_energy_enstrophy": list(it)}
+    del q, g
+    return out
+
+
+def large_dt_study(steps):
+    """The large-time-step regime: the mountain flow on ne = 20, p = 5 (86,400
+    nodes) with dt = 4 h, EPI3..EPI6 (start-up untimed, then `steps` timed
+    steps each), and EPI6 with dt = 1 h over the same simulated time for
+    comparison; KIOPS statistics per step."""
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    w0 = inputs.WORKLOADS["f2_ne20_p5_mountain_dt4h"]
+    out = {"workload": f"{w0.name}: ne={w0.ne}, p={w0.p} ({w0.n_nodes} nodes), Gaussian mountain, "
+                       f"tol {w0.tol:g}, m<={w0.m_max}"}
+    g0 = dfrsw.Grid(w0.ne, w0.p, *w0.constants())
+    P, B1, B2 = g0.node_frames()
+    g0.close()
+    Q, hB = inputs.initial_state(w0, P, B1, B2)
+    g = dfrsw.Grid(w0.ne, w0.p, *w0.constants(), hB=hB)
+    dfrsw.dfr_autotune(g, "fp64")
+    opts = dfrsw.kiops_opts(tol=w0.tol, m_max=w0.m_max)
+    for order, dt_s, nsteps in [(3, 14400.0, steps), (4, 14400.0, steps), (5, 14400.0, steps), (6, 14400.0, steps),
+                                (6, 3600.0, 4 * steps)]:
+        dt = dt_s * inputs.EARTH_OMEGA
+        st = dfrsw.epi_create(g, order, dt, torch.from_numpy(Q).cuda(), startup_substeps=4)
+        for _ in range(order - 2):
+            dfrsw.epi_step(g, st, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        agg = {"n_matvec": 0, "n_substeps": 0, "n_rejected": 0}
+        mmax = 0
+        for _ in range(nsteps):
+            s = dfrsw.epi_step(g, st, opts)
+            for k in agg:
+                agg[k] += s[k]
+            mmax = max(mmax, s["m_last"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        key = f"epi{order}_dt{int(dt_s / 3600)}h"
+        out[key] = {"steps_per_s": nsteps / el, "sim_days_per_wall_hour": (nsteps * dt_s / 86400.0) / (el / 3600.0),
+                    "jv_per_step": agg["n_matvec"] / nsteps, "substeps_per_step": agg["n_substeps"] / nsteps,
+                    "rejections_per_step": agg["n_rejected"] / nsteps, "max_krylov_m": mmax}
+        log(f"large dt {key}: {nsteps} steps in {el:.3f}s, {agg['n_matvec'] / nsteps:.0f} J*v/step")
+        del st
+    del g
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline_leg(workload_name):
     """Time the oracle on this host: one steady-state EPI step after the
     start-up steps (untimed, one EPI2 sub-step each)."""
@@ -433,6 +511,8 @@ def main():
     ap.add_argument("--c4-steps", type=int, default=2)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member ensemble comparison")
     ap.add_argument("--no-ausm", action="store_true", help="skip the AUSM-flux figures")
+    ap.add_argument("--no-diagnostics", action="store_true", help="skip the conservation-diagnostics figures")
+    ap.add_argument("--no-large-dt", action="store_true", help="skip the dt = 4 h figures")
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
     ap.add_argument("--ensemble-workers", type=int, default=8)
@@ -454,7 +534,8 @@ def main():
     if args.summarize_profile:
         return summarize_profile(args)
     if args.headline_only:
-        args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_ausm = args.no_cpu_baseline = True
+        args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_ausm = args.no_diagnostics = \
+            args.no_large_dt = args.no_cpu_baseline = True
 
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)
@@ -634,6 +715,14 @@ def main():
     # ---- the AUSM interface flux (App. D) on the same path
     if not args.no_ausm:
         out["ausm"] = ausm_study(args.steps, 50)
+
+    # ---- conservation diagnostics (Sec. 5.4)
+    if not args.no_diagnostics:
+        out["diagnostics_c2"] = diagnostics_study(20)
+
+    # ---- the large-time-step regime (dt = 4 h)
+    if not args.no_large_dt:
+        out["large_dt"] = large_dt_study(4)
 
     # ---- the oracle on this host's cores (bounded sample, one thread)
     if not args.no_cpu_baseline:

@@ -90,6 +90,11 @@ WORKLOADS = {
     "c4_ne120_p6_mountain": Workload("c4_ne120_p6_mountain", ne=120, p=6, order=6, dt_s=600.0,
                                      steps=144, tol=1e-10, m_max=64, eps=1e-150, seed=4,
                                      kind="mountain", gh0=5960.0 * GRAVITY, u0=20.0),
+    # the large-time-step regime: the mountain flow on a grid of 86,400 nodes
+    # (ne=20, p=5) with dt = 4 h (Courant numbers 40-80 at this resolution)
+    "f2_ne20_p5_mountain_dt4h": Workload("f2_ne20_p5_mountain_dt4h", ne=20, p=5, order=6, dt_s=14400.0,
+                                         steps=90, tol=1e-10, m_max=64, eps=1e-150, seed=4,
+                                         kind="mountain", gh0=5960.0 * GRAVITY, u0=20.0),
 }
 
 
