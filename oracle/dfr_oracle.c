@@ -61,7 +61,7 @@
  *       evaluation, as in R3; when the split Froude number is exactly zero
  *       the advective part is taken from the low side.
  *   A4  The pressure component of the mass flux vanishes (h^{0n} = 0).
- *   D1  The derivatives of Eq. (43) are element-local collocation derivatives
+ *   V1  The derivatives of Eq. (43) are element-local collocation derivatives
  *       of the nodal covariant velocity g_jk u^k (as in R5); integrals over
  *       the sphere use the GL quadrature of each element with the area
  *       element sqrt(g) dx^1 dx^2.
@@ -794,7 +794,7 @@ int orc_diagnostics(const orc_grid *G, const double *Q, const double *hB, double
             double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
             metric_t m = metric_at(G, X, Y);
             double d2 = 1.0 + X * X + Y * Y;
-            /* element-local derivatives (reading D1) */
+            /* element-local derivatives (reading V1) */
             double d1v2 = 0.0, d2v1 = 0.0;
             for (int k = 0; k < ns; ++k) {
               d1v2 += G->Dgl[ni][k] * v2[nj][k];
