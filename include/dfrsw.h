@@ -46,7 +46,14 @@ enum {
   DFR_E_KIOPS = -6       /* the Krylov controller did not converge */
 };
 
-typedef enum { DFR_FP64 = 0, DFR_FP32_JV = 1 } dfr_precision;
+/* Precision of the products inside KIOPS / EPI.  DFR_FP64: complex FP64.
+ * DFR_FP32_JV: the complex-step evaluation in complex FP32 (FP64 Krylov
+ * basis, inner products, norms, Hessenberg, exponential, combination and EPI
+ * update).  DFR_FP32_JV_BASIS32: as DFR_FP32_JV with the Krylov basis stored
+ * in FP32 (its vectors rounded once when stored; inner products and norms
+ * accumulate in FP64 over the stored values); single-grid KIOPS / EPI only,
+ * dfr_jvp_complex_step treats it as DFR_FP32_JV. */
+typedef enum { DFR_FP64 = 0, DFR_FP32_JV = 1, DFR_FP32_JV_BASIS32 = 2 } dfr_precision;
 
 typedef struct dfr_ctx dfr_ctx;
 typedef struct epi_state epi_state;

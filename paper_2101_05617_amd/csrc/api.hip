@@ -692,16 +692,23 @@ int dfr_get_krylov_tile(const dfr_ctx *h, int *tx, int *ty) {
 }
 
 int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
-  if (!h || (prec != DFR_FP64 && prec != DFR_FP32_JV)) return DFR_E_INVAL;
+  if (!h || (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) return DFR_E_INVAL;
   Ctx &c = h->c;
   const int64_t n3 = 3 * c.n;
-  // a smooth positive state and a direction in the Krylov workspace
+  // a smooth positive state and a direction in the Krylov workspace (and
+  // FP32 copies of the direction and of a previous vector for an FP32 basis)
   double *q = c.d_V, *v = c.d_V + n3, *w = c.d_V + 2 * n3;
+  float *vf = reinterpret_cast<float *>(c.d_V + 3 * n3), *pf = vf + n3, *wf = pf + n3;
   int rc = launch_fill(&c, q, v);
   if (rc) return rc;
-  const bool fp32 = prec == DFR_FP32_JV;
+  const bool fp32 = prec != DFR_FP64, b32 = prec == DFR_FP32_JV_BASIS32;
   if (fp32) {
     rc = launch_copy_to_f32(&c, n3, q, (float *)c.d_qf32);
+    if (rc) return rc;
+  }
+  if (b32) {
+    rc = launch_copy_to_f32(&c, n3, v, vf);
+    if (!rc) rc = launch_copy_to_f32(&c, n3, q, pf);
     if (rc) return rc;
   }
   const double eps = fp32 ? 1e-20 : 1e-150;
@@ -713,7 +720,7 @@ int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
   ar.p = std::min(4, MAX_P);
   ar.start = 1;
   for (int k = 0; k < ar.p; ++k) ar.W[k] = v;
-  ar.vprev = q;
+  ar.vprev = b32 ? (const void *)pf : (const void *)q;
   ar.pin = q;
   ar.np_in = 1;
   ar.pout = c.d_partials;
@@ -742,9 +749,12 @@ int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
       bt[0] = t.first;
       bt[1] = t.second;
     }
+    c.basis32 = b32;
     rc = time_launches(c, e0, e1, 5, [&] {
-      return launch_dfr(&c, q, (const float *)c.d_qf32, v, nullptr, eps, true, fp32, w, &ar);
+      return launch_dfr(&c, q, (const float *)c.d_qf32, b32 ? (const void *)vf : (const void *)v, nullptr, eps, true,
+                        fp32, b32 ? (void *)wf : (void *)w, &ar);
     }, &ms);
+    c.basis32 = false;
     if (rc) break;
     if (ms < best_ar) {
       best_ar = ms;
@@ -795,12 +805,13 @@ int dfr_rhs(dfr_ctx *h, const double *q, double *dqdt) {
 }
 
 int dfr_jvp_complex_step(dfr_ctx *h, const double *q, const double *v, double eps, dfr_precision prec, double *jv) {
-  if (!h || !q || !v || !jv || jv == q || jv == v || !(eps > 0.0) || (prec != DFR_FP64 && prec != DFR_FP32_JV)) {
+  if (!h || !q || !v || !jv || jv == q || jv == v || !(eps > 0.0) ||
+      (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
     set_error("invalid argument");
     return DFR_E_INVAL;
   }
   Ctx &c = h->c;
-  if (prec == DFR_FP32_JV) {
+  if (prec != DFR_FP64) {
     int rc = launch_copy_to_f32(&c, 3 * c.n, q, (float *)c.d_qf32);
     if (rc) return rc;
     return launch_dfr(&c, nullptr, (const float *)c.d_qf32, v, nullptr, eps, true, true, jv, nullptr);

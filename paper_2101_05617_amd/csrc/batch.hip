@@ -318,7 +318,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
         u.p = k.p;
         u.w = out;
         u.vj = c.d_V + (int64_t)k.j * n3;
-        u.vprev = ar.vprev;
+        u.vprev = static_cast<const double *>(ar.vprev);   // batched bases are FP64
         u.pin = c.d_partials;
         u.np_in = k.npA;
         u.pout = c.d_partials2;
@@ -573,6 +573,10 @@ int epi_ensemble_create(dfr_ensemble *E, int order, double dt, int startup_subst
                         double eps, dfr_precision prec, epi_ensemble **out) {
   if (!E || !q0 || !out) {
     set_error("epi_ensemble_create: invalid argument");
+    return DFR_E_INVAL;
+  }
+  if (prec == DFR_FP32_JV_BASIS32) {
+    set_error("epi_ensemble_create: the batched form keeps its Krylov bases in FP64 (DFR_FP64 or DFR_FP32_JV)");
     return DFR_E_INVAL;
   }
   *out = nullptr;

@@ -77,7 +77,7 @@ struct ArnoldiArgs {
   int p;                  // number of W columns
   int start;              // 1: v_j is the sub-step's start vector
   const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
-  const double *vprev;    // V_{j-1} (normalised) or NULL (iop = 1)
+  const void *vprev;      // v~_{j-1} as stored (basis element type) or NULL (iop = 1)
   const double *pin;      // partial sums of the previous kernel, one per workgroup
   int np_in;
   double *pout;           // this kernel's partial inner products, two per workgroup
@@ -196,7 +196,11 @@ struct Ctx {
   int tile_tx = 1, tile_ty = 1;   // elements per workgroup of the DFR kernel (x^1, x^2)
   int ar_tx = 1, ar_ty = 1;       // the same for the J*v kernel with the Arnoldi prologue/epilogue
   size_t lds_limit = 65536;       // LDS one workgroup may use
-  double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N
+  double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N (FP64, or FP32 when basis32)
+  bool basis32 = false;           // the current KIOPS call keeps its basis in FP32
+  void *vslot(int k) const {
+    return reinterpret_cast<char *>(d_V) + (size_t)k * 3 * (size_t)n * (basis32 ? sizeof(float) : sizeof(double));
+  }
   double *d_W = nullptr;          // MAX_P scaled b columns of 3N
   double *d_partials = nullptr;   // per-block partial sums (J*v inner products)
   double *d_partials2 = nullptr;  // per-block partial sums (norms)
@@ -234,12 +238,14 @@ inline void dfr_launch(Ctx *c, int kind, void (*kernel)(KArgs...), dim3 grid, di
 }
 
 // kernels.hip
-int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const double *vscale,
-               double eps, bool complex_step, bool fp32, double *out, const ArnoldiArgs *ar);
-int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out);
-int launch_update(Ctx *c, int j, double *w, const double *vj, const double *vprev, const double *pin, int np_in,
+// v, out and the basis slots are FP64, or FP32 in the Krylov form when
+// c->basis32 (the product of the FP32 form with an FP32 basis)
+int launch_dfr(Ctx *c, const double *q, const float *q32, const void *v, const double *vscale,
+               double eps, bool complex_step, bool fp32, void *out, const ArnoldiArgs *ar);
+int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, void *out, int *np_out);
+int launch_update(Ctx *c, int j, void *w, const void *vj, const void *vprev, const double *pin, int np_in,
                   double *pout, int *np_out);
-int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out);
+int launch_start(Ctx *c, const double *x, void *v0, double *pout, int *np_out);
 int launch_combine(Ctx *c, double *x);
 int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol);
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);

@@ -13,6 +13,7 @@
 #include "dfrsw_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 
@@ -366,10 +367,10 @@ __device__ __forceinline__ T lin(cx<T> z) {
 // The kernel body: tile `lb` (0 <= lb < 6 (ne/TX)(ne/TY)) of the grid
 // described by g.  Its partial inner products (Krylov form) go to
 // ar.pout[2 lb], ar.pout[2 lb + 1]; tile 0 records the prologue's values.
-template <int NS, typename T, typename TQ, bool CS, bool AR, int RS>
+template <int NS, typename T, typename TQ, bool CS, bool AR, int RS, typename TV>
 __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, const int TX, const int TY, const int lb,
-                                         const TQ *__restrict__ q, const double *__restrict__ v,
-                                         const double *__restrict__ vscale, double eps, double *__restrict__ out,
+                                         const TQ *__restrict__ q, const TV *__restrict__ v,
+                                         const double *__restrict__ vscale, double eps, TV *__restrict__ out,
                                          const ArnoldiArgs &ar) {
   constexpr int NN = NS * NS;
   constexpr int L = CS ? 2 : 1;   // parts kept of a state value
@@ -476,7 +477,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       double a = 0.0;
       for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
       wb[f] = a;
-      if (ar.vprev) vp[f] = sp * ar.vprev[id];
+      if (ar.vprev) vp[f] = sp * (double)static_cast<const TV *>(ar.vprev)[id];
     }
   }
 
@@ -503,7 +504,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       const T qr = (T)q[f * N + gidx];
       T qi = T(0);
       if constexpr (CS) {
-        const double vv = v[f * N + gidx];
+        const double vv = (double)v[f * N + gidx];
         vtrue[f] = vv;
         qi = (T)(eps * vv);
       }
@@ -572,7 +573,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       const int id = first + k * st;
       const T wk = wlo ? (T)ops.lm[k] : (T)ops.lp[k];
       ar_ += wk * (T)q[id];
-      if constexpr (CS) ai_ += wk * (T)(eps * v[id]);
+      if constexpr (CS) ai_ += wk * (T)(eps * (double)v[id]);
     }
     T *tp = TR + (((4 * nel + h) * 3 + f) * NS + t) * L;
     tp[0] = ar_;
@@ -732,7 +733,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     }
     if constexpr (!AR) {
 #pragma unroll
-      for (int f = 0; f < 3; ++f) out[f * N + gidx] = w[f];
+      for (int f = 0; f < 3; ++f) out[f * N + gidx] = (TV)w[f];
     }
   }
   if constexpr (!AR) return;
@@ -744,10 +745,11 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int id = f * N + gidx;
-      const double a = vs * (wr[f] * invE + wb[f]);
+      // the inner products use the value as stored (rounded to the basis type)
+      const TV a = (TV)(vs * (wr[f] * invE + wb[f]));
       out[id] = a;
-      d0 += a * (vs * vtrue[f]);
-      d1 += a * vp[f];
+      d0 += (double)a * (vs * vtrue[f]);
+      d1 += (double)a * vp[f];
     }
   }
   block_sum2(d0, d1, red);
@@ -761,15 +763,15 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
 // rounded up to whole groups of eight workgroups; RS: the common flux
 // (0 Rusanov, 1 AUSM), a template argument so that each kernel keeps the
 // registers of its own flux
-template <int NS, typename T, typename TQ, bool CS, bool AR, int RS>
+template <int NS, typename T, typename TQ, bool CS, bool AR, int RS, typename TV>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
                                                                const int TY, const TQ *__restrict__ q,
-                                                               const double *__restrict__ v,
+                                                               const TV *__restrict__ v,
                                                                const double *__restrict__ vscale, double eps,
-                                                               double *__restrict__ out, const ArnoldiArgs ar) {
+                                                               TV *__restrict__ out, const ArnoldiArgs ar) {
   const int lb = (int)logical_block(6 * (g.ne / TX) * (g.ne / TY));
   if (lb < 0) return;   // uniform: padding workgroup of the XCD mapping
-  dfr_body<NS, T, TQ, CS, AR, RS>(g, ops, TX, TY, lb, q, v, vscale, eps, out, ar);
+  dfr_body<NS, T, TQ, CS, AR, RS, TV>(g, ops, TX, TY, lb, q, v, vscale, eps, out, ar);
 }
 
 // several grids (ensemble members) in one launch: member m owns the logical
@@ -786,8 +788,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCal
   }
   __syncthreads();
   const DfrCall &c = calls[s_m];
-  dfr_body<NS, T, TQ, CS, AR, 0>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q), c.v,
-                                 c.vscale, c.eps, c.out, c.ar);
+  dfr_body<NS, T, TQ, CS, AR, 0, double>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q),
+                                         c.v, c.vscale, c.eps, c.out, c.ar);
 }
 
 // ---------------------------------------------------------------------------
@@ -810,7 +812,8 @@ __device__ __forceinline__ int find_call(const C *__restrict__ calls, int ncalls
 
 // first Arnoldi step of a sub-step whose top block is identically zero:
 // w = W b_0 (no J v); both partial inner products vanish
-__device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3, const ArnoldiArgs &ar, double *out) {
+template <typename TV>
+__device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3, const ArnoldiArgs &ar, TV *out) {
   __shared__ double red[256];
   if (ar.kd->happy) return;
   double sig, bj[MAX_P];
@@ -818,14 +821,15 @@ __device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     double acc = 0.0;
     for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * bj[k];
-    out[i] = acc;
+    out[i] = (TV)acc;
   }
   if (threadIdx.x == 0) {
     ar.pout[blk * 2 + 0] = 0.0;
     ar.pout[blk * 2 + 1] = 0.0;
   }
 }
-__global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, double *out) {
+template <typename TV>
+__global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, TV *out) {
   arnoldi_first_body(blockIdx.x, gridDim.x, n3, ar, out);
 }
 __global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__restrict__ calls, int ncalls) {
@@ -840,8 +844,9 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__
 // partial ||w||^2 per workgroup.  Basis vectors stay as built (v~_k), their
 // scales sigma_k kept in KDev.  The first UNROLL elements of each thread are
 // read before the prologue, in flight during its reductions.
-__device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n3, int j, int p, double *w,
-                                                    const double *vj, const double *vprev, const double *pin,
+template <typename TV>
+__device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n3, int j, int p, TV *w,
+                                                    const TV *vj, const TV *vprev, const double *pin,
                                                     int np_in, double *pout, KDev *kd) {
   constexpr int UNROLL = 4;
   __shared__ double red[512];
@@ -854,9 +859,9 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
     const int64_t i = i0 + u * gs;
     xw[u] = xv[u] = xp[u] = 0.0;
     if (i < n3) {
-      xw[u] = w[i];
-      xv[u] = vj[i];
-      if (two) xp[u] = vprev[i];
+      xw[u] = (double)w[i];
+      xv[u] = (double)vj[i];
+      if (two) xp[u] = (double)vprev[i];
     }
   }
   if (kd->happy) return;
@@ -893,22 +898,25 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t i = i0 + u * gs;
     if (i < n3) {
-      const double x = (xw[u] - ca * xv[u]) - cb * xp[u];
+      // the norm is that of the vector as stored (rounded to the basis type)
+      const TV x = (TV)((xw[u] - ca * xv[u]) - cb * xp[u]);
       w[i] = x;
-      acc += x * x;
+      acc += (double)x * (double)x;
     }
   }
   for (int64_t i = i0 + UNROLL * gs; i < n3; i += gs) {
-    double x = w[i] - ca * vj[i];
-    if (two) x -= cb * vprev[i];
+    double y = (double)w[i] - ca * (double)vj[i];
+    if (two) y -= cb * (double)vprev[i];
+    const TV x = (TV)y;
     w[i] = x;
-    acc += x * x;
+    acc += (double)x * (double)x;
   }
   const double b = block_sum(acc, red);
   if (threadIdx.x == 0) pout[blk] = b;
 }
-__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, double *w, const double *vj,
-                                                               const double *vprev, const double *pin, int np_in,
+template <typename TV>
+__global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, TV *w, const TV *vj,
+                                                               const TV *vprev, const double *pin, int np_in,
                                                                double *pout, KDev *kd) {
   arnoldi_update_body(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
 }
@@ -918,19 +926,21 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *
 }
 
 // start of a sub-step: v~_0 = x (copied), partial ||x||^2 per workgroup
-__device__ __forceinline__ void arnoldi_start_body(int blk, int nblk, int64_t n3, const double *x, double *v0,
+template <typename TV>
+__device__ __forceinline__ void arnoldi_start_body(int blk, int nblk, int64_t n3, const double *x, TV *v0,
                                                    double *pout) {
   __shared__ double red[BLOCK / 64];
   double acc = 0.0;
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
-    const double xv = x[i];
+    const TV xv = (TV)x[i];
     v0[i] = xv;
-    acc += xv * xv;
+    acc += (double)xv * (double)xv;
   }
   const double b = block_sum(acc, red);
   if (threadIdx.x == 0) pout[blk] = b;
 }
-__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, double *v0, double *pout) {
+template <typename TV>
+__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, TV *v0, double *pout) {
   arnoldi_start_body(blockIdx.x, gridDim.x, n3, x, v0, pout);
 }
 __global__ __launch_bounds__(BLOCK) void arnoldi_start_batch(const StartCall *__restrict__ calls, int ncalls) {
@@ -940,7 +950,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_start_batch(const StartCall *__
 
 // accepted sub-step: x = beta * sum_{k<J} sigma_k v~_k E[k][0]; the
 // coefficients are staged in LDS
-__device__ __forceinline__ void arnoldi_combine_body(int blk, int nblk, int64_t n3, const double *V, int64_t ldv,
+template <typename TV>
+__device__ __forceinline__ void arnoldi_combine_body(int blk, int nblk, int64_t n3, const TV *V, int64_t ldv,
                                                      const KDev *kd, double *x) {
   __shared__ double cf[MAX_M + 1];
   const int J = kd->J;
@@ -949,11 +960,12 @@ __device__ __forceinline__ void arnoldi_combine_body(int blk, int nblk, int64_t 
   __syncthreads();
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     double acc = 0.0;
-    for (int k = 0; k < J; ++k) acc += V[k * ldv + i] * cf[k];
+    for (int k = 0; k < J; ++k) acc += (double)V[k * ldv + i] * cf[k];
     x[i] = beta * acc;
   }
 }
-__global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, const double *V, int64_t ldv, const KDev *kd,
+template <typename TV>
+__global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, const TV *V, int64_t ldv, const KDev *kd,
                                                                 double *x) {
   arnoldi_combine_body(blockIdx.x, gridDim.x, n3, V, ldv, kd, x);
 }
@@ -1391,31 +1403,47 @@ int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi) {
 }
 
 template <int NS, typename T, typename TQ, bool CS, bool AR>
-static void launch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale, double eps, double *out,
+static void launch_ns(Ctx *c, const TQ *q, const void *v, const double *vscale, double eps, void *out,
                       const ArnoldiArgs &ar) {
   const int tx = ar.on ? c->ar_tx : c->tile_tx, ty = ar.on ? c->ar_ty : c->tile_ty;
   const size_t lds = (size_t)dfr_lds_layout(NS, tx, ty, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T);
   const int threads = std::max(256, ((tx * ty * NS * NS + 63) / 64) * 64);
   const int64_t nb = dfr_grid_blocks(c, ar.on != 0);
   const int kind = !CS ? DFR_K_RHS : (ar.on ? DFR_K_JV_ARNOLDI : DFR_K_JV);
+  const dim3 grid((unsigned)nb), block(threads);
+  if constexpr (AR && std::is_same<T, float>::value) {
+    if (c->basis32) {   // the FP32 form with an FP32 basis
+      const float *vf = static_cast<const float *>(v);
+      float *of = static_cast<float *>(out);
+      if (c->ga.riemann == DFR_AUSM)
+        dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 1, float>), grid, block, lds, c->ga, c->ops, tx, ty, q, vf, vscale, eps, of, ar);
+      else
+        dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 0, float>), grid, block, lds, c->ga, c->ops, tx, ty, q, vf, vscale, eps, of, ar);
+      return;
+    }
+  }
+  const double *vd = static_cast<const double *>(v);
+  double *od = static_cast<double *>(out);
   if (c->ga.riemann == DFR_AUSM)
-    dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 1>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
+    dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 1, double>), grid, block, lds, c->ga, c->ops, tx, ty, q, vd, vscale, eps, od, ar);
   else
-    dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 0>), dim3((unsigned)nb), dim3(threads), lds, c->ga, c->ops, tx, ty, q, v, vscale, eps, out, ar);
+    dfr_launch(c, kind, (dfr_kernel<NS, T, TQ, CS, AR, 0, double>), grid, block, lds, c->ga, c->ops, tx, ty, q, vd, vscale, eps, od, ar);
 }
 
 template <int NS>
 static int set_lds_attr(size_t bytes) {
-  const void *fns[] = {(const void *)dfr_kernel<NS, double, double, false, false, 0>,
-                       (const void *)dfr_kernel<NS, double, double, true, false, 0>,
-                       (const void *)dfr_kernel<NS, float, float, true, false, 0>,
-                       (const void *)dfr_kernel<NS, double, double, true, true, 0>,
-                       (const void *)dfr_kernel<NS, float, float, true, true, 0>,
-                       (const void *)dfr_kernel<NS, double, double, false, false, 1>,
-                       (const void *)dfr_kernel<NS, double, double, true, false, 1>,
-                       (const void *)dfr_kernel<NS, float, float, true, false, 1>,
-                       (const void *)dfr_kernel<NS, double, double, true, true, 1>,
-                       (const void *)dfr_kernel<NS, float, float, true, true, 1>,
+  const void *fns[] = {(const void *)dfr_kernel<NS, double, double, false, false, 0, double>,
+                       (const void *)dfr_kernel<NS, double, double, true, false, 0, double>,
+                       (const void *)dfr_kernel<NS, float, float, true, false, 0, double>,
+                       (const void *)dfr_kernel<NS, double, double, true, true, 0, double>,
+                       (const void *)dfr_kernel<NS, float, float, true, true, 0, double>,
+                       (const void *)dfr_kernel<NS, float, float, true, true, 0, float>,
+                       (const void *)dfr_kernel<NS, double, double, false, false, 1, double>,
+                       (const void *)dfr_kernel<NS, double, double, true, false, 1, double>,
+                       (const void *)dfr_kernel<NS, float, float, true, false, 1, double>,
+                       (const void *)dfr_kernel<NS, double, double, true, true, 1, double>,
+                       (const void *)dfr_kernel<NS, float, float, true, true, 1, double>,
+                       (const void *)dfr_kernel<NS, float, float, true, true, 1, float>,
                        (const void *)dfr_kernel_batch<NS, double, double, false, false>,
                        (const void *)dfr_kernel_batch<NS, double, double, true, false>,
                        (const void *)dfr_kernel_batch<NS, float, float, true, false>,
@@ -1440,7 +1468,7 @@ int dfr_set_lds_limits(Ctx *c, size_t bytes) {
 }
 
 template <typename T, typename TQ, bool CS>
-static int dispatch_ns(Ctx *c, const TQ *q, const double *v, const double *vscale, double eps, double *out,
+static int dispatch_ns(Ctx *c, const TQ *q, const void *v, const double *vscale, double eps, void *out,
                        const ArnoldiArgs &ar) {
   switch (c->ns) {
     case 2: ar.on ? launch_ns<2, T, TQ, CS, CS>(c, q, v, vscale, eps, out, ar)
@@ -1463,8 +1491,8 @@ static int dispatch_ns(Ctx *c, const TQ *q, const double *v, const double *vscal
   return DFR_OK;
 }
 
-int launch_dfr(Ctx *c, const double *q, const float *q32, const double *v, const double *vscale, double eps,
-               bool complex_step, bool fp32, double *out, const ArnoldiArgs *ar) {
+int launch_dfr(Ctx *c, const double *q, const float *q32, const void *v, const double *vscale, double eps,
+               bool complex_step, bool fp32, void *out, const ArnoldiArgs *ar) {
   ArnoldiArgs none{};
   const ArnoldiArgs &a = ar ? *ar : none;
   if (!complex_step) return dispatch_ns<double, double, false>(c, q, nullptr, nullptr, 0.0, out, a);
@@ -1479,29 +1507,42 @@ static inline int grid_reduce(int64_t n) {
   return g < 1024 ? g : 1024;
 }
 
-int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, double *out, int *np_out) {
+int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, void *out, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);
-  dfr_launch(c, DFR_K_OTHER, arnoldi_first_kernel, dim3(nb), dim3(BLOCK), 0, n3, ar, out);
+  if (c->basis32)
+    dfr_launch(c, DFR_K_OTHER, arnoldi_first_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, ar, static_cast<float *>(out));
+  else
+    dfr_launch(c, DFR_K_OTHER, arnoldi_first_kernel<double>, dim3(nb), dim3(BLOCK), 0, n3, ar, static_cast<double *>(out));
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
 }
 
-int launch_update(Ctx *c, int j, double *w, const double *vj, const double *vprev, const double *pin, int np_in,
+int launch_update(Ctx *c, int j, void *w, const void *vj, const void *vprev, const double *pin, int np_in,
                   double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);
-  dfr_launch(c, DFR_K_UPDATE, arnoldi_update_kernel, dim3(nb), dim3(BLOCK), 0, n3, j, c->kiops_p, w, vj, vprev, pin, np_in, pout, c->d_kd);
+  if (c->basis32)
+    dfr_launch(c, DFR_K_UPDATE, arnoldi_update_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, j, c->kiops_p,
+               static_cast<float *>(w), static_cast<const float *>(vj), static_cast<const float *>(vprev), pin, np_in,
+               pout, c->d_kd);
+  else
+    dfr_launch(c, DFR_K_UPDATE, arnoldi_update_kernel<double>, dim3(nb), dim3(BLOCK), 0, n3, j, c->kiops_p,
+               static_cast<double *>(w), static_cast<const double *>(vj), static_cast<const double *>(vprev), pin,
+               np_in, pout, c->d_kd);
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
 }
 
-int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out) {
+int launch_start(Ctx *c, const double *x, void *v0, double *pout, int *np_out) {
   const int64_t n3 = 3 * c->n;
   const int nb = grid_reduce(n3);
-  dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel, dim3(nb), dim3(BLOCK), 0, n3, x, v0, pout);
+  if (c->basis32)
+    dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<float *>(v0), pout);
+  else
+    dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<double>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<double *>(v0), pout);
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
@@ -1509,7 +1550,12 @@ int launch_start(Ctx *c, const double *x, double *v0, double *pout, int *np_out)
 
 int launch_combine(Ctx *c, double *x) {
   const int64_t n3 = 3 * c->n;
-  dfr_launch(c, DFR_K_OTHER, arnoldi_combine_kernel, dim3(grid_for(n3)), dim3(BLOCK), 0, n3, c->d_V, n3, c->d_kd, x);
+  if (c->basis32)
+    dfr_launch(c, DFR_K_OTHER, arnoldi_combine_kernel<float>, dim3(grid_for(n3)), dim3(BLOCK), 0, n3,
+               reinterpret_cast<const float *>(c->d_V), n3, (const KDev *)c->d_kd, x);
+  else
+    dfr_launch(c, DFR_K_OTHER, arnoldi_combine_kernel<double>, dim3(grid_for(n3)), dim3(BLOCK), 0, n3,
+               (const double *)c->d_V, n3, (const KDev *)c->d_kd, x);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

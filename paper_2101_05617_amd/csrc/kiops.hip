@@ -135,7 +135,7 @@ void km_arnoldi_args(const KiopsMachine &k, const kiops_opts &o, ArnoldiArgs &ar
     ar.W[i] = c.d_W + i * n3;
     ar.ybot[i] = k.ybot[i];
   }
-  ar.vprev = (k.j >= 1 && o.iop >= 2) ? c.d_V + (int64_t)(k.j - 1) * n3 : nullptr;
+  ar.vprev = (k.j >= 1 && o.iop >= 2) ? c.vslot(k.j - 1) : nullptr;
   ar.pin = c.d_partials2;
   ar.np_in = k.npB;
   ar.pout = c.d_partials;
@@ -227,11 +227,18 @@ int km_decide(KiopsMachine &k, const KHost &r, const kiops_opts &o, bool *accept
   return DFR_OK;
 }
 
+// basis32: the basis vectors are kept in FP32 (the FP32 form only); inner
+// products, norms, the Hessenberg and the combination stay FP64
 static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out, int n_phi, const double *const *b,
-                      const kiops_opts &o, double eps, bool fp32, double *w, KiopsRun &st) {
+                      const kiops_opts &o, double eps, bool fp32, bool basis32, double *w, KiopsRun &st) {
   const int64_t n3 = 3 * c.n;
   int rc = kiops_validate(c, o, n_phi, tau_out);
   if (rc) return rc;
+  struct BasisMode {
+    Ctx &c;
+    BasisMode(Ctx &cc, bool b32) : c(cc) { c.basis32 = b32; }
+    ~BasisMode() { c.basis32 = false; }
+  } mode(c, fp32 && basis32);
   KiopsMachine k;
   k.c = &c;
   k.q = q;
@@ -263,28 +270,27 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
   rc = launch_axpby(&c, n3, 1.0, b[0], 0.0, nullptr, w);
   if (rc) return rc;
 
-  double *V = c.d_V;
   double *pA = c.d_partials, *pB = c.d_partials2;
   while (k.phase != KiopsMachine::DONE) {
     rc = km_begin_attempt(k, o);
     if (rc) return rc;
     if (k.need_start) {
-      rc = launch_start(&c, w, V, pB, &k.npB);
+      rc = launch_start(&c, w, c.vslot(0), pB, &k.npB);
       if (rc) return rc;
     }
     while (k.j < k.m) {
       ArnoldiArgs ar;
       km_arnoldi_args(k, o, ar);
-      double *out = V + (int64_t)(k.j + 1) * n3;
+      void *out = c.vslot(k.j + 1);
       if (k.j == 0 && k.t == 0.0 && k.b0_absent) {
         rc = launch_arnoldi_first(&c, ar, out, &k.npA);
         k.skipped = true;
       } else {
-        rc = launch_dfr(&c, q, q32, V + (int64_t)k.j * n3, nullptr, eps, true, fp32, out, &ar);
+        rc = launch_dfr(&c, q, q32, c.vslot(k.j), nullptr, eps, true, fp32, out, &ar);
         k.npA = (int)dfr_num_tiles(&c, true);
       }
       if (rc) return rc;
-      rc = launch_update(&c, k.j, out, V + (int64_t)k.j * n3, ar.vprev, pA, k.npA, pB, &k.npB);
+      rc = launch_update(&c, k.j, out, c.vslot(k.j), ar.vprev, pA, k.npA, pB, &k.npB);
       if (rc) return rc;
       ++k.j;
     }
@@ -380,7 +386,8 @@ extern "C" {
 
 int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, const double *const *b, const kiops_opts *o,
                     double eps, dfr_precision prec, double *w, kiops_stats *stats) {
-  if (!h || !q || !b || !o || !w || !(eps > 0.0) || (prec != DFR_FP64 && prec != DFR_FP32_JV)) {
+  if (!h || !q || !b || !o || !w || !(eps > 0.0) ||
+      (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
     set_error("kiops_phi_apply: invalid argument");
     return DFR_E_INVAL;
   }
@@ -392,11 +399,11 @@ int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, cons
   Ctx &c = h->c;
   int rc = launch_check_state(&c, q);
   if (rc) return rc;
-  const bool fp32 = prec == DFR_FP32_JV;
+  const bool fp32 = prec != DFR_FP64;
   const float *q32 = prep_q32(c, q, fp32, rc);
   if (rc) return rc;
   KiopsRun r;
-  rc = kiops_core(c, q, q32, tau_out, n_phi, b, *o, eps, fp32, w, r);
+  rc = kiops_core(c, q, q32, tau_out, n_phi, b, *o, eps, fp32, prec == DFR_FP32_JV_BASIS32, w, r);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     add_stats(stats, r);
@@ -406,7 +413,8 @@ int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, cons
 
 int epi_create(dfr_ctx *h, int order, double dt, int startup_substeps, const double *q0, double eps, dfr_precision prec,
                epi_state **out) {
-  if (!h || !q0 || !out || order < 2 || order > 6 || !(dt > 0.0) || startup_substeps < 1 || !(eps > 0.0)) {
+  if (!h || !q0 || !out || order < 2 || order > 6 || !(dt > 0.0) || startup_substeps < 1 || !(eps > 0.0) ||
+      (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
     set_error("epi_create: invalid argument");
     return DFR_E_INVAL;
   }
@@ -483,7 +491,8 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
   }
   Ctx &c = h->c;
   const int64_t n3 = 3 * c.n;
-  const bool fp32 = st->prec == DFR_FP32_JV;
+  const bool fp32 = st->prec != DFR_FP64;
+  const bool basis32 = st->prec == DFR_FP32_JV_BASIS32;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   int rc = launch_check_state(&c, st->q);
   if (rc) return rc;
@@ -506,7 +515,7 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
       if (rc) return rc;
       const double *bb[2] = {nullptr, Fs};
       KiopsRun r;
-      rc = kiops_core(c, st->qs, q32, hstep, 1, bb, *o, st->eps, fp32, st->w, r);
+      rc = kiops_core(c, st->qs, q32, hstep, 1, bb, *o, st->eps, fp32, basis32, st->w, r);
       add_stats(stats, r);
       if (rc) return rc;
       rc = launch_axpby(&c, n3, 1.0, st->qs, 1.0, st->w, st->qs);
@@ -543,7 +552,7 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
       bb[m] = bm;
     }
     KiopsRun r;
-    rc = kiops_core(c, st->q, q32, st->dt, st->M, bb.data(), *o, st->eps, fp32, st->w, r);
+    rc = kiops_core(c, st->q, q32, st->dt, st->M, bb.data(), *o, st->eps, fp32, basis32, st->w, r);
     add_stats(stats, r);
     if (rc) return rc;
     rc = launch_axpby(&c, n3, 1.0, st->q, 1.0, st->w, st->qs);

@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libdfrsw.so")
 
 DFR_FP64 = 0
 DFR_FP32_JV = 1
-_PREC = {"fp64": DFR_FP64, "fp32_jv": DFR_FP32_JV, DFR_FP64: DFR_FP64, DFR_FP32_JV: DFR_FP32_JV}
+DFR_FP32_JV_BASIS32 = 2
+_PREC = {"fp64": DFR_FP64, "fp32_jv": DFR_FP32_JV, "fp32_jv_basis32": DFR_FP32_JV_BASIS32,
+         DFR_FP64: DFR_FP64, DFR_FP32_JV: DFR_FP32_JV, DFR_FP32_JV_BASIS32: DFR_FP32_JV_BASIS32}
 
 ERRORS = {-1: "DFR_E_INVAL", -2: "DFR_E_NOMEM", -3: "DFR_E_HIP", -4: "DFR_E_NONFINITE", -5: "DFR_E_DEPTH",
           -6: "DFR_E_KIOPS"}
