@@ -188,6 +188,19 @@ int epi_get_state(const epi_state *st, double *q);
 /* Number of steps taken. */
 int64_t epi_num_steps(const epi_state *st);
 int epi_destroy(epi_state *st);
+/* Checkpoint and restart of an EPI integration.  epi_save writes to a host
+ * buffer everything the next steps depend on: order, dt, start-up sub-steps,
+ * eps, precision, step count, the grid's shape (ne, p), q_n and the history
+ * q_{n-i}, F(q_{n-i}) that later steps read (Eq. 33), all as raw FP64 in the
+ * library's layout behind a versioned header.  With host_buf NULL it only
+ * stores the size needed in *nbytes; otherwise *nbytes is the buffer size on
+ * entry and the bytes written on return (DFR_E_INVAL if too small).
+ * Synchronises the stream.  epi_load makes a new state on ctx from such a
+ * buffer (DFR_E_INVAL if the header or the size is wrong or the grid's ne, p
+ * differ); continuing from it gives the results of the uninterrupted run,
+ * bit for bit, on the same kind of device. */
+int epi_save(const epi_state *st, void *host_buf, size_t *nbytes);
+int epi_load(dfr_ctx *ctx, const void *host_buf, size_t nbytes, epi_state **out);
 
 /* Ensembles (many independent grids, e.g. an ensemble of small forecasts).
  *

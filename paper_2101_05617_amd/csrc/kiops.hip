@@ -477,6 +477,113 @@ int epi_destroy(epi_state *st) {
 
 int64_t epi_num_steps(const epi_state *st) { return st ? st->nsteps : -1; }
 
+// checkpoint layout: header, then q_n, then (q_{n-i}, F_{n-i}) for the
+// history entries in use, i = 1..min(nsteps, P), each 3N doubles
+namespace {
+struct EpiCkptHeader {
+  char magic[8];          // "DFREPI01"
+  int32_t order, s, prec, ne, p, nhist;
+  int64_t nsteps, n;
+  double dt, eps;
+};
+constexpr char kCkptMagic[8] = {'D', 'F', 'R', 'E', 'P', 'I', '0', '1'};
+}  // namespace
+
+int epi_save(const epi_state *st, void *buf, size_t *nbytes) {
+  if (!st || !nbytes) {
+    set_error("epi_save: invalid argument");
+    return DFR_E_INVAL;
+  }
+  Ctx &c = *st->c;
+  const int nh = (int)std::min<int64_t>(st->nsteps, st->P);
+  const size_t vec = sizeof(double) * 3 * c.n;
+  const size_t need = sizeof(EpiCkptHeader) + vec * (1 + 2 * (size_t)nh);
+  if (!buf) {
+    *nbytes = need;
+    return DFR_OK;
+  }
+  if (*nbytes < need) {
+    set_error("epi_save: buffer too small");
+    return DFR_E_INVAL;
+  }
+  EpiCkptHeader hd{};
+  std::memcpy(hd.magic, kCkptMagic, 8);
+  hd.order = st->order;
+  hd.s = st->s;
+  hd.prec = (int32_t)st->prec;
+  hd.ne = c.ne;
+  hd.p = c.p_deg;
+  hd.nhist = nh;
+  hd.nsteps = st->nsteps;
+  hd.n = c.n;
+  hd.dt = st->dt;
+  hd.eps = st->eps;
+  char *b = static_cast<char *>(buf);
+  std::memcpy(b, &hd, sizeof(hd));
+  b += sizeof(hd);
+  DFR_HIP(hipStreamSynchronize(c.stream));
+  DFR_HIP(hipMemcpy(b, st->q, vec, hipMemcpyDeviceToHost));
+  b += vec;
+  for (int i = 0; i < nh; ++i) {
+    DFR_HIP(hipMemcpy(b, st->hq[i], vec, hipMemcpyDeviceToHost));
+    b += vec;
+    DFR_HIP(hipMemcpy(b, st->hF[i], vec, hipMemcpyDeviceToHost));
+    b += vec;
+  }
+  *nbytes = need;
+  return DFR_OK;
+}
+
+int epi_load(dfr_ctx *h, const void *buf, size_t nbytes, epi_state **out) {
+  if (!h || !buf || !out || nbytes < sizeof(EpiCkptHeader)) {
+    set_error("epi_load: invalid argument");
+    return DFR_E_INVAL;
+  }
+  *out = nullptr;
+  Ctx &c = h->c;
+  EpiCkptHeader hd;
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0) {
+    set_error("epi_load: not an EPI checkpoint of this version");
+    return DFR_E_INVAL;
+  }
+  if (hd.ne != c.ne || hd.p != c.p_deg || hd.n != c.n) {
+    set_error("epi_load: the checkpoint is of another grid (ne, p)");
+    return DFR_E_INVAL;
+  }
+  const size_t vec = sizeof(double) * 3 * c.n;
+  const int P = hd.order == 2 ? 0 : hd.order - 2;
+  if (hd.nhist < 0 || hd.nhist != (int)std::min<int64_t>(hd.nsteps, P) ||
+      nbytes != sizeof(hd) + vec * (1 + 2 * (size_t)hd.nhist)) {
+    set_error("epi_load: inconsistent checkpoint size or history");
+    return DFR_E_INVAL;
+  }
+  const char *b = static_cast<const char *>(buf) + sizeof(hd);
+  // a state with the saved parameters (q_n copied in by epi_create)
+  DFR_HIP(hipMemcpyAsync(c.d_tmp, b, vec, hipMemcpyHostToDevice, c.stream));
+  epi_state *st = nullptr;
+  int rc = epi_create(h, hd.order, hd.dt, hd.s, c.d_tmp, hd.eps, (dfr_precision)hd.prec, &st);
+  if (rc) return rc;
+  b += vec;
+  for (int i = 0; i < hd.nhist; ++i) {
+    if (hipMemcpyAsync(st->hq[i], b, vec, hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+        hipMemcpyAsync(st->hF[i], b + vec, vec, hipMemcpyHostToDevice, c.stream) != hipSuccess) {
+      epi_destroy(st);
+      set_error("epi_load: copy failed");
+      return DFR_E_HIP;
+    }
+    b += 2 * vec;
+  }
+  st->nsteps = hd.nsteps;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) {
+    epi_destroy(st);
+    set_error("epi_load: copy failed");
+    return DFR_E_HIP;
+  }
+  *out = st;
+  return DFR_OK;
+}
+
 int epi_get_state(const epi_state *st, double *q) {
   if (!st || !q) return DFR_E_INVAL;
   Ctx &c = *st->c;

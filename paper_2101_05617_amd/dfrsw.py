@@ -82,6 +82,8 @@ def lib():
             "epi_get_state": (i, [vp, vp]),
             "epi_num_steps": (i64, [vp]),
             "epi_destroy": (i, [vp]),
+            "epi_save": (i, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
+            "epi_load": (i, [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
             "epi_step_concurrent": (i, [i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(KiopsOpts), i,
                                         ctypes.POINTER(KiopsStats)]),
             "dfr_ensemble_create": (i, [i, ctypes.POINTER(_GridDesc), vp, ctypes.POINTER(vp)]),
@@ -115,7 +117,7 @@ def lib():
 def exported_symbols():
     return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
-            "epi_num_steps", "epi_destroy", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
+            "epi_num_steps", "epi_destroy", "epi_save", "epi_load", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
             "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_diagnostics", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_last_error"]
@@ -208,8 +210,11 @@ def kiops_phi_apply(g: Grid, q_lin, tau_out, bs, opts=None, eps=1e-150, prec="fp
 class EpiState:
     """An epi_state: multistep EPI integrator with its history on the GPU."""
 
-    def __init__(self, g: Grid, order, dt, q0, startup_substeps=10, eps=1e-150, prec="fp64"):
+    def __init__(self, g: Grid, order, dt, q0, startup_substeps=10, eps=1e-150, prec="fp64", _handle=None):
         self.g = g
+        if _handle is not None:
+            self._h = _handle
+            return
         h = ctypes.c_void_p()
         _check(lib().epi_create(g.handle, int(order), float(dt), int(startup_substeps), _dev(q0), float(eps),
                                 _PREC[prec], ctypes.byref(h)))
@@ -229,6 +234,23 @@ class EpiState:
     @property
     def handle(self):
         return self._h
+
+
+def epi_save(st: EpiState) -> bytes:
+    """Checkpoint of an EPI integration (host bytes)."""
+    n = ctypes.c_size_t(0)
+    _check(lib().epi_save(st.handle, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().epi_save(st.handle, buf, ctypes.byref(n)))
+    return buf.raw[: n.value]
+
+
+def epi_load(g: Grid, data: bytes) -> EpiState:
+    """A new EPI state on grid g from a checkpoint made by epi_save."""
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    h = ctypes.c_void_p()
+    _check(lib().epi_load(g.handle, buf, len(data), ctypes.byref(h)))
+    return EpiState(g, 0, 0.0, None, _handle=h)
 
 
 KERNEL_KINDS = {"jv_arnoldi": 0, "jv": 1, "rhs": 2, "update": 3, "expm": 4, "other": 5, "finalize": 6}
