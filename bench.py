@@ -448,6 +448,16 @@ def large_dt_study(steps):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline_leg(workload_name):
     """Time the oracle on this host: one steady-state EPI step after the
     start-up steps (untimed, one EPI2 sub-step each)."""
@@ -473,7 +483,23 @@ def cpu_baseline_leg(workload_name):
     for _ in range(10):
         G.jvp(Q, V, w.eps)
     tj = (time.perf_counter() - t1) / 10
-    return {"step_s": dt, "jv_s": tj, "n_matvec": st.n_matvec}
+    out = {"step_s": dt, "jv_s": tj, "n_matvec": st.n_matvec}
+    del G, E
+    # the product alone on the two largest grids (one call after one untimed)
+    for key, name in (("jv_s_c2", "c2_ne60_p6_jet"), ("jv_s_c4", "c4_ne120_p6_mountain")):
+        wk = inputs.WORKLOADS[name]
+        G0 = oracle.OracleGrid(wk.ne, wk.ns, *wk.constants())
+        P, B1, B2 = G0.node_frames()
+        del G0
+        Qk, hB = inputs.initial_state(wk, P, B1, B2)
+        Gk = oracle.OracleGrid(wk.ne, wk.ns, *wk.constants(), hB=hB)
+        Vk = np.random.default_rng(1).standard_normal(3 * Gk.N) * 1e-3
+        Gk.jvp(Qk, Vk, 1e-150)
+        t1 = time.perf_counter()
+        Gk.jvp(Qk, Vk, 1e-150)
+        out[key] = time.perf_counter() - t1
+        del Gk, Qk, Vk, P, B1, B2
+    return out
 
 
 def jv_only(w, args):
@@ -729,21 +755,36 @@ def main():
     if not args.no_large_dt:
         out["large_dt"] = large_dt_study(4)
 
-    # ---- the oracle on this host's cores (bounded sample, one thread)
+    # ---- the oracle on this host's cores (bounded sample): one thread, then
+    # every thread of this host's share (its element loop runs under OpenMP)
     if not args.no_cpu_baseline:
-        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-        log("cpu baseline: oracle, one thread")
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
-                            "--workload", args.workload], capture_output=True, text=True, env=env, timeout=900)
-        if r.returncode == 0:
-            cb = json.loads(r.stdout.strip().splitlines()[-1])
+        legs = {}
+        n_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        for nt in (1, n_all):
+            env = dict(os.environ, OMP_NUM_THREADS=str(nt), OPENBLAS_NUM_THREADS=str(nt), MKL_NUM_THREADS=str(nt))
+            log(f"cpu baseline: oracle, {nt} thread(s)")
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                                "--workload", args.workload], capture_output=True, text=True, env=env, timeout=900)
+            if r.returncode != 0:
+                log("cpu baseline failed: " + r.stderr[-2000:])
+                break
+            legs[nt] = json.loads(r.stdout.strip().splitlines()[-1])
+        if 1 in legs:
+            cb = legs[1]
             out["cpu_baseline"] = {"value": 1.0 / cb["step_s"], "unit": "EPI steps/s", "cores": 1, "kind": "oracle",
                                    "sample": f"one EPI{w.order} step of {w.name} after {P_hist} untimed EPI2 "
                                              f"start-up steps ({cb['n_matvec']} J*v); J*v alone "
                                              f"{cb['jv_s'] * 1e3:.1f} ms",
-                                   "jv_per_s": 1.0 / cb["jv_s"]}
+                                   "jv_per_s": 1.0 / cb["jv_s"],
+                                   "jv_per_s_c2_ne60_p6": 1.0 / cb["jv_s_c2"],
+                                   "jv_per_s_c4_ne120_p6": 1.0 / cb["jv_s_c4"],
+                                   "cpu": cpu_model()}
+            if n_all in legs and n_all != 1:
+                cm = legs[n_all]
+                out["cpu_baseline"]["all_threads"] = {
+                    "value": 1.0 / cm["step_s"], "cores": n_all, "jv_per_s": 1.0 / cm["jv_s"],
+                    "jv_per_s_c2_ne60_p6": 1.0 / cm["jv_s_c2"], "jv_per_s_c4_ne120_p6": 1.0 / cm["jv_s_c4"]}
         else:
-            log("cpu baseline failed: " + r.stderr[-2000:])
             out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
     return 0

@@ -25,8 +25,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dfr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-# plain build: no FMA contraction, no fast-math, so every operation is the one written
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+# plain build: no FMA contraction, no fast-math, so every operation is the one written;
+# OpenMP only splits the element loop of the right-hand side (OMP_NUM_THREADS)
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force: bool = True) -> str:

@@ -618,86 +618,90 @@ static void face_flux(const orc_grid *G, const cplx *Q, int p, int ej, int ei, i
   else common_flux(G, qo, qn, m.sg, h, n, Fs);
 }
 
-/* Complex right-hand side dQ/dt = F(Q) for Q = (H, H u^1, H u^2).           */
+/* The right-hand side at the nodes of element (p, ej, ei).                 */
+static void element_rhs(const orc_grid *G, const cplx *Q, cplx *dQ, int p, int ej, int ei) {
+  int ns = G->ns;
+  int64_t N = orc_num_nodes(G);
+  double D = orc_delta(G);
+  cplx F1[3 * ORC_MAXNS * ORC_MAXNS], F2[3 * ORC_MAXNS * ORC_MAXNS];
+  cplx FW[3 * ORC_MAXNS], FE[3 * ORC_MAXNS], FS[3 * ORC_MAXNS], FN[3 * ORC_MAXNS];
+  /* nodal fluxes sqrt(g) T^{mu j} (Eq. 136) */
+  for (int nj = 0; nj < ns; ++nj)
+    for (int ni = 0; ni < ns; ++ni) {
+      double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
+      metric_t m = metric_at(G, X, Y);
+      double h[2][2] = { { m.h11, m.h12 }, { m.h12, m.h22 } };
+      cplx q[3];
+      for (int f = 0; f < 3; ++f) q[f] = m.sg * Q[orc_idx(G, f, p, ej, ei, nj, ni)];
+      cplx f1[3], f2[3];
+      normal_flux(G, q, m.sg, h, 0, f1);
+      normal_flux(G, q, m.sg, h, 1, f2);
+      for (int f = 0; f < 3; ++f) {
+        F1[(f * ns + nj) * ns + ni] = f1[f];
+        F2[(f * ns + nj) * ns + ni] = f2[f];
+      }
+    }
+  /* common fluxes at the four faces */
+  for (int t = 0; t < ns; ++t) {
+    face_flux(G, Q, p, ej, ei, EW, t, FW + 3 * t);
+    face_flux(G, Q, p, ej, ei, EE, t, FE + 3 * t);
+    face_flux(G, Q, p, ej, ei, ES, t, FS + 3 * t);
+    face_flux(G, Q, p, ej, ei, EN, t, FN + 3 * t);
+  }
+  /* derivative of the continuous flux polynomial (Eqs. 12, 14) and sources */
+  for (int nj = 0; nj < ns; ++nj)
+    for (int ni = 0; ni < ns; ++ni) {
+      double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
+      metric_t m = metric_at(G, X, Y);
+      double h[2][2] = { { m.h11, m.h12 }, { m.h12, m.h22 } };
+      double c0[2][2], csy[2][2][2];
+      christoffel_at(G, p, X, Y, c0, csy);
+      cplx q[3];
+      for (int f = 0; f < 3; ++f) q[f] = m.sg * Q[orc_idx(G, f, p, ej, ei, nj, ni)];
+      int64_t n0 = orc_idx(G, 0, p, ej, ei, nj, ni);
+      for (int f = 0; f < 3; ++f) {
+        /* x^1 direction: extended points {W face, row nodes, E face} */
+        cplx d1 = G->Dt[ni][0] * FW[3 * nj + f] + G->Dt[ni][ns + 1] * FE[3 * nj + f];
+        for (int k = 0; k < ns; ++k) d1 += G->Dt[ni][k + 1] * F1[(f * ns + nj) * ns + k];
+        cplx d2 = G->Dt[nj][0] * FS[3 * ni + f] + G->Dt[nj][ns + 1] * FN[3 * ni + f];
+        for (int k = 0; k < ns; ++k) d2 += G->Dt[nj][k + 1] * F2[(f * ns + k) * ns + ni];
+        cplx rhs = -(2.0 / D) * (d1 + d2);
+        if (f > 0) {
+          int i = f - 1;
+          /* Coriolis: -2 sqrt(g) Gamma^i_{j0} H u^j = -2 Gamma^i_{0j} q^j */
+          cplx src = 0.0;
+          for (int j = 0; j < 2; ++j) src += -2.0 * c0[i][j] * q[1 + j];
+          /* metric: -sqrt(g) Gamma^i_jk (H u^j u^k + g h^jk H^2 / 2) */
+          for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k)
+              src += -csy[i][j][k] * (q[1 + j] * q[1 + k] / q[0] + 0.5 * G->g * h[j][k] * q[0] * q[0] / m.sg);
+          /* orography: -sqrt(g) H g h^ij dh_B/dx^j */
+          if (G->dhb)
+            for (int j = 0; j < 2; ++j) src += -q[0] * G->g * h[i][j] * G->dhb[(int64_t)j * N + n0];
+          rhs += src;
+        }
+        dQ[(int64_t)f * N + n0] = rhs / m.sg;
+      }
+    }
+}
+
+/* Complex right-hand side dQ/dt = F(Q) for Q = (H, H u^1, H u^2).  Elements
+   are independent (each writes only its own nodes), so the loop over them
+   may run on several threads (OpenMP, OMP_NUM_THREADS) with results that do
+   not depend on the thread count. */
 int orc_rhs_complex(const orc_grid *G, const cplx *Q, cplx *dQ) {
-  int ne = G->ne, ns = G->ns;
+  int ne = G->ne;
   int64_t N = orc_num_nodes(G);
   for (int64_t i = 0; i < 3 * N; ++i)
     if (!isfinite(creal(Q[i])) || !isfinite(cimag(Q[i]))) return ORC_ENONFINITE;
   for (int64_t i = 0; i < N; ++i)
     if (!(creal(Q[i]) > 0.0)) return ORC_EDEPTH;
-  double D = orc_delta(G);
-  cplx *F1 = (cplx *)malloc(sizeof(cplx) * 3 * ns * ns);
-  cplx *F2 = (cplx *)malloc(sizeof(cplx) * 3 * ns * ns);
-  cplx *FW = (cplx *)malloc(sizeof(cplx) * 3 * ns), *FE = (cplx *)malloc(sizeof(cplx) * 3 * ns);
-  cplx *FS = (cplx *)malloc(sizeof(cplx) * 3 * ns), *FN = (cplx *)malloc(sizeof(cplx) * 3 * ns);
-  if (!F1 || !F2 || !FW || !FE || !FS || !FN) {
-    free(F1); free(F2); free(FW); free(FE); free(FS); free(FN);
-    return ORC_ENOMEM;
+  int64_t nel = 6LL * ne * ne;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < nel; ++e) {
+    int ei = (int)(e % ne), ej = (int)((e / ne) % ne), p = (int)(e / ((int64_t)ne * ne));
+    element_rhs(G, Q, dQ, p, ej, ei);
   }
-  for (int p = 0; p < 6; ++p)
-    for (int ej = 0; ej < ne; ++ej)
-      for (int ei = 0; ei < ne; ++ei) {
-        /* nodal fluxes sqrt(g) T^{mu j} (Eq. 136) */
-        for (int nj = 0; nj < ns; ++nj)
-          for (int ni = 0; ni < ns; ++ni) {
-            double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
-            metric_t m = metric_at(G, X, Y);
-            double h[2][2] = { { m.h11, m.h12 }, { m.h12, m.h22 } };
-            cplx q[3];
-            for (int f = 0; f < 3; ++f) q[f] = m.sg * Q[orc_idx(G, f, p, ej, ei, nj, ni)];
-            cplx f1[3], f2[3];
-            normal_flux(G, q, m.sg, h, 0, f1);
-            normal_flux(G, q, m.sg, h, 1, f2);
-            for (int f = 0; f < 3; ++f) {
-              F1[(f * ns + nj) * ns + ni] = f1[f];
-              F2[(f * ns + nj) * ns + ni] = f2[f];
-            }
-          }
-        /* common fluxes at the four faces */
-        for (int t = 0; t < ns; ++t) {
-          face_flux(G, Q, p, ej, ei, EW, t, FW + 3 * t);
-          face_flux(G, Q, p, ej, ei, EE, t, FE + 3 * t);
-          face_flux(G, Q, p, ej, ei, ES, t, FS + 3 * t);
-          face_flux(G, Q, p, ej, ei, EN, t, FN + 3 * t);
-        }
-        /* derivative of the continuous flux polynomial (Eqs. 12, 14) and sources */
-        for (int nj = 0; nj < ns; ++nj)
-          for (int ni = 0; ni < ns; ++ni) {
-            double X = tan(node_x(G, ei, ni)), Y = tan(node_x(G, ej, nj));
-            metric_t m = metric_at(G, X, Y);
-            double h[2][2] = { { m.h11, m.h12 }, { m.h12, m.h22 } };
-            double c0[2][2], csy[2][2][2];
-            christoffel_at(G, p, X, Y, c0, csy);
-            cplx q[3];
-            for (int f = 0; f < 3; ++f) q[f] = m.sg * Q[orc_idx(G, f, p, ej, ei, nj, ni)];
-            int64_t n0 = orc_idx(G, 0, p, ej, ei, nj, ni);
-            for (int f = 0; f < 3; ++f) {
-              /* x^1 direction: extended points {W face, row nodes, E face} */
-              cplx d1 = G->Dt[ni][0] * FW[3 * nj + f] + G->Dt[ni][ns + 1] * FE[3 * nj + f];
-              for (int k = 0; k < ns; ++k) d1 += G->Dt[ni][k + 1] * F1[(f * ns + nj) * ns + k];
-              cplx d2 = G->Dt[nj][0] * FS[3 * ni + f] + G->Dt[nj][ns + 1] * FN[3 * ni + f];
-              for (int k = 0; k < ns; ++k) d2 += G->Dt[nj][k + 1] * F2[(f * ns + k) * ns + ni];
-              cplx rhs = -(2.0 / D) * (d1 + d2);
-              if (f > 0) {
-                int i = f - 1;
-                /* Coriolis: -2 sqrt(g) Gamma^i_{j0} H u^j = -2 Gamma^i_{0j} q^j */
-                cplx src = 0.0;
-                for (int j = 0; j < 2; ++j) src += -2.0 * c0[i][j] * q[1 + j];
-                /* metric: -sqrt(g) Gamma^i_jk (H u^j u^k + g h^jk H^2 / 2) */
-                for (int j = 0; j < 2; ++j)
-                  for (int k = 0; k < 2; ++k)
-                    src += -csy[i][j][k] * (q[1 + j] * q[1 + k] / q[0] + 0.5 * G->g * h[j][k] * q[0] * q[0] / m.sg);
-                /* orography: -sqrt(g) H g h^ij dh_B/dx^j */
-                if (G->dhb)
-                  for (int j = 0; j < 2; ++j) src += -q[0] * G->g * h[i][j] * G->dhb[(int64_t)j * N + n0];
-                rhs += src;
-              }
-              dQ[(int64_t)f * N + n0] = rhs / m.sg;
-            }
-          }
-      }
-  free(F1); free(F2); free(FW); free(FE); free(FS); free(FN);
   return ORC_OK;
 }
 
