@@ -1500,11 +1500,15 @@ int launch_dfr(Ctx *c, const double *q, const float *q32, const void *v, const d
   return dispatch_ns<double, double, true>(c, q, v, vscale, eps, out, a);
 }
 
+// workgroups of the vector kernels whose partial sums the next kernel
+// reduces (in every one of its workgroups): at most DFR_REDUCE_BLOCKS
+#ifndef DFR_REDUCE_BLOCKS
+#define DFR_REDUCE_BLOCKS 1024
+#endif
+static_assert(DFR_REDUCE_BLOCKS <= 1024, "the prologue reductions take at most 1024 partial sums");
 static inline int grid_reduce(int64_t n) {
-  // vector kernels whose partial sums are consumed by the next kernel use at
-  // most 1024 workgroups (grid-stride loops)
   const int g = grid_for(n);
-  return g < 1024 ? g : 1024;
+  return g < DFR_REDUCE_BLOCKS ? g : DFR_REDUCE_BLOCKS;
 }
 
 int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, void *out, int *np_out) {
