@@ -12,6 +12,7 @@ Layout of the package:
   phi.py        scalar phi-functions and the dense augmented-matrix reference
   kiops.py      adaptive Krylov phi-combination with incomplete orthogonalisation
   epi.py        multistep EPI2..EPI6 integrators with the EPI2 start-up
+  ode.py        the stiff ODE test problems of Sec. 5.1 (numpy)
 """
 from __future__ import annotations
 

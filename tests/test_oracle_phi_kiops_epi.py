@@ -10,7 +10,7 @@ import scipy.integrate
 import scipy.linalg
 
 import oracle
-from oracle import epi, kiops, phi
+from oracle import epi, kiops, ode, phi
 from paper_2101_05617_amd import inputs
 
 
@@ -171,24 +171,9 @@ def test_epi_is_exact_for_affine_problems():
 
 
 def _semilinear(n=400):
-    """Sec. 5.1 semilinear parabolic problem, u = x(1-x) e^t exact, FD2 +
-    trapezoid integral, written as an autonomous system with time appended.
-    The forcing uses the discrete trapezoid value of int x(1-x) so that
-    x(1-x) e^t solves the semi-discrete system exactly."""
-    x = np.linspace(0, 1, n + 2)[1:-1]
-    h = 1.0 / (n + 1)
-    A = (np.diag(-2 * np.ones(n)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)) / h ** 2
-    wt = np.full(n, h)
-    Id = wt @ (x * (1 - x))
-    src = x - x * x + 2 - Id
-
-    def rhs(q):
-        return np.concatenate([A @ q[:-1] + wt @ q[:-1] + np.exp(q[-1]) * src, [1.0]])
-
-    def jvp(q, v):
-        return np.concatenate([A @ v[:-1] + wt @ v[:-1] + v[-1] * np.exp(q[-1]) * src, [0.0]])
-
-    exact = lambda t: np.concatenate([x * (1 - x) * np.exp(t), [t]])
+    """Sec. 5.1 semilinear parabolic problem (oracle/ode.py), u = x(1-x) e^t
+    exact, with time appended as a last unknown."""
+    rhs, jvp, _, exact = ode.semilinear(n)
     return rhs, jvp, exact
 
 
