@@ -96,6 +96,28 @@ int dfr_create(const dfr_grid_desc *desc, void *hip_stream, dfr_ctx **out);
 int dfr_destroy(dfr_ctx *ctx);
 /* N = 6 ne^2 (p+1)^2 */
 int64_t dfr_num_nodes(const dfr_ctx *ctx);
+
+/* The stiff test problems of Sec. 5.1 on the same KIOPS / EPI path: a
+ * context that holds a semi-discrete ODE system du/dt = F(u) instead of a
+ * grid, with second-order finite differences and the paper's constants.
+ *   DFR_ODE_ADR: u_t + alpha (u_x + u_y) = eps (u_xx + u_yy) + gamma u (u -
+ *     1/2)(1 - u) on [0,1]^2 (eps 1/100, alpha -10, gamma 100), homogeneous
+ *     Neumann by reflection, on an n x n vertex grid (n^2 unknowns, index
+ *     j n + i with i along x; 3 <= n <= 256).
+ *   DFR_ODE_BURGERS: u_t + (u^2/2)_x = eps u_xx on [0,1] (eps 1e-3), u = 0
+ *     at both ends, n interior points (the flux difference as (u_{i+1}^2 -
+ *     u_{i-1}^2)/(4h)).
+ *   DFR_ODE_SEMILINEAR: u_t - u_xx = int_0^1 u dx + phi(x, t), u = 0 at both
+ *     ends, n interior points, trapezoid integral, phi such that x(1-x) e^t
+ *     solves the discrete system; unknown n is the time t (n + 1 unknowns).
+ * dfr_rhs gives F(u); dfr_jvp_complex_step gives the exact J(u) v (eps is
+ * ignored; DFR_FP64 only); kiops_phi_apply and the epi_* calls run as on a
+ * grid, in FP64 (epi_step_concurrent too).  The grid-only calls (node
+ * frames, tiles, Riemann solver, diagnostics) return DFR_E_INVAL on such a
+ * context.  Vectors have dfr_num_unknowns(ctx) doubles (3N on a grid). */
+typedef enum { DFR_ODE_ADR = 1, DFR_ODE_BURGERS = 2, DFR_ODE_SEMILINEAR = 3 } dfr_ode_problem;
+int dfr_create_ode(int problem, int n, void *hip_stream, dfr_ctx **out);
+int64_t dfr_num_unknowns(const dfr_ctx *ctx);
 /* Per node: unit position P and the coordinate basis dP/dx^1, dP/dx^2 on the
  * unit sphere (3 doubles each, node order as above).  Host outputs of size 3N. */
 int dfr_node_frames(const dfr_ctx *ctx, double *host_P, double *host_B1, double *host_B2);

@@ -401,7 +401,7 @@ static void default_tile(Ctx &c) {
 }
 
 static int alloc_workspace(Ctx &c) {
-  const int64_t n3 = 3 * c.n;
+  const int64_t n3 = c.n3;
   DFR_HIP(hipMalloc(&c.d_diag, sizeof(double) * (3 * diag_blocks(&c) + 3)));
   // largest grid of any tile (1 x 1 tiles) or of the vector kernels
   const int64_t nb = std::max<int64_t>(6LL * c.ne * c.ne + 8, 8192);
@@ -571,6 +571,7 @@ int dfr_create(const dfr_grid_desc *d, void *stream, dfr_ctx **out) {
   c.ns = d->p + 1;
   c.nelem = 6LL * c.ne * c.ne;
   c.n = c.nelem * c.ns * c.ns;
+  c.n3 = 3 * c.n;
   c.radius = d->radius;
   c.omega = d->omega;
   c.gravity = d->gravity;
@@ -593,6 +594,71 @@ int dfr_create(const dfr_grid_desc *d, void *stream, dfr_ctx **out) {
   *out = h;
   return DFR_OK;
 }
+
+int dfr_create_ode(int problem, int n, void *stream, dfr_ctx **out) {
+  if (!out) return DFR_E_INVAL;
+  *out = nullptr;
+  const int nmax = problem == DFR_ODE_ADR ? 256 : 65536;
+  if (problem < DFR_ODE_ADR || problem > DFR_ODE_SEMILINEAR || n < 3 || n > nmax) {
+    set_error("dfr_create_ode: unknown problem or size out of range");
+    return DFR_E_INVAL;
+  }
+  dfr_ctx *h = new (std::nothrow) dfr_ctx();
+  if (!h) return DFR_E_NOMEM;
+  Ctx &c = h->c;
+  OdeArgs &o = c.ode;
+  o.kind = problem;
+  o.n = n;
+  if (problem == DFR_ODE_ADR) {          // Sec. 5.1: eps = 1/100, alpha = -10, gamma = 100
+    o.len = (int64_t)n * n;
+    o.h = 1.0 / (n - 1);
+    o.eps = 1.0 / 100.0;
+    o.alpha = -10.0;
+    o.gamma = 100.0;
+  } else if (problem == DFR_ODE_BURGERS) {   // eps = 1e-3
+    o.len = n;
+    o.h = 1.0 / (n + 1);
+    o.eps = 1e-3;
+  } else {                                   // semilinear parabolic, time appended
+    o.len = n + 1;
+    o.h = 1.0 / (n + 1);
+    double s = 0.0;
+    for (int i = 1; i <= n; ++i) {
+      const double x = i * o.h;
+      s += x * (1.0 - x);
+    }
+    o.isum = o.h * s;
+  }
+  c.ode_kind = problem;
+  c.ne = 1;
+  c.p_deg = 1;
+  c.ns = 2;
+  c.nelem = 1;
+  c.n = o.len;
+  c.n3 = o.len;
+  c.radius = c.omega = c.gravity = 1.0;
+  c.stream = (hipStream_t)stream;
+  int rc = DFR_OK;
+  if (hipGetDevice(&c.device) != hipSuccess) {
+    set_error("no HIP device");
+    rc = DFR_E_HIP;
+  }
+  if (!rc && (hipMalloc(&c.d_err, sizeof(int)) != hipSuccess || hipMemset(c.d_err, 0, sizeof(int)) != hipSuccess)) {
+    set_error("dfr_create_ode: out of device memory");
+    rc = DFR_E_NOMEM;
+  }
+  c.ga.err_flag = c.d_err;
+  if (!rc) rc = alloc_workspace(c);
+  if (rc) {
+    free_ctx(c);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DFR_OK;
+}
+
+int64_t dfr_num_unknowns(const dfr_ctx *h) { return h ? h->c.n3 : -1; }
 
 int dfr_timing_enable(dfr_ctx *h, int enable) {
   if (!h) return DFR_E_INVAL;
@@ -630,6 +696,10 @@ int dfr_destroy(dfr_ctx *h) {
 int64_t dfr_num_nodes(const dfr_ctx *h) { return h ? h->c.n : -1; }
 
 int dfr_node_frames(const dfr_ctx *h, double *P, double *B1, double *B2) {
+  if (h && h->c.ode_kind) {
+    set_error("dfr_node_frames: a grid context is required (this one holds a test problem)");
+    return DFR_E_INVAL;
+  }
   if (!h || !P || !B1 || !B2) {
     set_error("null argument");
     return DFR_E_INVAL;
@@ -650,6 +720,10 @@ int dfr_node_frames(const dfr_ctx *h, double *P, double *B1, double *B2) {
 }
 
 int dfr_set_tile(dfr_ctx *h, int tx, int ty) {
+  if (h && h->c.ode_kind) {
+    set_error("dfr_set_tile: a grid context is required (this one holds a test problem)");
+    return DFR_E_INVAL;
+  }
   if (!h) return DFR_E_INVAL;
   Ctx &c = h->c;
   for (const auto &t : tile_candidates(c))
@@ -663,6 +737,10 @@ int dfr_set_tile(dfr_ctx *h, int tx, int ty) {
 }
 
 int dfr_set_riemann(dfr_ctx *h, int solver) {
+  if (h && h->c.ode_kind) {
+    set_error("dfr_set_riemann: a grid context is required (this one holds a test problem)");
+    return DFR_E_INVAL;
+  }
   if (!h || (solver != DFR_RUSANOV && solver != DFR_AUSM)) {
     set_error("dfr_set_riemann: solver must be DFR_RUSANOV or DFR_AUSM");
     return DFR_E_INVAL;
@@ -692,9 +770,13 @@ int dfr_get_krylov_tile(const dfr_ctx *h, int *tx, int *ty) {
 }
 
 int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
+  if (h && h->c.ode_kind) {
+    set_error("dfr_autotune: a grid context is required (this one holds a test problem)");
+    return DFR_E_INVAL;
+  }
   if (!h || (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) return DFR_E_INVAL;
   Ctx &c = h->c;
-  const int64_t n3 = 3 * c.n;
+  const int64_t n3 = c.n3;
   // a smooth positive state and a direction in the Krylov workspace (and
   // FP32 copies of the direction and of a previous vector for an FP32 basis)
   double *q = c.d_V, *v = c.d_V + n3, *w = c.d_V + 2 * n3;
@@ -782,6 +864,10 @@ int dfr_sync(dfr_ctx *h) {
 }
 
 int dfr_diagnostics(dfr_ctx *h, const double *q, double *zeta, double *fcor, double *host_out3) {
+  if (h && h->c.ode_kind) {
+    set_error("dfr_diagnostics: a grid context is required (this one holds a test problem)");
+    return DFR_E_INVAL;
+  }
   if (!h || !q || !host_out3 || zeta == q || fcor == q || (zeta && zeta == fcor)) {
     set_error("invalid argument");
     return DFR_E_INVAL;
@@ -805,6 +891,10 @@ int dfr_rhs(dfr_ctx *h, const double *q, double *dqdt) {
 }
 
 int dfr_jvp_complex_step(dfr_ctx *h, const double *q, const double *v, double eps, dfr_precision prec, double *jv) {
+  if (h && h->c.ode_kind && prec != DFR_FP64) {
+    set_error("dfr_jvp_complex_step: test problems take the exact Jacobian in FP64 (DFR_FP64)");
+    return DFR_E_INVAL;
+  }
   if (!h || !q || !v || !jv || jv == q || jv == v || !(eps > 0.0) ||
       (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
     set_error("invalid argument");
@@ -812,7 +902,7 @@ int dfr_jvp_complex_step(dfr_ctx *h, const double *q, const double *v, double ep
   }
   Ctx &c = h->c;
   if (prec != DFR_FP64) {
-    int rc = launch_copy_to_f32(&c, 3 * c.n, q, (float *)c.d_qf32);
+    int rc = launch_copy_to_f32(&c, c.n3, q, (float *)c.d_qf32);
     if (rc) return rc;
     return launch_dfr(&c, nullptr, (const float *)c.d_qf32, v, nullptr, eps, true, true, jv, nullptr);
   }

@@ -43,6 +43,17 @@ struct DiagOps {
   double Dg[MAX_NS][MAX_NS];
 };
 
+// The stiff test problems of Sec. 5.1 (semi-discrete, second-order finite
+// differences): kind 1 advection-diffusion-reaction on an n x n vertex grid
+// with reflecting (Neumann) ends, kind 2 Burgers on n interior points with
+// zero ends, kind 3 semilinear parabolic on n interior points with zero ends
+// and time as unknown n.  isum: the trapezoid integral of x(1-x) (kind 3).
+struct OdeArgs {
+  int kind, n;
+  int64_t len;   // number of unknowns
+  double h, eps, alpha, gamma, isum;
+};
+
 // Per-abscissa tangent data: X = tan x, 1 + X^2, 1/(1 + X^2).
 struct Tan3 {
   double x, ax, rax, pad;
@@ -174,6 +185,10 @@ struct KHost {
 struct Ctx {
   int ne, ns, p_deg;
   int64_t n, nelem;
+  int64_t n3 = 0;                 // length of a state vector (3 N on a grid)
+  // a Sec. 5.1 test problem instead of a grid (0: the shallow-water grid)
+  int ode_kind = 0;
+  OdeArgs ode{};
   double radius, omega, gravity;
   double lam0, phi0, alp0;
   hipStream_t stream;
@@ -199,7 +214,7 @@ struct Ctx {
   double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N (FP64, or FP32 when basis32)
   bool basis32 = false;           // the current KIOPS call keeps its basis in FP32
   void *vslot(int k) const {
-    return reinterpret_cast<char *>(d_V) + (size_t)k * 3 * (size_t)n * (basis32 ? sizeof(float) : sizeof(double));
+    return reinterpret_cast<char *>(d_V) + (size_t)k * (size_t)n3 * (basis32 ? sizeof(float) : sizeof(double));
   }
   double *d_W = nullptr;          // MAX_P scaled b columns of 3N
   double *d_partials = nullptr;   // per-block partial sums (J*v inner products)
@@ -253,6 +268,8 @@ int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
 int64_t diag_blocks(const Ctx *c);
 int launch_diagnostics(Ctx *c, const double *q, double *zeta, double *fcor);
 int launch_check_state(Ctx *c, const double *q);
+int launch_ode(Ctx *c, const double *q, const double *v, const double *vscale, bool jvp, double *out,
+               const ArnoldiArgs *ar);
 int launch_fill(Ctx *c, double *q, double *v);
 int latched_error(Ctx &c);
 size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32);

@@ -1245,22 +1245,24 @@ __global__ __launch_bounds__(BLOCK) void fill_kernel(int64_t n, double *q, doubl
   }
 }
 
-__device__ __forceinline__ void check_state_body(int blk, int nblk, int64_t n, const double *q, int *err) {
+// every value finite, the first ndepth (the depths H) positive
+__device__ __forceinline__ void check_state_body(int blk, int nblk, int64_t nall, int64_t ndepth, const double *q,
+                                                 int *err) {
   int bad = 0;
-  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < 3 * n; i += (int64_t)nblk * BLOCK) {
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < nall; i += (int64_t)nblk * BLOCK) {
     const double x = q[i];
     if (!isfinite(x)) bad |= 1;
-    if (i < n && !(x > 0.0)) bad |= 2;
+    if (i < ndepth && !(x > 0.0)) bad |= 2;
   }
   if (bad) atomicOr(err, bad);
 }
-__global__ __launch_bounds__(BLOCK) void check_state_kernel(int64_t n, const double *q, int *err) {
-  check_state_body(blockIdx.x, gridDim.x, n, q, err);
+__global__ __launch_bounds__(BLOCK) void check_state_kernel(int64_t nall, int64_t ndepth, const double *q, int *err) {
+  check_state_body(blockIdx.x, gridDim.x, nall, ndepth, q, err);
 }
 // n = nodes (the vector holds 3n values); out = the member's error flag
 __global__ __launch_bounds__(BLOCK) void check_state_batch(const AxpbyCall *__restrict__ calls, int ncalls) {
   const AxpbyCall &c = calls[find_call(calls, ncalls)];
-  check_state_body(blockIdx.x - c.b0, c.nblk, c.n, c.x, reinterpret_cast<int *>(c.out));
+  check_state_body(blockIdx.x - c.b0, c.nblk, 3 * c.n, c.n, c.x, reinterpret_cast<int *>(c.out));
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,6 +1367,112 @@ __global__ __launch_bounds__(BLOCK) void diag_sum_kernel(int64_t nb, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// The stiff test problems of Sec. 5.1 on the same Krylov machinery.  They are
+// small (at most a few thousand unknowns), so one workgroup of 1024 threads
+// evaluates F(u) or the exact J(u) v and, in the Krylov form, the Arnoldi
+// prologue and epilogue of the DFR kernel: w = sigma_j (J v~_j + W u_j) and
+// the two inner products, reduced in a fixed order (one partial pair).
+constexpr int ODE_THREADS = 1024;
+
+// fixed-order sum over the workgroup (ODE_THREADS threads)
+__device__ double ode_block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < ODE_THREADS / 64; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+// (J v)_i or F(u)_i of problem `o` at unknown i; usum / vsum: the sums of the
+// first n values of u / v (semilinear integral term)
+template <bool JVP>
+__device__ __forceinline__ double ode_value(const OdeArgs &o, const double *u, const double *v, int64_t i, double vsum) {
+  const double h = o.h;
+  if (o.kind == 1) {   // advection-diffusion-reaction, Neumann by reflection
+    const int N = o.n;
+    const int ii = (int)(i % N), jj = (int)(i / N);
+    const int64_t e = ii + 1 < N ? i + 1 : i - 1, w = ii > 0 ? i - 1 : i + 1;
+    const int64_t nn = jj + 1 < N ? i + N : i - N, s = jj > 0 ? i - N : i + N;
+    const double *x = JVP ? v : u;
+    const double lin = o.eps * (x[e] + x[w] + x[nn] + x[s] - 4.0 * x[i]) / (h * h) -
+                       o.alpha * ((x[e] - x[w]) / (2.0 * h) + (x[nn] - x[s]) / (2.0 * h));
+    const double ui = u[i];
+    if (JVP) return lin + o.gamma * (-3.0 * ui * ui + 3.0 * ui - 0.5) * v[i];
+    return lin + o.gamma * ui * (ui - 0.5) * (1.0 - ui);
+  }
+  if (o.kind == 2) {   // Burgers, zero ends
+    const int n = o.n;
+    const double *x = JVP ? v : u;
+    const double xp = i + 1 < n ? x[i + 1] : 0.0, xm = i > 0 ? x[i - 1] : 0.0;
+    const double lap = (xp - 2.0 * x[i] + xm) / (h * h);
+    const double up = i + 1 < n ? u[i + 1] : 0.0, um = i > 0 ? u[i - 1] : 0.0;
+    if (JVP) return -(up * xp - um * xm) / (2.0 * h) + o.eps * lap;
+    return -(up * up - um * um) / (4.0 * h) + o.eps * lap;
+  }
+  // semilinear parabolic, zero ends, time as unknown n
+  const int n = o.n;
+  if (i == n) return JVP ? 0.0 : 1.0;
+  const double *x = JVP ? v : u;
+  const double xp = i + 1 < n ? x[i + 1] : 0.0, xm = i > 0 ? x[i - 1] : 0.0;
+  const double xi = (double)(i + 1) * h;
+  const double src = xi * (1.0 - xi) + 2.0 - o.isum;
+  const double lap = (xp - 2.0 * x[i] + xm) / (h * h);
+  const double et = exp(u[n]);
+  return lap + h * vsum + (JVP ? v[n] : 1.0) * et * src;
+}
+
+template <bool JVP, bool AR>
+__global__ __launch_bounds__(ODE_THREADS) void ode_kernel(const OdeArgs o, const double *__restrict__ u,
+                                                          const double *__restrict__ v,
+                                                          const double *__restrict__ vscale,
+                                                          double *__restrict__ out, const ArnoldiArgs ar) {
+  __shared__ double red[256];
+  const int64_t len = o.len;
+  double sig = 1.0, bj[MAX_P];
+  if constexpr (AR) {
+    if (ar.kd->happy) return;
+    if (!arnoldi_prologue(ar, red, true, sig, bj)) return;
+  }
+  // the integral term of the semilinear problem: sum of the first n values
+  double xsum = 0.0;
+  if (o.kind == 3) {
+    const double *x = JVP ? v : u;
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < o.n; i += ODE_THREADS) a += x[i];
+    xsum = ode_block_sum(a, red);
+  }
+  const double vs = AR ? sig : ((JVP && vscale) ? *vscale : 1.0);
+  double d0 = 0.0, d1 = 0.0;
+  const double *ub = AR ? ar.kd->botu + ar.j * MAX_P : nullptr;
+  const double sp = (AR && ar.vprev) ? ar.kd->sigma[ar.j - 1] : 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += ODE_THREADS) {
+    const double r = ode_value<JVP>(o, u, v, i, xsum);
+    if constexpr (AR) {
+      double wb = 0.0;
+      for (int k = 0; k < ar.p; ++k) wb += ar.W[k][i] * (ar.start ? ar.ybot[k] : ub[k]);
+      const double a = vs * (r + wb);
+      out[i] = a;
+      d0 += a * (vs * v[i]);
+      if (ar.vprev) d1 += a * (sp * static_cast<const double *>(ar.vprev)[i]);
+    } else {
+      out[i] = JVP ? r * vs : r;
+    }
+  }
+  if constexpr (AR) {
+    d0 = ode_block_sum(d0, red);
+    d1 = ode_block_sum(d1, red);
+    if (threadIdx.x == 0) {
+      ar.pout[0] = d0;
+      ar.pout[1] = d1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 static inline int grid_for(int64_t n) {
   int64_t b = (n + BLOCK - 1) / BLOCK;
@@ -1380,6 +1488,7 @@ size_t dfr_lds_bytes(int ns, int tx, int ty, bool fp32) {
 }
 
 int64_t dfr_num_tiles(const Ctx *c, bool arnoldi) {
+  if (c->ode_kind) return 1;   // one workgroup
   const int tx = arnoldi ? c->ar_tx : c->tile_tx, ty = arnoldi ? c->ar_ty : c->tile_ty;
   return 6LL * (c->ne / tx) * (c->ne / ty);
 }
@@ -1493,6 +1602,8 @@ static int dispatch_ns(Ctx *c, const TQ *q, const void *v, const double *vscale,
 
 int launch_dfr(Ctx *c, const double *q, const float *q32, const void *v, const double *vscale, double eps,
                bool complex_step, bool fp32, void *out, const ArnoldiArgs *ar) {
+  if (c->ode_kind)
+    return launch_ode(c, q, static_cast<const double *>(v), vscale, complex_step, static_cast<double *>(out), ar);
   ArnoldiArgs none{};
   const ArnoldiArgs &a = ar ? *ar : none;
   if (!complex_step) return dispatch_ns<double, double, false>(c, q, nullptr, nullptr, 0.0, out, a);
@@ -1512,7 +1623,7 @@ static inline int grid_reduce(int64_t n) {
 }
 
 int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, void *out, int *np_out) {
-  const int64_t n3 = 3 * c->n;
+  const int64_t n3 = c->n3;
   const int nb = grid_reduce(n3);
   if (c->basis32)
     dfr_launch(c, DFR_K_OTHER, arnoldi_first_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, ar, static_cast<float *>(out));
@@ -1525,7 +1636,7 @@ int launch_arnoldi_first(Ctx *c, const ArnoldiArgs &ar, void *out, int *np_out) 
 
 int launch_update(Ctx *c, int j, void *w, const void *vj, const void *vprev, const double *pin, int np_in,
                   double *pout, int *np_out) {
-  const int64_t n3 = 3 * c->n;
+  const int64_t n3 = c->n3;
   const int nb = grid_reduce(n3);
   if (c->basis32)
     dfr_launch(c, DFR_K_UPDATE, arnoldi_update_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, j, c->kiops_p,
@@ -1541,7 +1652,7 @@ int launch_update(Ctx *c, int j, void *w, const void *vj, const void *vprev, con
 }
 
 int launch_start(Ctx *c, const double *x, void *v0, double *pout, int *np_out) {
-  const int64_t n3 = 3 * c->n;
+  const int64_t n3 = c->n3;
   const int nb = grid_reduce(n3);
   if (c->basis32)
     dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<float *>(v0), pout);
@@ -1553,7 +1664,7 @@ int launch_start(Ctx *c, const double *x, void *v0, double *pout, int *np_out) {
 }
 
 int launch_combine(Ctx *c, double *x) {
-  const int64_t n3 = 3 * c->n;
+  const int64_t n3 = c->n3;
   if (c->basis32)
     dfr_launch(c, DFR_K_OTHER, arnoldi_combine_kernel<float>, dim3(grid_for(n3)), dim3(BLOCK), 0, n3,
                reinterpret_cast<const float *>(c->d_V), n3, (const KDev *)c->d_kd, x);
@@ -1590,7 +1701,8 @@ int launch_fill(Ctx *c, double *q, double *v) {
 }
 
 int launch_check_state(Ctx *c, const double *q) {
-  dfr_launch(c, DFR_K_OTHER, check_state_kernel, dim3(grid_for(3 * c->n)), dim3(BLOCK), 0, c->n, q, c->d_err);
+  dfr_launch(c, DFR_K_OTHER, check_state_kernel, dim3(grid_for(c->n3)), dim3(BLOCK), 0, c->n3,
+             c->ode_kind ? (int64_t)0 : c->n, q, c->d_err);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
@@ -1761,6 +1873,21 @@ int launch_diagnostics(Ctx *c, const double *q, double *zeta, double *fcor) {
 #undef DIAG_CASE
   DFR_HIP(hipGetLastError());
   dfr_launch(c, DFR_K_FINALIZE, diag_sum_kernel, dim3(1), dim3(BLOCK), 0, nb, (const double *)part, part + 3 * nb);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_ode(Ctx *c, const double *q, const double *v, const double *vscale, bool jvp, double *out,
+               const ArnoldiArgs *ar) {
+  ArnoldiArgs none{};
+  const ArnoldiArgs &a = ar ? *ar : none;
+  const int kind = !jvp ? DFR_K_RHS : (a.on ? DFR_K_JV_ARNOLDI : DFR_K_JV);
+  if (!jvp)
+    dfr_launch(c, kind, ode_kernel<false, false>, dim3(1), dim3(ODE_THREADS), 0, c->ode, q, v, vscale, out, a);
+  else if (a.on)
+    dfr_launch(c, kind, ode_kernel<true, true>, dim3(1), dim3(ODE_THREADS), 0, c->ode, q, v, vscale, out, a);
+  else
+    dfr_launch(c, kind, ode_kernel<true, false>, dim3(1), dim3(ODE_THREADS), 0, c->ode, q, v, vscale, out, a);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

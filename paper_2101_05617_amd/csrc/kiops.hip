@@ -40,7 +40,7 @@ namespace dfrsw {
 int latched_error(Ctx &c);
 
 static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
-  const int64_t n3 = 3 * c.n;
+  const int64_t n3 = c.n3;
   int64_t b = (n3 + BLOCK - 1) / BLOCK;
   if (b > 2048) b = 2048;
   double *d_out = (double *)c.d_expm_scratch;   // KHost block reused as 4 doubles
@@ -125,7 +125,7 @@ int km_begin_attempt(KiopsMachine &k, const kiops_opts &o) {
 // Arguments of the Krylov-form product for basis vector j.
 void km_arnoldi_args(const KiopsMachine &k, const kiops_opts &o, ArnoldiArgs &ar) {
   const Ctx &c = *k.c;
-  const int64_t n3 = 3 * c.n;
+  const int64_t n3 = c.n3;
   ar = ArnoldiArgs{};
   ar.on = 1;
   ar.j = k.j;
@@ -231,7 +231,7 @@ int km_decide(KiopsMachine &k, const KHost &r, const kiops_opts &o, bool *accept
 // products, norms, the Hessenberg and the combination stay FP64
 static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out, int n_phi, const double *const *b,
                       const kiops_opts &o, double eps, bool fp32, bool basis32, double *w, KiopsRun &st) {
-  const int64_t n3 = 3 * c.n;
+  const int64_t n3 = c.n3;
   int rc = kiops_validate(c, o, n_phi, tau_out);
   if (rc) return rc;
   struct BasisMode {
@@ -374,7 +374,7 @@ void add_stats(kiops_stats *acc, const KiopsRun &r) {
 static const float *prep_q32(Ctx &c, const double *q, bool fp32, int &rc) {
   rc = DFR_OK;
   if (!fp32) return nullptr;
-  rc = launch_copy_to_f32(&c, 3 * c.n, q, (float *)c.d_qf32);
+  rc = launch_copy_to_f32(&c, c.n3, q, (float *)c.d_qf32);
   return (const float *)c.d_qf32;
 }
 
@@ -397,6 +397,10 @@ int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, cons
       return DFR_E_INVAL;
     }
   Ctx &c = h->c;
+  if (c.ode_kind && prec != DFR_FP64) {
+    set_error("kiops_phi_apply: test problems run in FP64");
+    return DFR_E_INVAL;
+  }
   int rc = launch_check_state(&c, q);
   if (rc) return rc;
   const bool fp32 = prec != DFR_FP64;
@@ -419,6 +423,10 @@ int epi_create(dfr_ctx *h, int order, double dt, int startup_substeps, const dou
     return DFR_E_INVAL;
   }
   *out = nullptr;
+  if (h->c.ode_kind && prec != DFR_FP64) {
+    set_error("epi_create: test problems run in FP64");
+    return DFR_E_INVAL;
+  }
   epi_state *st = new (std::nothrow) epi_state();
   if (!st) return DFR_E_NOMEM;
   Ctx &c = h->c;
@@ -432,7 +440,7 @@ int epi_create(dfr_ctx *h, int order, double dt, int startup_substeps, const dou
   st->eps = eps;
   st->prec = prec;
   st->nsteps = 0;
-  const size_t bytes = sizeof(double) * 3 * c.n;
+  const size_t bytes = sizeof(double) * c.n3;
   auto alloc = [&](double **p) { return hipMalloc(p, bytes) == hipSuccess; };
   bool ok = alloc(&st->q) && alloc(&st->F) && alloc(&st->qs) && alloc(&st->w) && alloc(&st->d) && alloc(&st->jd);
   for (int i = 0; ok && i < st->P; ++i) {
@@ -496,7 +504,7 @@ int epi_save(const epi_state *st, void *buf, size_t *nbytes) {
   }
   Ctx &c = *st->c;
   const int nh = (int)std::min<int64_t>(st->nsteps, st->P);
-  const size_t vec = sizeof(double) * 3 * c.n;
+  const size_t vec = sizeof(double) * c.n3;
   const size_t need = sizeof(EpiCkptHeader) + vec * (1 + 2 * (size_t)nh);
   if (!buf) {
     *nbytes = need;
@@ -551,7 +559,7 @@ int epi_load(dfr_ctx *h, const void *buf, size_t nbytes, epi_state **out) {
     set_error("epi_load: the checkpoint is of another grid (ne, p)");
     return DFR_E_INVAL;
   }
-  const size_t vec = sizeof(double) * 3 * c.n;
+  const size_t vec = sizeof(double) * c.n3;
   const int P = hd.order == 2 ? 0 : hd.order - 2;
   if (hd.nhist < 0 || hd.nhist != (int)std::min<int64_t>(hd.nsteps, P) ||
       nbytes != sizeof(hd) + vec * (1 + 2 * (size_t)hd.nhist)) {
@@ -587,7 +595,7 @@ int epi_load(dfr_ctx *h, const void *buf, size_t nbytes, epi_state **out) {
 int epi_get_state(const epi_state *st, double *q) {
   if (!st || !q) return DFR_E_INVAL;
   Ctx &c = *st->c;
-  DFR_HIP(hipMemcpyAsync(q, st->q, sizeof(double) * 3 * c.n, hipMemcpyDeviceToDevice, c.stream));
+  DFR_HIP(hipMemcpyAsync(q, st->q, sizeof(double) * c.n3, hipMemcpyDeviceToDevice, c.stream));
   return DFR_OK;
 }
 
@@ -597,7 +605,7 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
     return DFR_E_INVAL;
   }
   Ctx &c = h->c;
-  const int64_t n3 = 3 * c.n;
+  const int64_t n3 = c.n3;
   const bool fp32 = st->prec != DFR_FP64;
   const bool basis32 = st->prec == DFR_FP32_JV_BASIS32;
   if (stats) std::memset(stats, 0, sizeof(*stats));

@@ -71,6 +71,8 @@ def lib():
             "dfr_create": (i, [ctypes.POINTER(_GridDesc), vp, ctypes.POINTER(vp)]),
             "dfr_destroy": (i, [vp]),
             "dfr_num_nodes": (i64, [vp]),
+            "dfr_create_ode": (i, [i, i, vp, ctypes.POINTER(vp)]),
+            "dfr_num_unknowns": (i64, [vp]),
             "dfr_node_frames": (i, [vp, vp, vp, vp]),
             "dfr_sync": (i, [vp]),
             "dfr_rhs": (i, [vp, vp, vp]),
@@ -115,7 +117,7 @@ def lib():
 
 
 def exported_symbols():
-    return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_node_frames", "dfr_sync", "dfr_rhs",
+    return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_create_ode", "dfr_num_unknowns", "dfr_node_frames", "dfr_sync", "dfr_rhs",
             "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
             "epi_num_steps", "epi_destroy", "epi_save", "epi_load", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
@@ -173,9 +175,35 @@ class Grid:
         _check(lib().dfr_node_frames(self._h, *(a.ctypes.data_as(ctypes.c_void_p) for a in (P, B1, B2))))
         return P, B1, B2
 
+    @property
+    def length(self):
+        """Doubles per state vector (3N on a grid)."""
+        return 3 * self.N
+
     def empty(self):
         import torch
-        return torch.empty(3 * self.N, dtype=torch.float64, device="cuda")
+        return torch.empty(self.length, dtype=torch.float64, device="cuda")
+
+
+ODE_PROBLEMS = {"adr": 1, "burgers": 2, "semilinear": 3}
+
+
+class OdeProblem(Grid):
+    """A context holding one of the Sec. 5.1 test problems ("adr", "burgers",
+    "semilinear") of size n instead of a grid; used with dfr_rhs,
+    dfr_jvp_complex_step (exact J v), kiops_phi_apply and the epi_* calls."""
+
+    def __init__(self, problem, n):
+        self.problem, self.n = problem, int(n)
+        self._hb = None
+        h = ctypes.c_void_p()
+        _check(lib().dfr_create_ode(ODE_PROBLEMS[problem], self.n, _stream(), ctypes.byref(h)))
+        self._h = h
+        self.N = int(lib().dfr_num_unknowns(h))
+
+    @property
+    def length(self):
+        return self.N
 
 
 # ---- entry points with the names of the C ABI ---------------------------------
