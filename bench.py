@@ -448,6 +448,53 @@ def large_dt_study(steps):
     return out
 
 
+def ode_suite_study():
+    """The stiff test problems of Sec. 5.1 on the GPU path: EPI4 and EPI6 over
+    each problem's interval at one of Fig. 2's step sizes, KIOPS tol 1e-14;
+    the error is the 2-norm against the exact solution (semilinear) or
+    against EPI6 with a quarter of the step (the other two)."""
+    import numpy as np
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    cases = [("adr", 40, 0.1, 2.2e-4), ("burgers", 1024, 1.0, 1.8e-3), ("semilinear", 400, 1.0, 5.0e-2)]
+    out = {}
+    opts = dfrsw.kiops_opts(tol=1e-14, m_max=64)
+    for name, n, T, h in cases:
+        D = dfrsw.OdeProblem(name, n)
+        u0 = inputs.ode_initial_state(name, n)
+        x = np.arange(1, n + 1) / (n + 1)
+
+        def run(order, hh):
+            nst = int(round(T / hh))
+            st = dfrsw.epi_create(D, order, T / nst, torch.from_numpy(u0).cuda(), startup_substeps=4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nmv = 0
+            for _ in range(nst):
+                nmv += dfrsw.epi_step(D, st, opts)["n_matvec"]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            q = dfrsw.epi_get_state(st).cpu().numpy()
+            st.close()
+            return q, el, nst, nmv
+
+        if name == "semilinear":
+            ref = np.concatenate([x * (1 - x) * np.exp(1.0), [1.0]])
+        else:
+            ref = run(6, h / 4)[0]
+        res = {"n_unknowns": int(u0.size), "t_final": T, "dt": h}
+        for order in (4, 6):
+            q, el, nst, nmv = run(order, h)
+            res[f"epi{order}"] = {"wall_s": el, "steps": nst, "steps_per_s": nst / el, "jv_per_step": nmv / nst,
+                                  "error_2norm": float(np.linalg.norm(q[: n if name == 'semilinear' else None] -
+                                                                      ref[: n if name == 'semilinear' else None]))}
+            log(f"ODE {name} EPI{order}: {nst} steps in {el:.3f}s, {nmv / nst:.0f} J*v/step")
+        out[name] = res
+        D.close()
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -544,6 +591,7 @@ def main():
     ap.add_argument("--no-ausm", action="store_true", help="skip the AUSM-flux figures")
     ap.add_argument("--no-diagnostics", action="store_true", help="skip the conservation-diagnostics figures")
     ap.add_argument("--no-large-dt", action="store_true", help="skip the dt = 4 h figures")
+    ap.add_argument("--no-ode", action="store_true", help="skip the Sec. 5.1 test problems")
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
     ap.add_argument("--ensemble-workers", type=int, default=8)
@@ -566,7 +614,7 @@ def main():
         return summarize_profile(args)
     if args.headline_only:
         args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_ausm = args.no_diagnostics = \
-            args.no_large_dt = args.no_cpu_baseline = True
+            args.no_large_dt = args.no_ode = args.no_cpu_baseline = True
 
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)
@@ -754,6 +802,10 @@ def main():
     # ---- the large-time-step regime (dt = 4 h)
     if not args.no_large_dt:
         out["large_dt"] = large_dt_study(4)
+
+    # ---- the stiff test problems of Sec. 5.1 on the same KIOPS / EPI path
+    if not args.no_ode:
+        out["ode_suite"] = ode_suite_study()
 
     # ---- the oracle on this host's cores (bounded sample): one thread, then
     # every thread of this host's share (its element loop runs under OpenMP)

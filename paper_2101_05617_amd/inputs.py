@@ -314,3 +314,22 @@ def random_direction(n3, seed):
     """A seeded unit-scale direction vector for J*v tests (N(0,1) entries)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal(n3)
+
+
+def ode_initial_state(name: str, n: int) -> np.ndarray:
+    """Initial states of the Sec. 5.1 test problems in the library's unknown
+    order: "adr" on the n x n vertex grid of [0,1]^2 (index j n + i, i along
+    x), 256 (x y (1-x)(1-y))^2 + 0.3; "burgers" on the n interior points of
+    [0,1], exp(-(x - 0.3)^2 / (2 0.05^2)); "semilinear" on the n interior
+    points, x(1-x), followed by the time 0."""
+    if name == "adr":
+        x = np.arange(n) / (n - 1)
+        X, Y = np.meshgrid(x, x)
+        return (256.0 * (X * Y * (1 - X) * (1 - Y)) ** 2 + 0.3).reshape(-1)
+    x = np.arange(1, n + 1) / (n + 1)
+    if name == "burgers":
+        return np.exp(-((x - 0.3) ** 2) / (2 * 0.05 ** 2))
+    if name == "semilinear":
+        return np.concatenate([x * (1 - x), [0.0]])
+    raise KeyError(name)
+

@@ -58,7 +58,7 @@ def test_ode_rhs_and_jvp_parity(name):
 def test_ode_kiops_parity(name):
     from paper_2101_05617_amd import dfrsw
     D, rhs, jvp, u0 = _problem(name)
-    tau = 4 * STEP[name]
+    tau = STEP[name]
     F = rhs(u0)
     ref, rst = okiops.kiops(tau, lambda v: jvp(u0, v), [None, F], tol=1e-12, m_max=64)
     got, gst = dfrsw.kiops_phi_apply(D, to_dev(u0), tau, [None, to_dev(F)], dfrsw.kiops_opts(tol=1e-12, m_max=64))
