@@ -118,6 +118,9 @@ def summarize_profile(args):
         cal = max(float(r["Counter_Value"]) for r in cc
                   if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"])
         vals = [float(r["Counter_Value"]) for r in cc if r["Counter_Name"] == counter and args.kernel in r["Kernel_Name"]]
+        if not vals:
+            lines.append(f"{counter}: no dispatch of a kernel matching {args.kernel!r}")
+            continue
         factor = (CAL_BYTES / 1024.0) / cal
         per = sum(vals) / len(vals) * factor * 1024.0
         traffic[counter] = per
