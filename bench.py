@@ -596,7 +596,8 @@ def main():
     ap.add_argument("--no-large-dt", action="store_true", help="skip the dt = 4 h figures")
     ap.add_argument("--no-ode", action="store_true", help="skip the Sec. 5.1 test problems")
     ap.add_argument("--ensemble-members", type=int, default=64)
-    ap.add_argument("--ensemble-steps", type=int, default=6, help="timed EPI4 steps after the start-up")
+    ap.add_argument("--ensemble-steps", type=int, default=94,
+                    help="timed EPI4 steps after the two start-up steps (94: one simulated day in all)")
     ap.add_argument("--ensemble-workers", type=int, default=8)
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline EPI run of --workload and its J*v figures (for profiling)")
