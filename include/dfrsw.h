@@ -47,10 +47,12 @@ enum {
 };
 
 /* Precision of the products inside KIOPS / EPI.  DFR_FP64: complex FP64.
- * DFR_FP32_JV: the complex-step evaluation in complex FP32 (FP64 Krylov
- * basis, inner products, norms, Hessenberg, exponential, combination and EPI
- * update).  DFR_FP32_JV_BASIS32: as DFR_FP32_JV with the Krylov basis stored
- * in FP32 (its vectors rounded once when stored; inner products and norms
+ * DFR_FP32_JV: the complex-step evaluations inside KIOPS in complex FP32;
+ * the Krylov basis, inner products, norms, Hessenberg, exponential and
+ * combination, the EPI stage combination and update stay FP64, and so do
+ * the products J_n (q_{n-i} - q_n) of the EPI remainders.
+ * DFR_FP32_JV_BASIS32: as DFR_FP32_JV with the Krylov basis stored in FP32
+ * (its vectors rounded once when stored; inner products and norms
  * accumulate in FP64 over the stored values); single-grid KIOPS / EPI only,
  * dfr_jvp_complex_step treats it as DFR_FP32_JV. */
 typedef enum { DFR_FP64 = 0, DFR_FP32_JV = 1, DFR_FP32_JV_BASIS32 = 2 } dfr_precision;

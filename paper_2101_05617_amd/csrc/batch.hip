@@ -711,12 +711,11 @@ int epi_ensemble_step(dfr_ensemble *E, epi_ensemble *X, const kiops_opts *o, kio
     for (int r = 0; r < s0->P; ++r) {
       // R_r = F(q_{n-r}) - F_n - J_n (q_{n-r} - q_n)   (Eq. 33 generalised)
       if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->hq[r], -1.0, st(i)->q, st(i)->d); }))) return rc;
+      // the remainder's product is FP64 in every precision (as in epi_step)
       std::vector<DfrCall> c;
-      for (int i = 0; i < n; ++i) {
-        const void *qq = fp32 ? (const void *)cx(i).d_qf32 : (const void *)st(i)->q;
-        c.push_back(make_call(*E, i, false, qq, st(i)->d, eps, st(i)->jd, nullptr));
-      }
-      if ((rc = launch_dfr_groups(*E, all, c, true, fp32, false))) return rc;
+      for (int i = 0; i < n; ++i)
+        c.push_back(make_call(*E, i, false, (const void *)st(i)->q, st(i)->d, eps, st(i)->jd, nullptr));
+      if ((rc = launch_dfr_groups(*E, all, c, true, false, false))) return rc;
       if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->hF[r], -1.0, st(i)->F, st(i)->R[r]); }))) return rc;
       if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->R[r], -1.0, st(i)->jd, st(i)->R[r]); }))) return rc;
     }

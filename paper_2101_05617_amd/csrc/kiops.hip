@@ -640,9 +640,13 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
     const float *q32 = prep_q32(c, st->q, fp32, rc);
     if (rc) return rc;
     for (int i = 0; i < st->P; ++i) {
-      // R_i = F(q_{n-i}) - F_n - J_n (q_{n-i} - q_n)   (Eq. 33 generalised)
+      // R_i = F(q_{n-i}) - F_n - J_n (q_{n-i} - q_n)   (Eq. 33 generalised).
+      // The remainder is a small difference of large terms, so its product
+      // is FP64 in every precision: a complex-FP32 product here leaves
+      // rounding noise in the b-vectors that the Krylov space must resolve
+      // (more products per step); the FP32 forms use FP32 inside KIOPS only.
       rc = launch_axpby(&c, n3, 1.0, st->hq[i], -1.0, st->q, st->d);
-      if (!rc) rc = launch_dfr(&c, st->q, q32, st->d, nullptr, st->eps, true, fp32, st->jd, nullptr);
+      if (!rc) rc = launch_dfr(&c, st->q, nullptr, st->d, nullptr, st->eps, true, false, st->jd, nullptr);
       if (!rc) rc = launch_axpby(&c, n3, 1.0, st->hF[i], -1.0, st->F, st->R[i]);
       if (!rc) rc = launch_axpby(&c, n3, 1.0, st->R[i], -1.0, st->jd, st->R[i]);
       if (rc) return rc;
