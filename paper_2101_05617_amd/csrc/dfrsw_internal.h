@@ -17,7 +17,10 @@ constexpr int MAX_NS = 8;        // p <= 7
 constexpr int MAX_M = 64;        // Krylov dimension cap
 constexpr int MAX_P = 8;         // phi-functions in one combination
 constexpr int BLOCK = 256;       // threads per block of the DFR and vector kernels
-constexpr int EXPM_BLOCK = 512;  // one workgroup of the small exponential: 17 x 17 4x4 tiles at m = 64
+#ifndef DFR_EXPM_BLOCK
+#define DFR_EXPM_BLOCK 1024
+#endif
+constexpr int EXPM_BLOCK = DFR_EXPM_BLOCK;  // one workgroup of the small exponential (a multiple of 64)
 
 void set_error(const std::string &msg);
 
@@ -88,6 +91,7 @@ struct ArnoldiArgs {
   int p;                  // number of W columns
   int start;              // 1: v_j is the sub-step's start vector
   const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
+  int wil;                // 1: W[0] holds the columns interleaved, 4 per value (p <= 4)
   const void *vprev;      // v~_{j-1} as stored (basis element type) or NULL (iop = 1)
   const double *pin;      // partial sums of the previous kernel, one per workgroup
   int np_in;
@@ -213,6 +217,7 @@ struct Ctx {
   size_t lds_limit = 65536;       // LDS one workgroup may use
   double *d_V = nullptr;          // (MAX_M + 1) top vectors of 3N (FP64, or FP32 when basis32)
   bool basis32 = false;           // the current KIOPS call keeps its basis in FP32
+  bool w_il = false;              // the current KIOPS call keeps W interleaved (W_IL)
   void *vslot(int k) const {
     return reinterpret_cast<char *>(d_V) + (size_t)k * (size_t)n3 * (basis32 ? sizeof(float) : sizeof(double));
   }
@@ -265,6 +270,8 @@ int launch_combine(Ctx *c, double *x);
 int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol);
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
+// W interleaved: out[4 i + k] = nu * cols[k][i] for k < p (NULL: zero), 0 for p <= k < 4
+int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out);
 int64_t diag_blocks(const Ctx *c);
 int launch_diagnostics(Ctx *c, const double *q, double *zeta, double *fcor);
 int launch_check_state(Ctx *c, const double *q);

@@ -471,11 +471,21 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   if (AR && active) {
     const double *ub = ar.kd->botu + ar.j * MAX_P;
     const double sp = ar.vprev ? ar.kd->sigma[ar.j - 1] : 0.0;   // v_{j-1} = sigma_{j-1} v~_{j-1}
+    double uw[4];   // the bottom entries paired with the interleaved columns (0 beyond p)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) uw[k] = k < ar.p ? (ar.start ? ar.ybot[k] : ub[k]) : 0.0;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int id = f * N + gidx;
       double a = 0.0;
-      for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
+      if (ar.wil) {
+        // four interleaved columns: two 16-byte loads per value
+        const double2 *w2 = reinterpret_cast<const double2 *>(ar.W[0]) + 2 * (int64_t)id;
+        const double2 x0 = w2[0], x1 = w2[1];
+        a = ((x0.x * uw[0] + x0.y * uw[1]) + x1.x * uw[2]) + x1.y * uw[3];
+      } else {
+        for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
+      }
       wb[f] = a;
       if (ar.vprev) vp[f] = sp * (double)static_cast<const TV *>(ar.vprev)[id];
     }
@@ -820,7 +830,12 @@ __device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3
   if (!arnoldi_prologue(ar, red, blk == 0, sig, bj)) return;
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     double acc = 0.0;
-    for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * bj[k];
+    if (ar.wil) {
+      const double *w = ar.W[0] + 4 * i;
+      for (int k = 0; k < ar.p; ++k) acc += w[k] * bj[k];
+    } else {
+      for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * bj[k];
+    }
     out[i] = (TV)acc;
   }
   if (threadIdx.x == 0) {
@@ -1888,6 +1903,34 @@ int launch_ode(Ctx *c, const double *q, const double *v, const double *vscale, b
     dfr_launch(c, kind, ode_kernel<true, true>, dim3(1), dim3(ODE_THREADS), 0, c->ode, q, v, vscale, out, a);
   else
     dfr_launch(c, kind, ode_kernel<true, false>, dim3(1), dim3(ODE_THREADS), 0, c->ode, q, v, vscale, out, a);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+__global__ __launch_bounds__(BLOCK) void w_interleave_kernel(int64_t n, int p, double nu, const double *c0,
+                                                             const double *c1, const double *c2, const double *c3,
+                                                             double *out) {
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+    double2 a, b;
+    a.x = (p > 0 && c0) ? nu * c0[i] : 0.0;
+    a.y = (p > 1 && c1) ? nu * c1[i] : 0.0;
+    b.x = (p > 2 && c2) ? nu * c2[i] : 0.0;
+    b.y = (p > 3 && c3) ? nu * c3[i] : 0.0;
+    double2 *o = reinterpret_cast<double2 *>(out) + 2 * i;
+    o[0] = a;
+    o[1] = b;
+  }
+}
+
+int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out) {
+  if (p > 4) {
+    set_error("interleaved W holds at most four columns");
+    return DFR_E_INVAL;
+  }
+  const double *k[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int i = 0; i < p; ++i) k[i] = cols[i];
+  dfr_launch(c, DFR_K_OTHER, w_interleave_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, n, p, nu, k[0], k[1], k[2], k[3],
+             out);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

@@ -132,9 +132,10 @@ void km_arnoldi_args(const KiopsMachine &k, const kiops_opts &o, ArnoldiArgs &ar
   ar.p = k.p;
   ar.start = (k.j == 0);
   for (int i = 0; i < k.p; ++i) {
-    ar.W[i] = c.d_W + i * n3;
+    ar.W[i] = c.w_il ? c.d_W : c.d_W + i * n3;
     ar.ybot[i] = k.ybot[i];
   }
+  ar.wil = c.w_il ? 1 : 0;
   ar.vprev = (k.j >= 1 && o.iop >= 2) ? c.vslot(k.j - 1) : nullptr;
   ar.pin = c.d_partials2;
   ar.np_in = k.npB;
@@ -234,10 +235,17 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
   const int64_t n3 = c.n3;
   int rc = kiops_validate(c, o, n_phi, tau_out);
   if (rc) return rc;
+  // layouts of this call (basis precision, interleaved W), reset on exit
   struct BasisMode {
     Ctx &c;
-    BasisMode(Ctx &cc, bool b32) : c(cc) { c.basis32 = b32; }
-    ~BasisMode() { c.basis32 = false; }
+    BasisMode(Ctx &cc, bool b32) : c(cc) {
+      c.basis32 = b32;
+      c.w_il = false;
+    }
+    ~BasisMode() {
+      c.basis32 = false;
+      c.w_il = false;
+    }
   } mode(c, fp32 && basis32);
   KiopsMachine k;
   k.c = &c;
@@ -260,10 +268,20 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
     return DFR_OK;
   }
   // W = nu [b_p, ..., b_1] (a zero column when there is no b_1); x = b_0
-  for (int i = 0; i < k.p; ++i) {
-    const double *bi = n_phi == 0 ? nullptr : b[k.p - i];
-    rc = launch_axpby(&c, n3, k.nu, bi, 0.0, nullptr, c.d_W + i * n3);
+  // with at most four columns (every EPI order) W is kept interleaved, so
+  // that the Krylov-form product reads it with wide loads
+  c.w_il = !c.ode_kind && k.p <= 4;
+  if (c.w_il) {
+    const double *cols[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int i = 0; i < k.p; ++i) cols[i] = n_phi == 0 ? nullptr : b[k.p - i];
+    rc = launch_w_interleave(&c, n3, k.p, k.nu, cols, c.d_W);
     if (rc) return rc;
+  } else {
+    for (int i = 0; i < k.p; ++i) {
+      const double *bi = n_phi == 0 ? nullptr : b[k.p - i];
+      rc = launch_axpby(&c, n3, k.nu, bi, 0.0, nullptr, c.d_W + i * n3);
+      if (rc) return rc;
+    }
   }
   c.kiops_p = k.p;
   c.kiops_mmax = k.m_max;

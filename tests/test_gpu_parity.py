@@ -169,7 +169,7 @@ def _kopts(tol, m_max, **kw):
     return dfrsw.kiops_opts(tol=tol, m_max=m_max, **kw)
 
 
-@pytest.mark.parametrize("nphi,with_b0", [(1, False), (3, False), (0, True), (2, True)])
+@pytest.mark.parametrize("nphi,with_b0", [(1, False), (3, False), (0, True), (2, True), (4, True), (6, False)])
 def test_kiops_parity(nphi, with_b0):
     w = small(C0, 3, 4, u_amp=1.0)
     G, D, Q = pair(w)
