@@ -42,11 +42,29 @@ template <typename T>
 __device__ __forceinline__ cx<T> cmul1(cx<T> a, cx<T> b) {
   return {a.r * b.r, fma(a.r, b.i, a.i * b.r)};
 }
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// lane exchange within rows of 16 lanes by DPP (register moves, no LDS):
+// CTRL 0xB1 swaps neighbours, 0x4E swaps pairs within a quad, 0x141 mirrors
+// each half-row, 0x140 mirrors each row
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// sum over the 64 lanes of a wave (every lane active), in a fixed order, the
+// same value in every lane: pairs, quads, half-rows and rows by DPP, then
+// the four row sums
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // block-wide sum over BLOCK threads in a fixed order (deterministic)
@@ -108,9 +126,7 @@ __device__ double reduce_fixed(const double *pin, int np, int stride, int off, d
   __syncthreads();
   if (threadIdx.x < 64) {
     const int l = threadIdx.x;
-    double v = (red[l] + red[l + 64]) + (red[l + 128] + red[l + 192]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const double v = wave_sum((red[l] + red[l + 64]) + (red[l + 128] + red[l + 192]));
     if (l == 0) red[0] = v;
   }
   __syncthreads();
@@ -135,13 +151,8 @@ __device__ void reduce_fixed2(const double *pin, int np, double *red, double &s0
   __syncthreads();
   if (threadIdx.x < 64) {
     const int l = threadIdx.x;
-    double x = (red[l] + red[l + 64]) + (red[l + 128] + red[l + 192]);
-    double y = (red[256 + l] + red[256 + l + 64]) + (red[256 + l + 128] + red[256 + l + 192]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      x += __shfl_xor(x, o, 64);
-      y += __shfl_xor(y, o, 64);
-    }
+    const double x = wave_sum((red[l] + red[l + 64]) + (red[l + 128] + red[l + 192]));
+    const double y = wave_sum((red[256 + l] + red[256 + l + 64]) + (red[256 + l + 128] + red[256 + l + 192]));
     if (l == 0) {
       red[0] = x;
       red[256] = y;
@@ -597,9 +608,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   if (AR && tid < 64) {
     // finish the reduction (the fixed butterfly of reduce_fixed) and the
     // prologue in the first wave; the results are read after two barriers
-    double x = (red[tid] + red[tid + 64]) + (red[tid + 128] + red[tid + 192]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    const double x = wave_sum((red[tid] + red[tid + 64]) + (red[tid + 128] + red[tid + 192]));
     double sg_, bj[MAX_P];
     const bool ok = arnoldi_finish(ar, x, tid, 64, lb == 0, sg_, bj);
     if (tid == 0) {
