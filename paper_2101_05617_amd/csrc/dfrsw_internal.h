@@ -351,6 +351,17 @@ int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi);
 int64_t dfr_num_tiles(const Ctx *c, bool arnoldi);
 std::vector<std::pair<int, int>> tile_candidates(const Ctx &c);   // admissible tiles (api.hip)
 int launch_norm2(Ctx *c, int64_t n, const double *x, double *partials, int nblk);
+// the squared 2-norms of k <= MAX_P + 1 vectors (NULL: 0) into out[0..k)
+// (device), two launches; partials: k * 1024 doubles of scratch
+int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *partials, double *out);
+// out_o = sum_i a[o][i] in_i for up to four inputs and four outputs (one pass)
+struct LinComb {
+  int nin, nout;
+  const double *in[4];
+  double *out[4];
+  double a[4][4];
+};
+int launch_lincomb(Ctx *c, int64_t n, const LinComb &lc);
 int launch_sum(Ctx *c, int np, const double *partials, double *out);
 
 }  // namespace dfrsw

@@ -1944,4 +1944,74 @@ int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const
   return DFR_OK;
 }
 
+// ||x_i||_2^2 of several vectors: per-workgroup partial sums in
+// partials[i * gridDim.x + blk], then one workgroup adds each set in a
+// fixed order
+struct VecSet {
+  const double *x[MAX_P + 1];
+};
+__global__ __launch_bounds__(BLOCK) void multi_norm2_kernel(int64_t n, int k, const VecSet vs, double *partials) {
+  __shared__ double red[BLOCK / 64];
+  for (int i = 0; i < k; ++i) {
+    const double *x = vs.x[i];
+    double acc = 0.0;
+    if (x)
+      for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK)
+        acc += x[j] * x[j];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = s;
+  }
+}
+__global__ __launch_bounds__(BLOCK) void multi_sum_kernel(int nb, int k, const double *partials, double *out) {
+  __shared__ double red[BLOCK / 64];
+  for (int i = 0; i < k; ++i) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BLOCK) acc += partials[(int64_t)i * nb + b];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) out[i] = s;
+  }
+}
+
+int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *partials, double *out) {
+  if (k < 1 || k > MAX_P + 1) {
+    set_error("launch_norms2: too many vectors");
+    return DFR_E_INVAL;
+  }
+  VecSet vs{};
+  for (int i = 0; i < k; ++i) vs.x[i] = x[i];
+  const int nb = grid_reduce(n);
+  dfr_launch(c, DFR_K_OTHER, multi_norm2_kernel, dim3(nb), dim3(BLOCK), 0, n, k, vs, partials);
+  DFR_HIP(hipGetLastError());
+  dfr_launch(c, DFR_K_FINALIZE, multi_sum_kernel, dim3(1), dim3(BLOCK), 0, nb, k, (const double *)partials, out);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+__global__ __launch_bounds__(BLOCK) void lincomb_kernel(int64_t n, const LinComb lc) {
+  for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
+    double x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = i < lc.nin ? lc.in[i][j] : 0.0;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      if (o >= lc.nout) break;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < lc.nin) s += lc.a[o][i] * x[i];
+      lc.out[o][j] = s;
+    }
+  }
+}
+
+int launch_lincomb(Ctx *c, int64_t n, const LinComb &lc) {
+  if (lc.nin < 1 || lc.nin > 4 || lc.nout < 1 || lc.nout > 4) {
+    set_error("launch_lincomb: one to four inputs and outputs");
+    return DFR_E_INVAL;
+  }
+  dfr_launch(c, DFR_K_OTHER, lincomb_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, n, lc);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
 }  // namespace dfrsw

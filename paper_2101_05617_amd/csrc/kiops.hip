@@ -39,24 +39,14 @@ namespace dfrsw {
 
 int latched_error(Ctx &c);
 
+// squared norms of the b-vectors: one pair of launches and one read-back
 static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
   const int64_t n3 = c.n3;
-  int64_t b = (n3 + BLOCK - 1) / BLOCK;
-  if (b > 2048) b = 2048;
-  double *d_out = (double *)c.d_expm_scratch;   // KHost block reused as 4 doubles
-  double got[MAX_P + 1];
-  for (int i = 0; i < k; ++i) {
-    if (!x[i]) {
-      got[i] = 0.0;
-      continue;
-    }
-    int rc = launch_norm2(&c, n3, x[i], c.d_partials, (int)b);
-    if (!rc) rc = launch_sum(&c, (int)b, c.d_partials, d_out);
-    if (rc) return rc;
-    DFR_HIP(hipMemcpyAsync(&got[i], d_out, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    DFR_HIP(hipStreamSynchronize(c.stream));
-  }
-  for (int i = 0; i < k; ++i) host_out[i] = got[i];
+  double *d_out = c.d_partials2;
+  int rc = launch_norms2(&c, n3, k, x, c.d_partials, d_out);
+  if (rc) return rc;
+  DFR_HIP(hipMemcpyAsync(host_out, d_out, sizeof(double) * k, hipMemcpyDeviceToHost, c.stream));
+  DFR_HIP(hipStreamSynchronize(c.stream));
   return DFR_OK;
 }
 
@@ -329,8 +319,7 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
     }
   }
   st = k.st;
-  DFR_HIP(hipStreamSynchronize(c.stream));
-  return latched_error(c);
+  return latched_error(c);   // synchronises the stream
 }
 
 // ---------------------------------------------------------------------------
@@ -665,28 +654,38 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
       // (more products per step); the FP32 forms use FP32 inside KIOPS only.
       rc = launch_axpby(&c, n3, 1.0, st->hq[i], -1.0, st->q, st->d);
       if (!rc) rc = launch_dfr(&c, st->q, nullptr, st->d, nullptr, st->eps, true, false, st->jd, nullptr);
-      if (!rc) rc = launch_axpby(&c, n3, 1.0, st->hF[i], -1.0, st->F, st->R[i]);
-      if (!rc) rc = launch_axpby(&c, n3, 1.0, st->R[i], -1.0, st->jd, st->R[i]);
+      if (!rc) {
+        LinComb lc{};
+        lc.nin = 3;
+        lc.nout = 1;
+        lc.in[0] = st->hF[i];
+        lc.in[1] = st->F;
+        lc.in[2] = st->jd;
+        lc.out[0] = st->R[i];
+        lc.a[0][0] = 1.0;
+        lc.a[0][1] = -1.0;
+        lc.a[0][2] = -1.0;
+        rc = launch_lincomb(&c, n3, lc);
+      }
       if (rc) return rc;
     }
     // b_1 = F_n, b_m = sum_i alpha_{m,i} R_i / dt^{m-1}
+    // (one pass over the remainders for all b_m, m = 2..M; M - 1 <= 3, P <= 4)
     std::vector<const double *> bb(st->M + 1, nullptr);
     bb[1] = st->F;
-    for (int m = 2; m <= st->M; ++m) {
-      double *bm = st->bm[m - 1];
-      bool first = true;
-      for (int i = 1; i <= st->P; ++i) {
-        const double a = st->A[m - 1][i - 1];
-        if (a == 0.0) continue;
-        if (first) rc = launch_axpby(&c, n3, a, st->R[i - 1], 0.0, nullptr, bm);
-        else rc = launch_axpby(&c, n3, 1.0, bm, a, st->R[i - 1], bm);
-        if (rc) return rc;
-        first = false;
+    if (st->M >= 2) {
+      LinComb lc{};
+      lc.nin = st->P;
+      lc.nout = st->M - 1;
+      for (int i = 0; i < st->P; ++i) lc.in[i] = st->R[i];
+      for (int m = 2; m <= st->M; ++m) {
+        const double sc = 1.0 / std::pow(st->dt, (double)(m - 1));
+        lc.out[m - 2] = st->bm[m - 1];
+        for (int i = 0; i < st->P; ++i) lc.a[m - 2][i] = st->A[m - 1][i] * sc;
+        bb[m] = st->bm[m - 1];
       }
-      if (first) DFR_HIP(hipMemsetAsync(bm, 0, sizeof(double) * n3, c.stream));
-      rc = launch_axpby(&c, n3, 1.0 / std::pow(st->dt, (double)(m - 1)), bm, 0.0, nullptr, bm);
+      rc = launch_lincomb(&c, n3, lc);
       if (rc) return rc;
-      bb[m] = bm;
     }
     KiopsRun r;
     rc = kiops_core(c, st->q, q32, st->dt, st->M, bb.data(), *o, st->eps, fp32, basis32, st->w, r);
@@ -697,8 +696,7 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
   }
   epi_rotate(st, q_new);
   if (q_out) DFR_HIP(hipMemcpyAsync(q_out, st->q, sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
-  DFR_HIP(hipStreamSynchronize(c.stream));
-  return latched_error(c);
+  return latched_error(c);   // synchronises the stream
 }
 
 int epi_step_concurrent(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *o, int n_workers,
