@@ -118,6 +118,13 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
                        const kiops_opts &o) {
   const int nk = (int)K.size();
   int rc = DFR_OK;
+  // interleaved W is a layout of this call only
+  struct WLayout {
+    std::vector<KiopsMachine> &K;
+    ~WLayout() {
+      for (auto &k : K) k.c->w_il = false;
+    }
+  } layout{K};
   // norms of every b_k: one launch of partial sums, one of finishing sums
   std::vector<AxpbyCall> nc, sc;
   std::vector<int> slot((size_t)nk * (MAX_P + 1), -1);
@@ -141,7 +148,8 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
   if ((rc = launch_vec_batch(E.stream, E.stage, VB_SUM, sc))) return rc;
   if (nres) DFR_HIP(hipMemcpyAsync(E.h_res, E.d_res, sizeof(double) * nres, hipMemcpyDeviceToHost, E.stream));
   if ((rc = sync_reset(E))) return rc;
-  // scaling, W = nu [b_p..b_1], x = b_0
+  // scaling, W = nu [b_p..b_1], x = b_0; with at most four columns W is
+  // interleaved (one launch per member), as in the single-member form
   std::vector<AxpbyCall> wc;
   for (int a = 0; a < nk; ++a) {
     KiopsMachine &k = K[a];
@@ -157,8 +165,15 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
       k.phase = KiopsMachine::DONE;
       continue;
     }
-    for (int i = 0; i < k.p; ++i)
-      wc.push_back(vcall(n3, k.nu, k.n_phi == 0 ? nullptr : k.b[k.p - i], 0.0, nullptr, c.d_W + i * n3));
+    c.w_il = !c.ode_kind && k.p <= 4;
+    if (c.w_il) {
+      const double *cols[4] = {nullptr, nullptr, nullptr, nullptr};
+      for (int i = 0; i < k.p; ++i) cols[i] = k.n_phi == 0 ? nullptr : k.b[k.p - i];
+      if ((rc = launch_w_interleave(&c, n3, k.p, k.nu, cols, c.d_W))) return rc;
+    } else {
+      for (int i = 0; i < k.p; ++i)
+        wc.push_back(vcall(n3, k.nu, k.n_phi == 0 ? nullptr : k.b[k.p - i], 0.0, nullptr, c.d_W + i * n3));
+    }
     c.kiops_p = k.p;
     c.kiops_mmax = k.m_max;
     wc.push_back(vcall(n3, 1.0, k.b[0], 0.0, nullptr, k.w));
