@@ -505,11 +505,14 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
   const bool fp32 = prec == DFR_FP32_JV;
   const int n = E->n;
   int rc = DFR_OK;
-  // a smooth state and a direction in every member's Krylov workspace
+  // a smooth state and a direction in every member's Krylov workspace, and
+  // four b-columns interleaved as KIOPS keeps them
   for (int i = 0; i < n && !rc; ++i) {
     Ctx &c = E->mem[i]->c;
     const int64_t n3 = 3 * c.n;
     rc = launch_fill(&c, c.d_V, c.d_V + n3);
+    const double *cols[4] = {c.d_V + n3, c.d_V + n3, c.d_V + n3, c.d_V + n3};
+    if (!rc) rc = launch_w_interleave(&c, n3, 4, 1.0, cols, c.d_W);
     if (!rc && fp32) rc = launch_copy_to_f32(&c, n3, c.d_V, (float *)c.d_qf32);
     if (!rc) DFR_HIP(hipMemsetAsync(&c.d_kd->happy, 0, sizeof(int), E->stream));
   }
@@ -545,7 +548,8 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
         ar.on = 1;
         ar.p = std::min(4, MAX_P);
         ar.start = 1;
-        for (int k = 0; k < ar.p; ++k) ar.W[k] = c.d_V + n3;
+        for (int k = 0; k < ar.p; ++k) ar.W[k] = c.d_W;
+        ar.wil = 1;
         ar.vprev = c.d_V;
         ar.pin = c.d_V;
         ar.np_in = 1;
@@ -556,16 +560,20 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
         calls.push_back(make_call(*E, i, true, q, c.d_V + n3, fp32 ? 1e-20 : 1e-150, c.d_V + 2 * n3, &ar));
         mem.push_back(i);
       }
-      float ms = 0.f;
+      // one untimed launch, then the fastest of three timed ones
+      float ms = 1e30f;
       for (int r = 0; r < 4 && !rc; ++r) {
-        if (r == 1) (void)hipEventRecord(e0, E->stream);
+        if (r > 0) (void)hipEventRecord(e0, E->stream);
         std::vector<DfrCall> cc = calls;
         rc = launch_dfr_groups(*E, mem, cc, true, fp32, true);
+        if (rc || r == 0) continue;
+        (void)hipEventRecord(e1, E->stream);
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        ms = std::min(ms, t);
       }
       if (rc) break;
-      (void)hipEventRecord(e1, E->stream);
-      (void)hipEventSynchronize(e1);
-      (void)hipEventElapsedTime(&ms, e0, e1);
       reset_stage(E->stage);
       if (ms < best) {
         best = ms;

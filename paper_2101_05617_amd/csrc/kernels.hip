@@ -116,13 +116,27 @@ __device__ __forceinline__ int64_t logical_block(int64_t nlogical) {
 // (always 64 lanes) adds them in a fixed pattern and a fixed butterfly.  Every
 // workgroup of every kernel gets the identical value.  red: 256 doubles of
 // LDS.  Call from all threads of the workgroup; valid in every thread.
+// One virtual lane l's share: the values k = l, l + 256, ... added in
+// increasing k (a missing value adds 0.0, which leaves the sum unchanged);
+// the loads of each group of four are issued together.
+__device__ __forceinline__ double lane_sum(const double *pin, int np, int stride, int off, int l) {
+  double s = 0.0;
+  for (int k0 = l; k0 < np; k0 += 1024) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 256 * u;
+      x[u] = k < np ? pin[(int64_t)k * stride + off] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += x[u];
+  }
+  return s;
+}
+
 __device__ double reduce_fixed(const double *pin, int np, int stride, int off, double *red) {
   __syncthreads();
-  for (int l = threadIdx.x; l < 256; l += blockDim.x) {
-    double s = 0.0;
-    for (int k = l; k < np; k += 256) s += pin[(int64_t)k * stride + off];
-    red[l] = s;
-  }
+  for (int l = threadIdx.x; l < 256; l += blockDim.x) red[l] = lane_sum(pin, np, stride, off, l);
   __syncthreads();
   if (threadIdx.x < 64) {
     const int l = threadIdx.x;
@@ -135,19 +149,11 @@ __device__ double reduce_fixed(const double *pin, int np, int stride, int off, d
   return r;
 }
 
-// reduce_fixed of the two interleaved sets pin[2k] and pin[2k+1] in one
-// pass (the same order, hence the same values).  red: 512 doubles of LDS.
-__device__ void reduce_fixed2(const double *pin, int np, double *red, double &s0, double &s1) {
-  __syncthreads();
-  for (int l = threadIdx.x; l < 256; l += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int k = l; k < np; k += 256) {
-      a += pin[2 * (int64_t)k];
-      b += pin[2 * (int64_t)k + 1];
-    }
-    red[l] = a;
-    red[256 + l] = b;
-  }
+// The end of a fixed-order reduction of two interleaved sets pin[2k],
+// pin[2k+1] (the order of reduce_fixed, hence the same values), once each
+// virtual lane l < 256 has left its shares in red[l] and red[256 + l]; red:
+// 512 doubles of LDS.  Valid in every thread.
+__device__ void reduce_fixed2_finish(double *red, double &s0, double &s1) {
   __syncthreads();
   if (threadIdx.x < 64) {
     const int l = threadIdx.x;
@@ -867,56 +873,105 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__
 // 0.  Body: w <- w - h_jj sigma_j v~_j - h_{j-1,j} sigma_{j-1} v~_{j-1};
 // partial ||w||^2 per workgroup.  Basis vectors stay as built (v~_k), their
 // scales sigma_k kept in KDev.  The first UNROLL elements of each thread are
-// read before the prologue, in flight during its reductions.
+// read before the prologue, in flight during its reductions.  With !two the
+// third stream rereads v~_j, multiplied by a zero coefficient.
 template <typename TV>
 __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n3, int j, int p, TV *w,
                                                     const TV *vj, const TV *vprev, const double *pin,
                                                     int np_in, double *pout, KDev *kd) {
   constexpr int UNROLL = 4;
+  static_assert(BLOCK == 256, "one virtual lane of the fixed-order reduction per thread");
   __shared__ double red[512];
   const bool two = (j >= 1) && (vprev != nullptr);
   const int64_t gs = (int64_t)nblk * BLOCK;
   const int64_t i0 = (int64_t)blk * BLOCK + threadIdx.x;
+  // This thread's first four partial pairs (virtual lane threadIdx.x of the
+  // fixed-order reduction), issued before the data: waiting for them then
+  // does not wait for the data.  All loads here are unconditional, at
+  // clamped indices (np_in >= 1, n3 >= 1), so that the wait is exact.
+  const int l = threadIdx.x;
+  double pa[4], pb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = min(l + 256 * u, np_in - 1);
+    pa[u] = pin[2 * (int64_t)k];
+    pb[u] = pin[2 * (int64_t)k + 1];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  const TV *vp2 = two ? vprev : vj;
   double xw[UNROLL], xv[UNROLL], xp[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
-    const int64_t i = i0 + u * gs;
-    xw[u] = xv[u] = xp[u] = 0.0;
-    if (i < n3) {
-      xw[u] = (double)w[i];
-      xv[u] = (double)vj[i];
-      if (two) xp[u] = (double)vprev[i];
-    }
+    const int64_t i = i0 + u * gs < n3 ? i0 + u * gs : n3 - 1;
+    xw[u] = (double)w[i];
+    xv[u] = (double)vj[i];
+    xp[u] = (double)vp2[i];
   }
-  if (kd->happy) return;
-  double d0, d1;
-  reduce_fixed2(pin, np_in, red, d0, d1);
-  const int ld = MAX_M + 2;
+  // the bottom blocks b_j, b_{j-1} and the scales, read ahead of the
+  // reduction's barriers (whole rows of MAX_P values: no branch on p)
   const double *bj = kd->bot + j * MAX_P;
   const double *bp = kd->bot + (j - (j >= 1 ? 1 : 0)) * MAX_P;
+  double bjv[MAX_P], bpv[MAX_P];
+#pragma unroll
+  for (int k = 0; k < MAX_P; ++k) {
+    bjv[k] = bj[k];
+    bpv[k] = bp[k];
+  }
+  const double sgj = kd->sigma[j], sgp = kd->sigma[j - (j >= 1 ? 1 : 0)];
+  // After a happy breakdown (uniform) nothing is written; the reductions
+  // still run, so that no branch ahead of them holds back the loads above.
+  const bool happy = kd->happy != 0;
+  double d0, d1;
+  {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = l + 256 * u < np_in;
+      a += in ? pa[u] : 0.0;
+      b += in ? pb[u] : 0.0;
+    }
+    for (int k = l + 1024; k < np_in; k += 256) {
+      a += pin[2 * (int64_t)k];
+      b += pin[2 * (int64_t)k + 1];
+    }
+    red[l] = a;
+    red[256 + l] = b;
+    reduce_fixed2_finish(red, d0, d1);
+  }
+  const int ld = MAX_M + 2;
+  // (loops over all MAX_P slots, unrolled, with k < p selecting: no
+  // run-time index into the register arrays)
   double wb[MAX_P];
-  for (int k = 0; k < p; ++k) wb[k] = (k + 1 < p) ? bj[k + 1] : 0.0;   // K b_j (upper shift)
+#pragma unroll
+  for (int k = 0; k < MAX_P; ++k) wb[k] = (k + 1 < MAX_P && k + 1 < p) ? bjv[k + 1 < MAX_P ? k + 1 : 0] : 0.0;   // K b_j
   double hjj = d0, hpj = d1;
-  for (int k = 0; k < p; ++k) hjj += bj[k] * wb[k];
+#pragma unroll
+  for (int k = 0; k < MAX_P; ++k)
+    if (k < p) hjj += bjv[k] * wb[k];
   if (two) {
-    for (int k = 0; k < p; ++k) hpj += bp[k] * wb[k];
+#pragma unroll
+    for (int k = 0; k < MAX_P; ++k)
+      if (k < p) hpj += bpv[k] * wb[k];
   } else {
     hpj = 0.0;
   }
-  if (blk == 0 && threadIdx.x == 0) {
+  if (!happy && blk == 0 && threadIdx.x == 0) {
     kd->H[j * ld + j] = hjj;
     if (two) kd->H[(j - 1) * ld + j] = hpj;
     double nb2 = 0.0;
-    for (int k = 0; k < p; ++k) {
-      double v = wb[k] - hjj * bj[k];
-      if (two) v -= hpj * bp[k];
-      kd->botu[(j + 1) * MAX_P + k] = v;
-      nb2 += v * v;
+#pragma unroll
+    for (int k = 0; k < MAX_P; ++k) {
+      if (k < p) {
+        double v = wb[k] - hjj * bjv[k];
+        if (two) v -= hpj * bpv[k];
+        kd->botu[(j + 1) * MAX_P + k] = v;
+        nb2 += v * v;
+      }
     }
     kd->wn2[j + 1] = nb2;
   }
-  const double ca = hjj * kd->sigma[j];
-  const double cb = two ? hpj * kd->sigma[j - 1] : 0.0;
+  const double ca = hjj * sgj;
+  const double cb = two ? hpj * sgp : 0.0;
   double acc = 0.0;
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
@@ -924,11 +979,11 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
     if (i < n3) {
       // the norm is that of the vector as stored (rounded to the basis type)
       const TV x = (TV)((xw[u] - ca * xv[u]) - cb * xp[u]);
-      w[i] = x;
+      if (!happy) w[i] = x;
       acc += (double)x * (double)x;
     }
   }
-  for (int64_t i = i0 + UNROLL * gs; i < n3; i += gs) {
+  for (int64_t i = i0 + UNROLL * gs; i < (happy ? 0 : n3); i += gs) {
     double y = (double)w[i] - ca * (double)vj[i];
     if (two) y -= cb * (double)vprev[i];
     const TV x = (TV)y;
@@ -936,7 +991,7 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
     acc += (double)x * (double)x;
   }
   const double b = block_sum(acc, red);
-  if (threadIdx.x == 0) pout[blk] = b;
+  if (!happy && threadIdx.x == 0) pout[blk] = b;
 }
 template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, TV *w, const TV *vj,
