@@ -12,6 +12,7 @@
 #include "dfrsw_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -411,8 +412,9 @@ static int alloc_workspace(Ctx &c) {
   DFR_HIP(hipMemset(c.d_counter, 0, sizeof(unsigned)));
   DFR_HIP(hipMalloc(&c.d_kd, sizeof(KDev)));
   DFR_HIP(hipMemset(c.d_kd, 0, sizeof(KDev)));
-  DFR_HIP(hipMalloc(&c.d_expm_scratch, sizeof(KHost)));
-  DFR_HIP(hipHostMalloc((void **)&c.h_res, sizeof(KHost), hipHostMallocDefault));
+  DFR_HIP(hipHostMalloc((void **)&c.mail, sizeof(HostMail), hipHostMallocCoherent | hipHostMallocMapped));
+  std::memset(c.mail, 0, sizeof(HostMail));
+  DFR_HIP(hipHostGetDevicePointer((void **)&c.d_mail, c.mail, 0));
   DFR_HIP(hipMalloc(&c.d_V, sizeof(double) * (MAX_M + 1) * n3));
   DFR_HIP(hipMalloc(&c.d_W, sizeof(double) * MAX_P * n3));
   DFR_HIP(hipMalloc(&c.d_qf32, sizeof(float) * n3));
@@ -452,8 +454,7 @@ static void free_ctx(Ctx &c) {
   (void)hipFree(c.d_partials2);
   (void)hipFree(c.d_counter);
   (void)hipFree(c.d_kd);
-  (void)hipFree(c.d_expm_scratch);
-  if (c.h_res) (void)hipHostFree(c.h_res);
+  if (c.mail) (void)hipHostFree(c.mail);
   (void)hipFree(c.d_V);
   (void)hipFree(c.d_W);
   (void)hipFree(c.d_qf32);
@@ -506,14 +507,43 @@ static void timing_fold(Ctx &c) {
   c.evused = 0;
 }
 
+// Wait for the kernel result numbered seq in the context's host mail: poll
+// its sequence number, and the stream's status every 256 polls (an idle
+// stream without the number, or a stream error, ends the wait).
+int mail_wait(Ctx &c, unsigned seq) {
+  volatile unsigned *s = &c.mail->seq;
+  for (unsigned it = 1;; ++it) {
+    if (*s == seq) break;
+    if ((it & 255) == 0) {
+      const hipError_t q = hipStreamQuery(c.stream);
+      if (q == hipSuccess) {
+        if (*s == seq) break;
+        set_error("a kernel result did not reach the host");
+        return DFR_E_HIP;
+      }
+      if (q != hipErrorNotReady) {
+        set_error(std::string("HIP error: ") + hipGetErrorString(q));
+        return DFR_E_HIP;
+      }
+    }
+#if defined(__x86_64__)
+    __builtin_ia32_pause();
+#endif
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  return DFR_OK;
+}
+
+// The flags latched by the kernels (bit 0: a non-finite input, bit 1: a
+// non-positive depth), read and cleared in stream order; when it returns,
+// every earlier operation on the stream has finished.
 int latched_error(Ctx &c) {
-  int flag = 0;
-  DFR_HIP(hipMemcpyAsync(&c.h_res->pad[0], c.d_err, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-  DFR_HIP(hipStreamSynchronize(c.stream));
-  flag = c.h_res->pad[0];
+  const unsigned seq = ++c.mail_seq;
+  int rc = launch_err_mail(&c, seq);
+  if (!rc) rc = mail_wait(c, seq);
+  if (rc) return rc;
+  const int flag = c.mail->err;
   if (flag) {
-    DFR_HIP(hipMemsetAsync(c.d_err, 0, sizeof(int), c.stream));
-    DFR_HIP(hipStreamSynchronize(c.stream));
     if (flag & 1) {
       set_error("non-finite value in an input state");
       return DFR_E_NONFINITE;

@@ -186,6 +186,16 @@ struct KHost {
   int J, happy, pad[2];
 };
 
+// Results the host waits for inside KIOPS, written by the kernels that
+// produce them straight into mapped, coherent host memory; seq is written
+// last, after a system-scope fence, and the host polls it.
+struct HostMail {
+  KHost kh;
+  double nrm2[MAX_P + 1];
+  int err;                        // the latched error flags, handed over and cleared
+  unsigned seq;
+};
+
 struct Ctx {
   int ne, ns, p_deg;
   int64_t n, nelem;
@@ -226,8 +236,9 @@ struct Ctx {
   double *d_partials2 = nullptr;  // per-block partial sums (norms)
   unsigned *d_counter = nullptr;
   KDev *d_kd = nullptr;
-  double *d_expm_scratch = nullptr;
-  KHost *h_res = nullptr;         // pinned
+  HostMail *mail = nullptr;       // mapped host memory (host address)
+  HostMail *d_mail = nullptr;     // the same memory, device address
+  unsigned mail_seq = 0;          // last sequence number asked for
   double *d_qf32 = nullptr;       // FP32 copy of the linearisation state (as float*)
   double *d_tmp = nullptr;        // scratch vector 3N
   // optional per-kernel event timing
@@ -267,7 +278,7 @@ int launch_update(Ctx *c, int j, void *w, const void *vj, const void *vprev, con
                   double *pout, int *np_out);
 int launch_start(Ctx *c, const double *x, void *v0, double *pout, int *np_out);
 int launch_combine(Ctx *c, double *x);
-int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol);
+int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol, unsigned seq);   // -> d_mail
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
 // W interleaved: out[4 i + k] = nu * cols[k][i] for k < p (NULL: zero), 0 for p <= k < 4
@@ -353,7 +364,9 @@ std::vector<std::pair<int, int>> tile_candidates(const Ctx &c);   // admissible 
 int launch_norm2(Ctx *c, int64_t n, const double *x, double *partials, int nblk);
 // the squared 2-norms of k <= MAX_P + 1 vectors (NULL: 0) into out[0..k)
 // (device), two launches; partials: k * 1024 doubles of scratch
-int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *partials, double *out);
+int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *partials, unsigned seq);   // -> d_mail
+int launch_err_mail(Ctx *c, unsigned seq);   // d_err -> d_mail->err, d_err cleared
+int mail_wait(Ctx &c, unsigned seq);          // wait for result seq in c.mail (api.hip)
 // out_o = sum_i a[o][i] in_i for up to four inputs and four outputs (one pass)
 struct LinComb {
   int nin, nout;

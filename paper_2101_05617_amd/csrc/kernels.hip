@@ -1120,7 +1120,7 @@ size_t expm_lds_bytes(int m) {
 }
 
 __device__ __forceinline__ void expm_body(KDev *kd, double tau, KHost *res, int jfin, const double *pin, int np_in,
-                                          double tol) {
+                                          double tol, unsigned *seq_out, unsigned seq) {
   extern __shared__ double lds[];
   __shared__ double red[256];
   __shared__ double cnorm;
@@ -1240,16 +1240,20 @@ __device__ __forceinline__ void expm_body(KDev *kd, double tau, KHost *res, int 
     res->eJ = eJ;
     res->J = J;
     res->happy = kd->happy;
+    if (seq_out) {   // a host-memory result: the sequence number last
+      __threadfence_system();
+      *(volatile unsigned *)seq_out = seq;
+    }
   }
 }
 __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, KHost *res, int jfin, const double *pin,
-                                                          int np_in, double tol) {
-  expm_body(kd, tau, res, jfin, pin, np_in, tol);
+                                                          int np_in, double tol, unsigned *seq_out, unsigned seq) {
+  expm_body(kd, tau, res, jfin, pin, np_in, tol, seq_out, seq);
 }
 // one workgroup per member
 __global__ __launch_bounds__(EXPM_BLOCK) void expm_batch(const ExpmCall *__restrict__ calls) {
   const ExpmCall &c = calls[blockIdx.x];
-  expm_body(c.kd, c.tau, c.res, c.jfin, c.pin, c.np_in, c.tol);
+  expm_body(c.kd, c.tau, c.res, c.jfin, c.pin, c.np_in, c.tol, nullptr, 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -1754,9 +1758,10 @@ int launch_combine(Ctx *c, double *x) {
   return DFR_OK;
 }
 
-int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol) {
+int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol, unsigned seq) {
   const size_t lds = expm_lds_bytes(c->kiops_mmax);
-  dfr_launch(c, DFR_K_EXPM, expm_kernel, dim3(1), dim3(EXPM_BLOCK), lds, c->d_kd, tau, (KHost *)c->d_expm_scratch, jfin, pin, np_in, tol);
+  dfr_launch(c, DFR_K_EXPM, expm_kernel, dim3(1), dim3(EXPM_BLOCK), lds, c->d_kd, tau, &c->d_mail->kh, jfin, pin, np_in,
+             tol, &c->d_mail->seq, seq);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
@@ -2017,7 +2022,8 @@ __global__ __launch_bounds__(BLOCK) void multi_norm2_kernel(int64_t n, int k, co
     if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = s;
   }
 }
-__global__ __launch_bounds__(BLOCK) void multi_sum_kernel(int nb, int k, const double *partials, double *out) {
+__global__ __launch_bounds__(BLOCK) void multi_sum_kernel(int nb, int k, const double *partials, double *out,
+                                                          unsigned *seq_out, unsigned seq) {
   __shared__ double red[BLOCK / 64];
   for (int i = 0; i < k; ++i) {
     double acc = 0.0;
@@ -2025,9 +2031,28 @@ __global__ __launch_bounds__(BLOCK) void multi_sum_kernel(int nb, int k, const d
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) out[i] = s;
   }
+  if (threadIdx.x == 0) {   // host-memory results: the sequence number last
+    __threadfence_system();
+    *(volatile unsigned *)seq_out = seq;
+  }
 }
 
-int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *partials, double *out) {
+// the latched error flags handed to the host and cleared, in stream order
+__global__ void err_mail_kernel(int *err, int *out, unsigned *seq_out, unsigned seq) {
+  if (threadIdx.x == 0) {
+    *(volatile int *)out = atomicExch(err, 0);
+    __threadfence_system();
+    *(volatile unsigned *)seq_out = seq;
+  }
+}
+
+int launch_err_mail(Ctx *c, unsigned seq) {
+  hipLaunchKernelGGL(err_mail_kernel, dim3(1), dim3(64), 0, c->stream, c->d_err, &c->d_mail->err, &c->d_mail->seq, seq);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *partials, unsigned seq) {
   if (k < 1 || k > MAX_P + 1) {
     set_error("launch_norms2: too many vectors");
     return DFR_E_INVAL;
@@ -2037,7 +2062,8 @@ int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *part
   const int nb = grid_reduce(n);
   dfr_launch(c, DFR_K_OTHER, multi_norm2_kernel, dim3(nb), dim3(BLOCK), 0, n, k, vs, partials);
   DFR_HIP(hipGetLastError());
-  dfr_launch(c, DFR_K_FINALIZE, multi_sum_kernel, dim3(1), dim3(BLOCK), 0, nb, k, (const double *)partials, out);
+  dfr_launch(c, DFR_K_FINALIZE, multi_sum_kernel, dim3(1), dim3(BLOCK), 0, nb, k, (const double *)partials,
+             c->d_mail->nrm2, &c->d_mail->seq, seq);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

@@ -39,14 +39,14 @@ namespace dfrsw {
 
 int latched_error(Ctx &c);
 
-// squared norms of the b-vectors: one pair of launches and one read-back
+// squared norms of the b-vectors: one pair of launches, the sums written to
+// host memory
 static int norms2(Ctx &c, int k, const double *const *x, double *host_out) {
-  const int64_t n3 = c.n3;
-  double *d_out = c.d_partials2;
-  int rc = launch_norms2(&c, n3, k, x, c.d_partials, d_out);
+  const unsigned seq = ++c.mail_seq;
+  int rc = launch_norms2(&c, c.n3, k, x, c.d_partials, seq);
   if (rc) return rc;
-  DFR_HIP(hipMemcpyAsync(host_out, d_out, sizeof(double) * k, hipMemcpyDeviceToHost, c.stream));
-  DFR_HIP(hipStreamSynchronize(c.stream));
+  if ((rc = mail_wait(c, seq))) return rc;
+  for (int i = 0; i < k; ++i) host_out[i] = c.mail->nrm2[i];
   return DFR_OK;
 }
 
@@ -302,12 +302,13 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
       if (rc) return rc;
       ++k.j;
     }
-    rc = launch_expm(&c, k.tau, k.j, pB, k.npB, o.tol);
+    const unsigned seq = ++c.mail_seq;
+    rc = launch_expm(&c, k.tau, k.j, pB, k.npB, o.tol, seq);
     if (rc) return rc;
-    DFR_HIP(hipMemcpyAsync(c.h_res, c.d_expm_scratch, sizeof(KHost), hipMemcpyDeviceToHost, c.stream));
-    DFR_HIP(hipStreamSynchronize(c.stream));
+    if ((rc = mail_wait(c, seq))) return rc;
+    const KHost kh = c.mail->kh;
     bool accept = false;
-    rc = km_decide(k, *c.h_res, o, &accept);
+    rc = km_decide(k, kh, o, &accept);
     if (rc == DFR_E_NONFINITE) {
       const int le = latched_error(c);
       return le ? le : rc;
