@@ -1106,9 +1106,11 @@ __device__ void lds_matvec(const double *X, int ld, const double *x, int xs, dou
     const int i = t >> 3, part = t & 7;
     double s = 0.0;
     for (int k = part; k < P; k += 8) s = fma(X[i * ld + k], x[k * xs], s);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
+    // the eight lanes of a row (whole waves take part: 8P is a multiple of
+    // 64): pairs, quads, then the two quads of the half-row, by DPP
+    s += dpp_mov<0xB1>(s);
+    s += dpp_mov<0x4E>(s);
+    s += dpp_mov<0x141>(s);
     if (part == 0) y[i * ys] = epi(i, s);
   }
 }
@@ -1154,14 +1156,17 @@ __device__ __forceinline__ void expm_body(KDev *kd, double tau, KHost *res, int 
     const int j = idx >> 2, part = idx & 3;
     double cs = 0.0;
     for (int i = part; i < P; i += 4) cs += fabs(A[i * ld + j]);
-    cs += __shfl_xor(cs, 1, 64);
-    cs += __shfl_xor(cs, 2, 64);
+    cs += dpp_mov<0xB1>(cs);   // the four lanes of a column (4P: whole waves)
+    cs += dpp_mov<0x4E>(cs);
     cm = fmax(cm, cs);
   }
   {
     double v = cm;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    v = fmax(v, dpp_mov<0xB1>(v));
+    v = fmax(v, dpp_mov<0x4E>(v));
+    v = fmax(v, dpp_mov<0x141>(v));
+    v = fmax(v, dpp_mov<0x140>(v));
+    v = fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
