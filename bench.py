@@ -159,8 +159,14 @@ def mixed_study(steps):
     from paper_2101_05617_amd import dfrsw, inputs
     w = inputs.WORKLOADS["c2_ne60_p6_jet"]
     opts = dfrsw.kiops_opts(tol=w.tol, m_max=w.m_max)
+    # the stated-error comparison: KIOPS tolerance one decade above the
+    # relative noise of a complex-FP32 product (about 1e-7)
+    tol_matched = 1e-6
+    opts_matched = dfrsw.kiops_opts(tol=tol_matched, m_max=w.m_max)
     res, finals = {}, {}
-    for prec, eps in (("fp64", 1e-150), ("fp32_jv", w.eps)):
+    for name, prec, eps, opts in (("fp64", "fp64", 1e-150, opts), ("fp32_jv", "fp32_jv", w.eps, opts),
+                                  ("fp32_jv_tol1e-6", "fp32_jv", w.eps, opts_matched),
+                                  ("fp64_tol1e-6", "fp64", 1e-150, opts_matched)):
         g = dfrsw.Grid(w.ne, w.p, *w.constants())
         dfrsw.dfr_autotune(g, prec)
         P, B1, B2 = g.node_frames()
@@ -178,24 +184,39 @@ def mixed_study(steps):
                 t_startup = time.perf_counter()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        finals[prec] = dfrsw.epi_get_state(st).cpu().numpy()
+        finals[name] = dfrsw.epi_get_state(st).cpu().numpy()
         n_after = steps - (w.order - 2)
-        res[prec] = {"steps_per_s": steps / (t1 - t0), "wall_s": t1 - t0, "jv_per_step": nmv / steps,
+        res[name] = {"steps_per_s": steps / (t1 - t0), "wall_s": t1 - t0, "jv_per_step": nmv / steps,
                      "epi6_steps_per_s_after_startup": n_after / (t1 - t_startup) if t_startup else None,
                      "tile": dfrsw.dfr_get_tile(g), "tile_krylov": dfrsw.dfr_get_krylov_tile(g)}
-        log(f"c2 {prec}: {steps} steps in {t1 - t0:.2f}s, {nmv / steps:.0f} J*v/step")
+        log(f"c2 {name}: {steps} steps in {t1 - t0:.2f}s, {nmv / steps:.0f} J*v/step")
         del st, g
         torch.cuda.synchronize()
     N = w.n_nodes
-    a, b = finals["fp32_jv"], finals["fp64"]
-    err_h = float(np.linalg.norm(a[:N] - b[:N]) / np.linalg.norm(b[:N]))
-    err_all = max(float(np.linalg.norm(a[f * N:(f + 1) * N] - b[f * N:(f + 1) * N]) /
-                        np.linalg.norm(b[f * N:(f + 1) * N])) for f in range(3))
+
+    def errs(name):
+        a, b = finals[name], finals["fp64"]
+        err_h = float(np.linalg.norm(a[:N] - b[:N]) / np.linalg.norm(b[:N]))
+        err_all = max(float(np.linalg.norm(a[f * N:(f + 1) * N] - b[f * N:(f + 1) * N]) /
+                            np.linalg.norm(b[f * N:(f + 1) * N])) for f in range(3))
+        return err_h, err_all
+    err_h, err_all = errs("fp32_jv")
+    em_h, em_all = errs("fp32_jv_tol1e-6")
+    e64_h, e64_all = errs("fp64_tol1e-6")
+    base = res["fp64"]["steps_per_s"]
     return {"workload": f"{w.name}: ne={w.ne}, p={w.p} ({N} nodes), EPI6, dt={w.dt_s:g}s, {steps} steps "
                         f"({steps * w.dt_s / 86400:g} days), tol {w.tol:g}, m<={w.m_max}",
             "fp64": res["fp64"], "fp32_jv": res["fp32_jv"],
-            "speedup_mixed_over_fp64": res["fp32_jv"]["steps_per_s"] / res["fp64"]["steps_per_s"],
-            "rel_l2_error_h_mixed_vs_fp64": err_h, "rel_l2_error_max_field": err_all}
+            "speedup_mixed_over_fp64": res["fp32_jv"]["steps_per_s"] / base,
+            "rel_l2_error_h_mixed_vs_fp64": err_h, "rel_l2_error_max_field": err_all,
+            "at_stated_error": {
+                "note": f"KIOPS tol {tol_matched:g} (one decade above the complex-FP32 product's relative "
+                        f"noise); error and speed-up against plain FP64 at tol {w.tol:g}",
+                "fp32_jv": res["fp32_jv_tol1e-6"], "fp64": res["fp64_tol1e-6"],
+                "speedup_mixed_over_fp64": res["fp32_jv_tol1e-6"]["steps_per_s"] / base,
+                "speedup_fp64_over_fp64": res["fp64_tol1e-6"]["steps_per_s"] / base,
+                "rel_l2_error_h_mixed": em_h, "rel_l2_error_max_field_mixed": em_all,
+                "rel_l2_error_h_fp64": e64_h, "rel_l2_error_max_field_fp64": e64_all}}
 
 
 def ensemble_study(n_members, steps, n_workers):
