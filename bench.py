@@ -25,6 +25,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6    # MI355X, FP64 vector (and FP64 matrix) peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, FP32 vector peak
 METRIC = "complex-step Jv/s + EPI steps/s, FP64 plain vs FP32-Jv batched at stated error"
 
 
@@ -131,8 +133,67 @@ def summarize_profile(args):
         lines.append(f"traffic_bytes_per_launch: {traffic['FETCH_SIZE'] + traffic['WRITE_SIZE']:.0f} "
                      f"fetch {traffic['FETCH_SIZE']:.0f} write {traffic['WRITE_SIZE']:.0f} "
                      f"kernel_source: {kernel_source_digest()}")
+    # further counter passes: the mean of every counter over the selected
+    # kernel's last N dispatches
+    util = {}
+    for d in args.counters or []:
+        cc = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
+              if args.kernel in r["Kernel_Name"]]
+        by = {}
+        for r in cc:
+            by.setdefault(r["Counter_Name"], []).append((int(r.get("Dispatch_Id") or 0), float(r["Counter_Value"])))
+        for name, v in sorted(by.items()):
+            v.sort()
+            v = [x for _, x in (v[-args.last:] if args.last else v)]
+            util[name] = sum(v) / len(v)
+            lines.append(f"counter {name}: mean {util[name]:.6g} over {len(v)} dispatches")
+    if util:
+        lines.append("utilisation: " + " ".join(f"{k}={v:.6g}" for k, v in sorted(util.items())) +
+                     f" kernel_source: {kernel_source_digest()}")
     print("\n".join(lines))
     return 0
+
+
+def profiled_utilisation(name):
+    """Counter means (VALUBusy, LdsUtil, ...) recorded in profiles/<name> for
+    the current kernel source, or None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("utilisation:"):
+            parts = line.split()
+            if parts[-1] != kernel_source_digest():
+                return None
+            return {k: float(v) for k, v in (p.split("=") for p in parts[1:-2])}
+    return None
+
+
+def utilisation_summary(name, avg_us):
+    """The recorded counter means of profiles/<name> as percentages against the
+    chip (VALU busy, LDS busy, occupancy, matrix-core busy, active lanes per
+    VALU instruction) and the FP64 / FP32 vector flops per launch as TFLOP/s
+    over `avg_us` (default: the profile's own timed average) against the
+    vector peaks; None without a record for the current kernel source."""
+    u = profiled_utilisation(name)
+    if not u:
+        return None
+    if not avg_us:   # the profile's own timed average
+        for line in open(os.path.join(ROOT, "profiles", name)):
+            if line.startswith("timed_region_avg_us:"):
+                avg_us = float(line.split()[1])
+    out = {k2: u.get(k1) for k1, k2 in (("VALUBusy", "valu_busy_pct"), ("LdsUtil", "lds_util_pct"),
+                                         ("OccupancyPercent", "occupancy_pct"), ("MfmaUtil", "mfma_util_pct"),
+                                         ("VALUUtilization", "valu_active_lanes_pct"))}
+    for key, peak, tag in (("SQ_INSTS_VALU_FLOPS_FP64", FP64_VECTOR_PEAK_TFLOPS, "fp64"),
+                           ("SQ_INSTS_VALU_FLOPS_FP32", FP32_VECTOR_PEAK_TFLOPS, "fp32")):
+        if key in u and avg_us:
+            # the counter adds an instruction's flops once per wave: x 64 lanes
+            # (issued lane slots; inactive lanes included)
+            tf = u[key] * 64 / (avg_us * 1e-6) / 1e12
+            out[f"valu_{tag}_tflops"] = tf
+            out[f"valu_{tag}_frac_of_peak"] = tf / peak
+    return out
 
 
 def profiled_traffic(name):
@@ -650,6 +711,8 @@ def main():
                     help="print a summary of rocprofv3 output in DIR (kernel trace) and exit")
     ap.add_argument("--fetch", metavar="DIR", help="with --summarize-profile: a FETCH_SIZE pass")
     ap.add_argument("--write", metavar="DIR", help="with --summarize-profile: a WRITE_SIZE pass")
+    ap.add_argument("--counters", metavar="DIR", action="append",
+                    help="with --summarize-profile: a further counter pass (repeatable)")
     ap.add_argument("--kernel", default="true, true>", help="with --summarize-profile: kernel name substring")
     ap.add_argument("--last", type=int, default=0,
                     help="with --summarize-profile: average over the last N launches (the timed region)")
@@ -779,6 +842,7 @@ def main():
             "traffic": profiled_traffic(f"dfr_kernel_krylov_{w.name}.txt"),
             "bytes_per_node": arnoldi_jv_bytes_per_node(M), "avg_launch_us": avg_jva_ms * 1e3,
             "launches": n_jva,
+            "utilisation": utilisation_summary(f"dfr_kernel_krylov_{w.name}.txt", avg_jva_ms * 1e3),
         },
         "roofline_plain_jv": {
             "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
@@ -814,10 +878,12 @@ def main():
             "nodes": N2, "tile_fp64": tile2, "tile_fp32": tile2_32,
             "fp64": {"us": t64 * 1e3, "jv_per_s": 1e3 / t64, "GBs": 72 * N2 / (t64 * 1e-3) / 1e9,
                      "frac_hbm": 72 * N2 / (t64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("dfr_kernel_jv_fp64_c2_ne60_p6_jet.txt")},
+                     "traffic": profiled_traffic("dfr_kernel_jv_fp64_c2_ne60_p6_jet.txt"),
+                     "utilisation": utilisation_summary("dfr_kernel_jv_fp64_c2_ne60_p6_jet.txt", t64 * 1e3)},
             "fp32_jv": {"us": t32 * 1e3, "jv_per_s": 1e3 / t32, "GBs": 60 * N2 / (t32 * 1e-3) / 1e9,
                         "frac_hbm": 60 * N2 / (t32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "traffic": profiled_traffic("dfr_kernel_jv_fp32_c2_ne60_p6_jet.txt"),
+                        "utilisation": utilisation_summary("dfr_kernel_jv_fp32_c2_ne60_p6_jet.txt", None),
                         "note": "timed per call including the FP32 copy of q (to_f32_kernel)"},
         }
         del v2, o2, q2, g2
