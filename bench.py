@@ -21,6 +21,7 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+PROFILES = os.path.join(ROOT, "profiles")   # committed rocprofv3 summaries
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -157,7 +158,7 @@ def summarize_profile(args):
 def profiled_utilisation(name):
     """Counter means (VALUBusy, LdsUtil, ...) recorded in profiles/<name> for
     the current kernel source, or None."""
-    path = os.path.join(ROOT, "profiles", name)
+    path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -179,7 +180,7 @@ def utilisation_summary(name, avg_us):
     if not u:
         return None
     if not avg_us:   # the profile's own timed average
-        for line in open(os.path.join(ROOT, "profiles", name)):
+        for line in open(os.path.join(PROFILES, name)):
             if line.startswith("timed_region_avg_us:"):
                 avg_us = float(line.split()[1])
     out = {k2: u.get(k1) for k1, k2 in (("VALUBusy", "valu_busy_pct"), ("LdsUtil", "lds_util_pct"),
@@ -199,7 +200,7 @@ def utilisation_summary(name, avg_us):
 def profiled_traffic(name):
     """HBM bytes per launch recorded in profiles/<name> for the current kernel
     source, or None (no record, or the kernels changed since)."""
-    path = os.path.join(ROOT, "profiles", name)
+    path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
     for line in open(path):
