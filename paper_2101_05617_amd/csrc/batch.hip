@@ -27,7 +27,8 @@ struct dfr_ensemble {
   Ops1D *d_ops = nullptr;            // and 1-D operators
   Stage stage;                       // call tables
   double *d_res = nullptr, *h_res = nullptr;   // per-call scalar results (norms)
-  KHost *d_kh = nullptr, *h_kh = nullptr;       // per-member exponential results
+  KHost *d_kh = nullptr, *h_kh = nullptr;       // per-member exponential results: mapped coherent host
+                                                //   memory (device address, host address), written by the kernel
   int **d_errp = nullptr;            // the members' error flags
   int *d_errv = nullptr, *h_errv = nullptr;
   std::vector<hipEvent_t> evfree;    // events for read-backs in flight
@@ -149,8 +150,9 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
   if (nres) DFR_HIP(hipMemcpyAsync(E.h_res, E.d_res, sizeof(double) * nres, hipMemcpyDeviceToHost, E.stream));
   if ((rc = sync_reset(E))) return rc;
   // scaling, W = nu [b_p..b_1], x = b_0; with at most four columns W is
-  // interleaved (one launch per member), as in the single-member form
+  // interleaved, as in the single-member form (one launch for all members)
   std::vector<AxpbyCall> wc;
+  std::vector<WilCall> wil;
   for (int a = 0; a < nk; ++a) {
     KiopsMachine &k = K[a];
     Ctx &c = *k.c;
@@ -167,9 +169,14 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
     }
     c.w_il = !c.ode_kind && k.p <= 4;
     if (c.w_il) {
-      const double *cols[4] = {nullptr, nullptr, nullptr, nullptr};
-      for (int i = 0; i < k.p; ++i) cols[i] = k.n_phi == 0 ? nullptr : k.b[k.p - i];
-      if ((rc = launch_w_interleave(&c, n3, k.p, k.nu, cols, c.d_W))) return rc;
+      WilCall wcall{};
+      wcall.nblk = vec_blocks(n3);
+      wcall.n = n3;
+      wcall.p = k.p;
+      wcall.nu = k.nu;
+      for (int i = 0; i < k.p; ++i) wcall.cols[i] = k.n_phi == 0 ? nullptr : k.b[k.p - i];
+      wcall.out = c.d_W;
+      wil.push_back(wcall);
     } else {
       for (int i = 0; i < k.p; ++i)
         wc.push_back(vcall(n3, k.nu, k.n_phi == 0 ? nullptr : k.b[k.p - i], 0.0, nullptr, c.d_W + i * n3));
@@ -178,6 +185,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
     c.kiops_mmax = k.m_max;
     wc.push_back(vcall(n3, 1.0, k.b[0], 0.0, nullptr, k.w));
   }
+  if ((rc = launch_wil_batch(E.stream, E.stage, wil))) return rc;
   if ((rc = launch_vec_batch(E.stream, E.stage, VB_AXPBY, wc))) return rc;
   const size_t lds = expm_lds_bytes(o.m_max);
 
@@ -355,24 +363,31 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
         ex_a.push_back(a);
       }
     }
+    // the round's call tables go to the device in one transfer, then its
+    // launches are issued in order
+    stage_defer(E.stage);
     if (!rc) rc = launch_start_batch(E.stream, E.stage, starts);
     if (!rc) rc = launch_first_batch(E.stream, E.stage, firsts);
     if (!rc) rc = launch_dfr_groups(E, jv64_m, jv64, true, false, true);
     if (!rc) rc = launch_dfr_groups(E, jv32_m, jv32, true, true, true);
     if (!rc) rc = launch_update_batch(E.stream, E.stage, ups);
+    if (!rc) rc = launch_expm_batch(E.stream, E.stage, ex, lds);
     if (rc) {
+      E.stage.defer = false;
+      E.stage.pending.clear();
+      drain();
+      return rc;
+    }
+    if ((rc = stage_flush(E.stage, E.stream))) {
       drain();
       return rc;
     }
     if (ex.empty()) continue;
     Pending f;
-    if (!rc) rc = launch_expm_batch(E.stream, E.stage, ex, lds);
-    if (!rc) rc = take_event(&f.ev);
-    if (rc) {
+    if ((rc = take_event(&f.ev))) {
       drain();
       return rc;
     }
-    DFR_HIP(hipMemcpyAsync(E.h_kh, E.d_kh, sizeof(KHost) * E.n, hipMemcpyDeviceToHost, E.stream));
     DFR_HIP(hipEventRecord(f.ev, E.stream));
     f.a = ex_a;
     for (int a : ex_a) waiting[a] = 1;
@@ -411,7 +426,6 @@ static void free_ensemble(dfr_ensemble *E) {
   (void)hipHostFree(E->stage.h);
   (void)hipFree(E->d_res);
   (void)hipHostFree(E->h_res);
-  (void)hipFree(E->d_kh);
   (void)hipHostFree(E->h_kh);
   (void)hipFree(E->d_errp);
   (void)hipFree(E->d_errv);
@@ -464,8 +478,8 @@ int dfr_ensemble_create(int n, const dfr_grid_desc *members, void *hip_stream, d
       hipHostMalloc((void **)&E->stage.h, STAGE_BYTES, hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&E->d_res, sizeof(double) * nres) != hipSuccess ||
       hipHostMalloc((void **)&E->h_res, sizeof(double) * nres, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&E->d_kh, sizeof(KHost) * n) != hipSuccess ||
-      hipHostMalloc((void **)&E->h_kh, sizeof(KHost) * n, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&E->h_kh, sizeof(KHost) * n, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&E->d_kh, E->h_kh, 0) != hipSuccess ||
       hipMalloc(&E->d_errp, sizeof(int *) * n) != hipSuccess || hipMalloc(&E->d_errv, sizeof(int) * n) != hipSuccess ||
       hipHostMalloc((void **)&E->h_errv, sizeof(int) * n, hipHostMallocDefault) != hipSuccess) {
     set_error("dfr_ensemble_create: allocation failed");

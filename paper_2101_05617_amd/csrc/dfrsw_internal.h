@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <utility>
 #include <vector>
@@ -145,6 +146,14 @@ struct CombineCall {
   const double *V;
   const struct KDev *kd;
   double *x;
+};
+struct WilCall {         // W = nu [cols] interleaved four per value (a member's b-columns)
+  int b0, nblk;
+  int64_t n;
+  int p;
+  double nu;
+  const double *cols[4];
+  double *out;
 };
 struct ExpmCall {        // one workgroup per member
   struct KDev *kd;
@@ -338,12 +347,28 @@ void epi_rotate(epi_state *st, double *q_new);
 // Staging of call tables for batched launches: a pinned host arena and its
 // device mirror; each table is copied on the stream before its launch.  The
 // arena is reset (reset_stage) only after the stream has been synchronised.
+// Staging arena for the call tables of batched launches (pinned host copy,
+// device copy).  In deferred mode the tables put since stage_defer() are
+// copied to the device by one transfer in stage_flush(), which then issues
+// the launches queued meanwhile, in their order.
 struct Stage {
   char *h = nullptr, *d = nullptr;
   size_t cap = 0, used = 0;
+  bool defer = false;
+  size_t pend0 = 0;                               // start of the range not yet copied
+  std::vector<std::function<int()>> pending;      // launches waiting for that copy
 };
 int stage_put(Stage &st, hipStream_t s, const void *src, size_t bytes, void **dev);
-inline void reset_stage(Stage &st) { st.used = 0; }
+int stage_launch(Stage &st, std::function<int()> launch);   // now, or queued in deferred mode
+inline void stage_defer(Stage &st) {
+  st.defer = true;
+  st.pend0 = st.used;
+}
+int stage_flush(Stage &st, hipStream_t s);     // copy, issue the queued launches, leave deferred mode
+inline void reset_stage(Stage &st) {
+  st.used = 0;
+  st.pend0 = 0;
+}
 
 // batched launches: every call of one launch has the same form (and, for the
 // DFR kernel, the same number of GL points ns)
@@ -356,6 +381,7 @@ int launch_combine_batch(hipStream_t s, Stage &st, std::vector<CombineCall> &cal
 int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, size_t lds);
 enum { VB_AXPBY = 0, VB_TO_F32 = 1, VB_NORM2 = 2, VB_SUM = 3, VB_CHECK = 4 };
 int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls);
+int launch_wil_batch(hipStream_t s, Stage &st, std::vector<WilCall> &calls);   // W of several members, one launch
 int vec_blocks(int64_t n);   // workgroups of a vector kernel on n values (at most 1024)
 
 int64_t dfr_grid_blocks(const Ctx *c, bool arnoldi);

@@ -1809,16 +1809,51 @@ int set_expm_lds_limit(int m) {
 int stage_put(Stage &st, hipStream_t s, const void *src, size_t bytes, void **dev) {
   const size_t off = (st.used + 255) & ~(size_t)255;
   if (off + bytes > st.cap) {
-    // the arena is full: wait for the copies in flight, then start over
+    if (bytes > st.cap) {
+      set_error("a batched call table exceeds the staging arena");
+      return DFR_E_INVAL;
+    }
+    // the arena is full: copy and issue what is deferred, wait for the
+    // copies in flight, then start over
+    if (st.defer) {
+      int rc = stage_flush(st, s);
+      if (rc) return rc;
+      st.defer = true;
+    }
     DFR_HIP(hipStreamSynchronize(s));
     st.used = 0;
+    st.pend0 = 0;
     return stage_put(st, s, src, bytes, dev);
   }
   std::memcpy(st.h + off, src, bytes);
-  DFR_HIP(hipMemcpyAsync(st.d + off, st.h + off, bytes, hipMemcpyHostToDevice, s));
+  if (!st.defer) DFR_HIP(hipMemcpyAsync(st.d + off, st.h + off, bytes, hipMemcpyHostToDevice, s));
   st.used = off + bytes;
   *dev = st.d + off;
   return DFR_OK;
+}
+
+int stage_launch(Stage &st, std::function<int()> launch) {
+  if (!st.defer) return launch();
+  st.pending.push_back(std::move(launch));
+  return DFR_OK;
+}
+
+int stage_flush(Stage &st, hipStream_t s) {
+  st.defer = false;
+  int rc = DFR_OK;
+  if (st.used > st.pend0) {
+    const hipError_t e = hipMemcpyAsync(st.d + st.pend0, st.h + st.pend0, st.used - st.pend0,
+                                        hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      set_error(std::string("HIP error: ") + hipGetErrorString(e));
+      rc = DFR_E_HIP;
+    }
+  }
+  st.pend0 = st.used;
+  for (auto &f : st.pending)
+    if (!rc) rc = f();
+  st.pending.clear();
+  return rc;
 }
 
 int vec_blocks(int64_t n) { return grid_reduce(n); }
@@ -1848,10 +1883,13 @@ static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &c
   int rc = stage_put(st, s, calls.data(), sizeof(DfrCall) * calls.size(), &d);
   if (rc) return rc;
   const int grid = ((nlog + 7) / 8) * 8;
-  hipLaunchKernelGGL((dfr_kernel_batch<NS, T, TQ, CS, AR>), dim3(grid), dim3(threads), lds, s, (const DfrCall *)d,
-                     (int)calls.size(), nlog);
-  DFR_HIP(hipGetLastError());
-  return DFR_OK;
+  const int n = (int)calls.size();
+  return stage_launch(st, [=]() -> int {
+    hipLaunchKernelGGL((dfr_kernel_batch<NS, T, TQ, CS, AR>), dim3(grid), dim3(threads), lds, s, (const DfrCall *)d,
+                       n, nlog);
+    DFR_HIP(hipGetLastError());
+    return DFR_OK;
+  });
 }
 
 template <int NS>
@@ -1887,9 +1925,12 @@ static int launch_calls(hipStream_t s, Stage &st, std::vector<C> &calls, K kerne
   void *d = nullptr;
   int rc = stage_put(st, s, calls.data(), sizeof(C) * calls.size(), &d);
   if (rc) return rc;
-  hipLaunchKernelGGL(kernel, dim3(nb), dim3(BLOCK), 0, s, (const C *)d, (int)calls.size());
-  DFR_HIP(hipGetLastError());
-  return DFR_OK;
+  const int n = (int)calls.size();
+  return stage_launch(st, [=]() -> int {
+    hipLaunchKernelGGL(kernel, dim3(nb), dim3(BLOCK), 0, s, (const C *)d, n);
+    DFR_HIP(hipGetLastError());
+    return DFR_OK;
+  });
 }
 
 int launch_first_batch(hipStream_t s, Stage &st, std::vector<FirstCall> &calls) {
@@ -1910,9 +1951,12 @@ int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, si
   void *d = nullptr;
   int rc = stage_put(st, s, calls.data(), sizeof(ExpmCall) * calls.size(), &d);
   if (rc) return rc;
-  hipLaunchKernelGGL(expm_batch, dim3((unsigned)calls.size()), dim3(EXPM_BLOCK), lds, s, (const ExpmCall *)d);
-  DFR_HIP(hipGetLastError());
-  return DFR_OK;
+  const unsigned n = (unsigned)calls.size();
+  return stage_launch(st, [=]() -> int {
+    hipLaunchKernelGGL(expm_batch, dim3(n), dim3(EXPM_BLOCK), lds, s, (const ExpmCall *)d);
+    DFR_HIP(hipGetLastError());
+    return DFR_OK;
+  });
 }
 
 int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls) {
@@ -1926,9 +1970,12 @@ int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> 
       void *d = nullptr;
       int rc = stage_put(st, s, calls.data(), sizeof(AxpbyCall) * calls.size(), &d);
       if (rc) return rc;
-      hipLaunchKernelGGL(sum_batch, dim3((unsigned)calls.size()), dim3(BLOCK), 0, s, (const AxpbyCall *)d);
-      DFR_HIP(hipGetLastError());
-      return DFR_OK;
+      const unsigned n = (unsigned)calls.size();
+      return stage_launch(st, [=]() -> int {
+        hipLaunchKernelGGL(sum_batch, dim3(n), dim3(BLOCK), 0, s, (const AxpbyCall *)d);
+        DFR_HIP(hipGetLastError());
+        return DFR_OK;
+      });
     }
     default: set_error("unknown batched vector kernel"); return DFR_E_INVAL;
   }
@@ -1981,10 +2028,9 @@ int launch_ode(Ctx *c, const double *q, const double *v, const double *vscale, b
   return DFR_OK;
 }
 
-__global__ __launch_bounds__(BLOCK) void w_interleave_kernel(int64_t n, int p, double nu, const double *c0,
-                                                             const double *c1, const double *c2, const double *c3,
-                                                             double *out) {
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+__device__ __forceinline__ void w_interleave_body(int blk, int nblk, int64_t n, int p, double nu, const double *c0,
+                                                  const double *c1, const double *c2, const double *c3, double *out) {
+  for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n; i += (int64_t)nblk * BLOCK) {
     double2 a, b;
     a.x = (p > 0 && c0) ? nu * c0[i] : 0.0;
     a.y = (p > 1 && c1) ? nu * c1[i] : 0.0;
@@ -1994,6 +2040,15 @@ __global__ __launch_bounds__(BLOCK) void w_interleave_kernel(int64_t n, int p, d
     o[0] = a;
     o[1] = b;
   }
+}
+__global__ __launch_bounds__(BLOCK) void w_interleave_kernel(int64_t n, int p, double nu, const double *c0,
+                                                             const double *c1, const double *c2, const double *c3,
+                                                             double *out) {
+  w_interleave_body(blockIdx.x, gridDim.x, n, p, nu, c0, c1, c2, c3, out);
+}
+__global__ __launch_bounds__(BLOCK) void w_interleave_batch(const WilCall *__restrict__ calls, int ncalls) {
+  const WilCall &c = calls[find_call(calls, ncalls)];
+  w_interleave_body(blockIdx.x - c.b0, c.nblk, c.n, c.p, c.nu, c.cols[0], c.cols[1], c.cols[2], c.cols[3], c.out);
 }
 
 int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out) {
@@ -2008,6 +2063,16 @@ int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
+
+int launch_wil_batch(hipStream_t s, Stage &st, std::vector<WilCall> &calls) {
+  for (auto &c : calls)
+    if (c.p > 4) {
+      set_error("interleaved W holds at most four columns");
+      return DFR_E_INVAL;
+    }
+  return launch_calls(s, st, calls, w_interleave_batch);
+}
+
 
 // ||x_i||_2^2 of several vectors: per-workgroup partial sums in
 // partials[i * gridDim.x + blk], then one workgroup adds each set in a
