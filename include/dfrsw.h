@@ -15,7 +15,9 @@
  *     named host_* and the descriptor's hB are HOST pointers.
  *   - Work is enqueued on the stream given to dfr_create.  dfr_rhs and
  *     dfr_jvp_complex_step are asynchronous; kiops_phi_apply and epi_step
- *     synchronise the stream (their adaptive control reads small scalars back).
+ *     return when all the work they issued on the stream has finished (their
+ *     adaptive control and their final error check wait for small results
+ *     that kernels write into mapped host memory).
  *   - Units: any consistent system.  The equations keep their form for
  *     radius = 1, omega = 1 and a rescaled gravity; the complex-FP32 form needs
  *     such a scaled state so that eps times the state stays far above the
@@ -192,7 +194,8 @@ int dfr_jvp_complex_step(dfr_ctx *ctx, const double *q, const double *v, double 
  * n_phi >= 0 (n_phi = 0 is the exponential).  Adaptive sub-stepping with
  * incomplete orthogonalisation (KIOPS); the controller is deterministic and
  * documented in the library source.  w: device, 3N doubles, may not alias
- * q_lin or any b[k].  stats may be NULL.  Synchronises the stream. */
+ * q_lin or any b[k].  stats may be NULL.  Returns when its work on the
+ * stream has finished. */
 int kiops_phi_apply(dfr_ctx *ctx, const double *q_lin, double tau_out, int n_phi,
                     const double *const *b, const kiops_opts *opts, double eps,
                     dfr_precision prec, double *w, kiops_stats *stats);
@@ -205,7 +208,7 @@ int epi_create(dfr_ctx *ctx, int order, double dt, int startup_substeps, const d
                double eps, dfr_precision prec, epi_state **out);
 /* Advance one step of size dt.  q_out (device, 3N doubles, may be NULL)
  * receives q_{n+1}.  stats (may be NULL) accumulates over the step's KIOPS
- * calls.  Synchronises the stream. */
+ * calls.  Returns when its work on the stream has finished. */
 int epi_step(dfr_ctx *ctx, epi_state *st, const kiops_opts *opts, double *q_out, kiops_stats *stats);
 /* Copy the current state q_n to a device buffer of 3N doubles. */
 int epi_get_state(const epi_state *st, double *q);
