@@ -228,6 +228,7 @@ def mixed_study(steps):
     res, finals = {}, {}
     for name, prec, eps, opts in (("fp64", "fp64", 1e-150, opts), ("fp32_jv", "fp32_jv", w.eps, opts),
                                   ("fp32_jv_tol1e-6", "fp32_jv", w.eps, opts_matched),
+                                  ("fp32_jv_basis32_tol1e-6", "fp32_jv_basis32", w.eps, opts_matched),
                                   ("fp64_tol1e-6", "fp64", 1e-150, opts_matched)):
         g = dfrsw.Grid(w.ne, w.p, *w.constants())
         dfrsw.dfr_autotune(g, prec)
@@ -264,6 +265,7 @@ def mixed_study(steps):
         return err_h, err_all
     err_h, err_all = errs("fp32_jv")
     em_h, em_all = errs("fp32_jv_tol1e-6")
+    eb_h, eb_all = errs("fp32_jv_basis32_tol1e-6")
     e64_h, e64_all = errs("fp64_tol1e-6")
     base = res["fp64"]["steps_per_s"]
     return {"workload": f"{w.name}: ne={w.ne}, p={w.p} ({N} nodes), EPI6, dt={w.dt_s:g}s, {steps} steps "
@@ -275,7 +277,10 @@ def mixed_study(steps):
                 "note": f"KIOPS tol {tol_matched:g} (one decade above the complex-FP32 product's relative "
                         f"noise); error and speed-up against plain FP64 at tol {w.tol:g}",
                 "fp32_jv": res["fp32_jv_tol1e-6"], "fp64": res["fp64_tol1e-6"],
+                "fp32_jv_basis32": res["fp32_jv_basis32_tol1e-6"],
                 "speedup_mixed_over_fp64": res["fp32_jv_tol1e-6"]["steps_per_s"] / base,
+                "speedup_mixed_basis32_over_fp64": res["fp32_jv_basis32_tol1e-6"]["steps_per_s"] / base,
+                "rel_l2_error_h_mixed_basis32": eb_h, "rel_l2_error_max_field_mixed_basis32": eb_all,
                 "speedup_fp64_over_fp64": res["fp64_tol1e-6"]["steps_per_s"] / base,
                 "rel_l2_error_h_mixed": em_h, "rel_l2_error_max_field_mixed": em_all,
                 "rel_l2_error_h_fp64": e64_h, "rel_l2_error_max_field_fp64": e64_all}}
