@@ -315,6 +315,7 @@ def ensemble_study(n_members, steps, n_workers):
                                    ("fp64_batched", "fp64", "batched", opts),
                                    ("fp32_jv_batched", "fp32_jv", "batched", opts),
                                    ("fp32_jv_batched_tol1e-6", "fp32_jv", "batched", opts_matched),
+                                   ("fp32_jv_basis32_batched_tol1e-6", "fp32_jv_basis32", "batched", opts_matched),
                                    ("fp64_batched_tol1e-6", "fp64", "batched", opts_matched)):
         ens = Ensemble(members, prec=prec, form=form)
         for _ in range(n_start):
@@ -347,6 +348,7 @@ def ensemble_study(n_members, steps, n_workers):
     e32, w32 = err("fp32_jv_batched")
     e64, w64 = err("fp64_batched")
     e32m, w32m = err("fp32_jv_batched_tol1e-6")
+    e32b, w32b = err("fp32_jv_basis32_batched_tol1e-6")
     e64m, w64m = err("fp64_batched_tol1e-6")
     base = res["fp64_sequential"]["member_steps_per_s"]
     return {"workload": f"{n_members} members, ne in {{8..40}}, p in {{4,5,6}} ({total_nodes} nodes in all), EPI4, "
@@ -364,6 +366,9 @@ def ensemble_study(n_members, steps, n_workers):
                     res["fp32_jv_batched_tol1e-6"]["member_steps_per_s"] / base,
                 "speedup_fp64_batched_over_fp64_sequential":
                     res["fp64_batched_tol1e-6"]["member_steps_per_s"] / base,
+                "speedup_fp32_basis32_batched_over_fp64_sequential":
+                    res["fp32_jv_basis32_batched_tol1e-6"]["member_steps_per_s"] / base,
+                "rel_l2_error_h_fp32_basis32_batched": {"all_members": e32b, "worst_member": w32b},
                 "rel_l2_error_h_fp32_batched": {"all_members": e32m, "worst_member": w32m},
                 "rel_l2_error_h_fp64_batched": {"all_members": e64m, "worst_member": w64m}},
             "simulated_days": (n_start + steps) * w0.dt_s / 86400.0}

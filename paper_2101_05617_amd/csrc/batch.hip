@@ -55,8 +55,8 @@ __global__ void gather_err_kernel(int *const *ptrs, int n, int *out) {
 
 static constexpr size_t STAGE_BYTES = 64u << 20;
 
-static DfrCall make_call(dfr_ensemble &E, int i, bool arnoldi, const void *q, const double *v, double eps,
-                         double *out, const ArnoldiArgs *ar) {
+static DfrCall make_call(dfr_ensemble &E, int i, bool arnoldi, const void *q, const void *v, double eps,
+                         void *out, const ArnoldiArgs *ar) {
   Ctx &c = E.mem[i]->c;
   DfrCall d{};
   d.g = E.d_ga + i;
@@ -76,7 +76,7 @@ static DfrCall make_call(dfr_ensemble &E, int i, bool arnoldi, const void *q, co
 // one launch per (number of GL points) group of the calls; the batched
 // kernels carry the Rusanov flux only
 static int launch_dfr_groups(dfr_ensemble &E, const std::vector<int> &member, std::vector<DfrCall> &calls, bool cs,
-                             bool fp32, bool arnoldi) {
+                             bool fp32, bool arnoldi, bool basis32 = false) {
   for (int m : member)
     if (E.mem[m]->c.ga.riemann != DFR_RUSANOV) {
       set_error("member " + std::to_string(m) + ": the batched ensemble form uses the Rusanov flux "
@@ -88,7 +88,7 @@ static int launch_dfr_groups(dfr_ensemble &E, const std::vector<int> &member, st
     for (size_t k = 0; k < calls.size(); ++k)
       if (E.mem[member[k]]->c.ns == ns) grp.push_back(calls[k]);
     if (grp.empty()) continue;
-    const int rc = launch_dfr_batch(E.stream, E.stage, ns, cs, fp32, arnoldi, grp);
+    const int rc = launch_dfr_batch(E.stream, E.stage, ns, cs, fp32, arnoldi, basis32, grp);
     if (rc) return rc;
   }
   return DFR_OK;
@@ -115,17 +115,22 @@ static int sync_reset(dfr_ensemble &E) {
 }
 
 // KIOPS for machines K (K[a] belongs to member mi[a]), all at once
+// basis32: the members keep their Krylov bases in FP32 (with FP32 products)
 static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std::vector<int> &mi,
-                       const kiops_opts &o) {
+                       const kiops_opts &o, bool basis32) {
   const int nk = (int)K.size();
   int rc = DFR_OK;
-  // interleaved W is a layout of this call only
-  struct WLayout {
+  // the basis precision and interleaved W are layouts of this call only
+  struct Layout {
     std::vector<KiopsMachine> &K;
-    ~WLayout() {
-      for (auto &k : K) k.c->w_il = false;
+    ~Layout() {
+      for (auto &k : K) {
+        k.c->w_il = false;
+        k.c->basis32 = false;
+      }
     }
   } layout{K};
+  for (auto &k : K) k.c->basis32 = basis32;
   // norms of every b_k: one launch of partial sums, one of finishing sums
   std::vector<AxpbyCall> nc, sc;
   std::vector<int> slot((size_t)nk * (MAX_P + 1), -1);
@@ -251,7 +256,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
       E.evfree.push_back(f.ev);
       pend.pop_front();
     }
-    return launch_combine_batch(E.stream, E.stage, cc);
+    return launch_combine_batch(E.stream, E.stage, basis32, cc);
   };
   auto drain = [&]() {
     for (auto &f : pend) {
@@ -312,7 +317,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
       if (k.phase == KiopsMachine::SWEEP) {
         ArnoldiArgs ar;
         km_arnoldi_args(k, o, ar);
-        double *out = c.d_V + (int64_t)(k.j + 1) * n3;
+        void *out = c.vslot(k.j + 1);
         if (k.j == 0 && k.t == 0.0 && k.b0_absent) {
           FirstCall f{};
           f.nblk = vec_blocks(n3);
@@ -324,7 +329,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
           k.skipped = true;
         } else {
           const void *qq = k.fp32 ? (const void *)k.q32 : (const void *)k.q;
-          DfrCall d = make_call(E, mi[a], true, qq, c.d_V + (int64_t)k.j * n3, k.eps, out, &ar);
+          DfrCall d = make_call(E, mi[a], true, qq, c.vslot(k.j), k.eps, out, &ar);
           if (k.fp32) {
             jv32.push_back(d);
             jv32_m.push_back(mi[a]);
@@ -340,8 +345,8 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
         u.j = k.j;
         u.p = k.p;
         u.w = out;
-        u.vj = c.d_V + (int64_t)k.j * n3;
-        u.vprev = static_cast<const double *>(ar.vprev);   // batched bases are FP64
+        u.vj = c.vslot(k.j);
+        u.vprev = ar.vprev;
         u.pin = c.d_partials;
         u.np_in = k.npA;
         u.pout = c.d_partials2;
@@ -366,11 +371,11 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
     // the round's call tables go to the device in one transfer, then its
     // launches are issued in order
     stage_defer(E.stage);
-    if (!rc) rc = launch_start_batch(E.stream, E.stage, starts);
-    if (!rc) rc = launch_first_batch(E.stream, E.stage, firsts);
+    if (!rc) rc = launch_start_batch(E.stream, E.stage, basis32, starts);
+    if (!rc) rc = launch_first_batch(E.stream, E.stage, basis32, firsts);
     if (!rc) rc = launch_dfr_groups(E, jv64_m, jv64, true, false, true);
-    if (!rc) rc = launch_dfr_groups(E, jv32_m, jv32, true, true, true);
-    if (!rc) rc = launch_update_batch(E.stream, E.stage, ups);
+    if (!rc) rc = launch_dfr_groups(E, jv32_m, jv32, true, true, true, basis32);
+    if (!rc) rc = launch_update_batch(E.stream, E.stage, basis32, ups);
     if (!rc) rc = launch_expm_batch(E.stream, E.stage, ex, lds);
     if (rc) {
       E.stage.defer = false;
@@ -512,11 +517,11 @@ dfr_ctx *dfr_ensemble_member(dfr_ensemble *E, int i) {
 }
 
 int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
-  if (!E || (prec != DFR_FP64 && prec != DFR_FP32_JV)) {
+  if (!E || (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
     set_error("dfr_ensemble_autotune: invalid argument");
     return DFR_E_INVAL;
   }
-  const bool fp32 = prec == DFR_FP32_JV;
+  const bool fp32 = prec != DFR_FP64, b32 = prec == DFR_FP32_JV_BASIS32;
   const int n = E->n;
   int rc = DFR_OK;
   // a smooth state and a direction in every member's Krylov workspace, and
@@ -528,6 +533,9 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
     const double *cols[4] = {c.d_V + n3, c.d_V + n3, c.d_V + n3, c.d_V + n3};
     if (!rc) rc = launch_w_interleave(&c, n3, 4, 1.0, cols, c.d_W);
     if (!rc && fp32) rc = launch_copy_to_f32(&c, n3, c.d_V, (float *)c.d_qf32);
+    // FP32 copies of the direction and of a previous vector (slots 3 and 4)
+    if (!rc && b32) rc = launch_copy_to_f32(&c, n3, c.d_V + n3, reinterpret_cast<float *>(c.d_V + 3 * n3));
+    if (!rc && b32) rc = launch_copy_to_f32(&c, n3, c.d_V, reinterpret_cast<float *>(c.d_V + 4 * n3));
     if (!rc) DFR_HIP(hipMemsetAsync(&c.d_kd->happy, 0, sizeof(int), E->stream));
   }
   if (rc) return rc;
@@ -564,14 +572,15 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
         ar.start = 1;
         for (int k = 0; k < ar.p; ++k) ar.W[k] = c.d_W;
         ar.wil = 1;
-        ar.vprev = c.d_V;
+        ar.vprev = b32 ? (const void *)(c.d_V + 4 * n3) : (const void *)c.d_V;
         ar.pin = c.d_V;
         ar.np_in = 1;
         ar.pout = c.d_partials;
         ar.kd = c.d_kd;
         ar.ybot[0] = 1.0;
         const void *q = fp32 ? (const void *)c.d_qf32 : (const void *)c.d_V;
-        calls.push_back(make_call(*E, i, true, q, c.d_V + n3, fp32 ? 1e-20 : 1e-150, c.d_V + 2 * n3, &ar));
+        const void *v = b32 ? (const void *)(c.d_V + 3 * n3) : (const void *)(c.d_V + n3);
+        calls.push_back(make_call(*E, i, true, q, v, fp32 ? 1e-20 : 1e-150, c.d_V + 2 * n3, &ar));
         mem.push_back(i);
       }
       // one untimed launch, then the fastest of three timed ones
@@ -579,7 +588,7 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
       for (int r = 0; r < 4 && !rc; ++r) {
         if (r > 0) (void)hipEventRecord(e0, E->stream);
         std::vector<DfrCall> cc = calls;
-        rc = launch_dfr_groups(*E, mem, cc, true, fp32, true);
+        rc = launch_dfr_groups(*E, mem, cc, true, fp32, true, b32);
         if (rc || r == 0) continue;
         (void)hipEventRecord(e1, E->stream);
         (void)hipEventSynchronize(e1);
@@ -610,10 +619,6 @@ int epi_ensemble_create(dfr_ensemble *E, int order, double dt, int startup_subst
                         double eps, dfr_precision prec, epi_ensemble **out) {
   if (!E || !q0 || !out) {
     set_error("epi_ensemble_create: invalid argument");
-    return DFR_E_INVAL;
-  }
-  if (prec == DFR_FP32_JV_BASIS32) {
-    set_error("epi_ensemble_create: the batched form keeps its Krylov bases in FP64 (DFR_FP64 or DFR_FP32_JV)");
     return DFR_E_INVAL;
   }
   *out = nullptr;
@@ -668,7 +673,7 @@ int epi_ensemble_step(dfr_ensemble *E, epi_ensemble *X, const kiops_opts *o, kio
     if (rc) return rc;
   }
   if (stats) std::memset(stats, 0, sizeof(kiops_stats) * n);
-  const bool fp32 = s0->prec == DFR_FP32_JV;
+  const bool fp32 = s0->prec != DFR_FP64, basis32 = s0->prec == DFR_FP32_JV_BASIS32;
   std::vector<int> all(n);
   for (int i = 0; i < n; ++i) all[i] = i;
   int rc = sync_reset(*E);
@@ -709,7 +714,7 @@ int epi_ensemble_step(dfr_ensemble *E, epi_ensemble *X, const kiops_opts *o, kio
       k.eps = st(i)->eps;
       k.fp32 = fp32;
     }
-    int r = kiops_batch(*E, K, all, *o);
+    int r = kiops_batch(*E, K, all, *o, basis32);
     if (stats)
       for (int i = 0; i < n; ++i) add_stats(&stats[i], K[i].st);
     return r;

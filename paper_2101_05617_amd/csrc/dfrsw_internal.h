@@ -112,24 +112,27 @@ struct DfrCall {
   int TX, TY;             // its tile
   int b0, ntiles;
   const void *q;          // state (double, or float in the FP32 form)
-  const double *v;
+  const void *v;          // direction (double, or float for an FP32 basis)
   const double *vscale;
   double eps;
-  double *out;
+  void *out;              // result (the type of v)
   ArnoldiArgs ar;
 };
+// basis vectors (out, w, vj, vprev, v0, V) are double, or float for an FP32
+// basis (the same for every call of a launch)
 struct FirstCall {
   int b0, nblk;
   int64_t n3;
   ArnoldiArgs ar;
-  double *out;
+  void *out;
 };
 struct UpdateCall {
   int b0, nblk;
   int64_t n3;
   int j, p;
-  double *w;
-  const double *vj, *vprev, *pin;
+  void *w;
+  const void *vj, *vprev;
+  const double *pin;
   int np_in;
   double *pout;
   struct KDev *kd;
@@ -138,12 +141,13 @@ struct StartCall {
   int b0, nblk;
   int64_t n3;
   const double *x;
-  double *v0, *pout;
+  void *v0;
+  double *pout;
 };
 struct CombineCall {
   int b0, nblk;
   int64_t n3;
-  const double *V;
+  const void *V;
   const struct KDev *kd;
   double *x;
 };
@@ -372,12 +376,12 @@ inline void reset_stage(Stage &st) {
 
 // batched launches: every call of one launch has the same form (and, for the
 // DFR kernel, the same number of GL points ns)
-int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool fp32, bool arnoldi,
+int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool fp32, bool arnoldi, bool basis32,
                      std::vector<DfrCall> &calls);
-int launch_first_batch(hipStream_t s, Stage &st, std::vector<FirstCall> &calls);
-int launch_update_batch(hipStream_t s, Stage &st, std::vector<UpdateCall> &calls);
-int launch_start_batch(hipStream_t s, Stage &st, std::vector<StartCall> &calls);
-int launch_combine_batch(hipStream_t s, Stage &st, std::vector<CombineCall> &calls);
+int launch_first_batch(hipStream_t s, Stage &st, bool basis32, std::vector<FirstCall> &calls);
+int launch_update_batch(hipStream_t s, Stage &st, bool basis32, std::vector<UpdateCall> &calls);
+int launch_start_batch(hipStream_t s, Stage &st, bool basis32, std::vector<StartCall> &calls);
+int launch_combine_batch(hipStream_t s, Stage &st, bool basis32, std::vector<CombineCall> &calls);
 int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, size_t lds);
 enum { VB_AXPBY = 0, VB_TO_F32 = 1, VB_NORM2 = 2, VB_SUM = 3, VB_CHECK = 4 };
 int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls);

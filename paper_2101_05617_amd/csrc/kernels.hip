@@ -800,8 +800,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 }
 
 // several grids (ensemble members) in one launch: member m owns the logical
-// blocks [b0, b0 + ntiles); Rusanov fluxes
-template <int NS, typename T, typename TQ, bool CS, bool AR>
+// blocks [b0, b0 + ntiles); Rusanov fluxes; TV: the basis type
+template <int NS, typename T, typename TQ, bool CS, bool AR, typename TV>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCall *__restrict__ calls, int ncalls,
                                                                      int nlogical) {
   __shared__ int s_m;
@@ -813,8 +813,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCal
   }
   __syncthreads();
   const DfrCall &c = calls[s_m];
-  dfr_body<NS, T, TQ, CS, AR, 0, double>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q),
-                                         c.v, c.vscale, c.eps, c.out, c.ar);
+  dfr_body<NS, T, TQ, CS, AR, 0, TV>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q),
+                                     static_cast<const TV *>(c.v), c.vscale, c.eps, static_cast<TV *>(c.out), c.ar);
 }
 
 // ---------------------------------------------------------------------------
@@ -862,9 +862,10 @@ template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, TV *out) {
   arnoldi_first_body(blockIdx.x, gridDim.x, n3, ar, out);
 }
+template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__restrict__ calls, int ncalls) {
   const FirstCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_first_body(blockIdx.x - c.b0, c.nblk, c.n3, c.ar, c.out);
+  arnoldi_first_body(blockIdx.x - c.b0, c.nblk, c.n3, c.ar, static_cast<TV *>(c.out));
 }
 
 // Gram-Schmidt step.  Prologue: the inner products h_{j,j}, h_{j-1,j} (top
@@ -999,9 +1000,11 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j
                                                                double *pout, KDev *kd) {
   arnoldi_update_body(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
 }
+template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls) {
   const UpdateCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_update_body(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, c.w, c.vj, c.vprev, c.pin, c.np_in, c.pout, c.kd);
+  arnoldi_update_body(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, static_cast<TV *>(c.w), static_cast<const TV *>(c.vj),
+                      static_cast<const TV *>(c.vprev), c.pin, c.np_in, c.pout, c.kd);
 }
 
 // start of a sub-step: v~_0 = x (copied), partial ||x||^2 per workgroup
@@ -1022,9 +1025,10 @@ template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, TV *v0, double *pout) {
   arnoldi_start_body(blockIdx.x, gridDim.x, n3, x, v0, pout);
 }
+template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_start_batch(const StartCall *__restrict__ calls, int ncalls) {
   const StartCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_start_body(blockIdx.x - c.b0, c.nblk, c.n3, c.x, c.v0, c.pout);
+  arnoldi_start_body(blockIdx.x - c.b0, c.nblk, c.n3, c.x, static_cast<TV *>(c.v0), c.pout);
 }
 
 // accepted sub-step: x = beta * sum_{k<J} sigma_k v~_k E[k][0]; the
@@ -1048,9 +1052,10 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_combine_kernel(int64_t n3, cons
                                                                 double *x) {
   arnoldi_combine_body(blockIdx.x, gridDim.x, n3, V, ldv, kd, x);
 }
+template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_combine_batch(const CombineCall *__restrict__ calls, int ncalls) {
   const CombineCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_combine_body(blockIdx.x - c.b0, c.nblk, c.n3, c.V, c.n3, c.kd, c.x);
+  arnoldi_combine_body(blockIdx.x - c.b0, c.nblk, c.n3, static_cast<const TV *>(c.V), c.n3, c.kd, c.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1641,11 +1646,12 @@ static int set_lds_attr(size_t bytes) {
                        (const void *)dfr_kernel<NS, double, double, true, true, 1, double>,
                        (const void *)dfr_kernel<NS, float, float, true, true, 1, double>,
                        (const void *)dfr_kernel<NS, float, float, true, true, 1, float>,
-                       (const void *)dfr_kernel_batch<NS, double, double, false, false>,
-                       (const void *)dfr_kernel_batch<NS, double, double, true, false>,
-                       (const void *)dfr_kernel_batch<NS, float, float, true, false>,
-                       (const void *)dfr_kernel_batch<NS, double, double, true, true>,
-                       (const void *)dfr_kernel_batch<NS, float, float, true, true>};
+                       (const void *)dfr_kernel_batch<NS, double, double, false, false, double>,
+                       (const void *)dfr_kernel_batch<NS, double, double, true, false, double>,
+                       (const void *)dfr_kernel_batch<NS, float, float, true, false, double>,
+                       (const void *)dfr_kernel_batch<NS, double, double, true, true, double>,
+                       (const void *)dfr_kernel_batch<NS, float, float, true, true, double>,
+                       (const void *)dfr_kernel_batch<NS, float, float, true, true, float>};
   for (const void *f : fns) DFR_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return DFR_OK;
 }
@@ -1868,7 +1874,7 @@ static int set_b0(std::vector<C> &calls) {
   return b;
 }
 
-template <int NS, typename T, typename TQ, bool CS, bool AR>
+template <int NS, typename T, typename TQ, bool CS, bool AR, typename TV>
 static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &calls) {
   int nlog = 0, threads = 256;
   size_t lds = 0;
@@ -1885,7 +1891,7 @@ static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &c
   const int grid = ((nlog + 7) / 8) * 8;
   const int n = (int)calls.size();
   return stage_launch(st, [=]() -> int {
-    hipLaunchKernelGGL((dfr_kernel_batch<NS, T, TQ, CS, AR>), dim3(grid), dim3(threads), lds, s, (const DfrCall *)d,
+    hipLaunchKernelGGL((dfr_kernel_batch<NS, T, TQ, CS, AR, TV>), dim3(grid), dim3(threads), lds, s, (const DfrCall *)d,
                        n, nlog);
     DFR_HIP(hipGetLastError());
     return DFR_OK;
@@ -1893,27 +1899,33 @@ static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &c
 }
 
 template <int NS>
-static int launch_dfr_batch_form(hipStream_t s, Stage &st, bool cs, bool fp32, bool ar, std::vector<DfrCall> &calls) {
-  if (!cs) return launch_dfr_batch_ns<NS, double, double, false, false>(s, st, calls);
+static int launch_dfr_batch_form(hipStream_t s, Stage &st, bool cs, bool fp32, bool ar, bool b32,
+                                 std::vector<DfrCall> &calls) {
+  if (!cs) return launch_dfr_batch_ns<NS, double, double, false, false, double>(s, st, calls);
   if (fp32) {
-    return ar ? launch_dfr_batch_ns<NS, float, float, true, true>(s, st, calls)
-              : launch_dfr_batch_ns<NS, float, float, true, false>(s, st, calls);
+    if (ar && b32) return launch_dfr_batch_ns<NS, float, float, true, true, float>(s, st, calls);
+    return ar ? launch_dfr_batch_ns<NS, float, float, true, true, double>(s, st, calls)
+              : launch_dfr_batch_ns<NS, float, float, true, false, double>(s, st, calls);
   }
-  return ar ? launch_dfr_batch_ns<NS, double, double, true, true>(s, st, calls)
-            : launch_dfr_batch_ns<NS, double, double, true, false>(s, st, calls);
+  return ar ? launch_dfr_batch_ns<NS, double, double, true, true, double>(s, st, calls)
+            : launch_dfr_batch_ns<NS, double, double, true, false, double>(s, st, calls);
 }
 
-int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool fp32, bool arnoldi,
+int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool fp32, bool arnoldi, bool basis32,
                      std::vector<DfrCall> &calls) {
   if (calls.empty()) return DFR_OK;
+  if (basis32 && !(complex_step && fp32 && arnoldi)) {
+    set_error("an FP32 basis goes with the complex-FP32 Krylov-form product only");
+    return DFR_E_INVAL;
+  }
   switch (ns) {
-    case 2: return launch_dfr_batch_form<2>(s, st, complex_step, fp32, arnoldi, calls);
-    case 3: return launch_dfr_batch_form<3>(s, st, complex_step, fp32, arnoldi, calls);
-    case 4: return launch_dfr_batch_form<4>(s, st, complex_step, fp32, arnoldi, calls);
-    case 5: return launch_dfr_batch_form<5>(s, st, complex_step, fp32, arnoldi, calls);
-    case 6: return launch_dfr_batch_form<6>(s, st, complex_step, fp32, arnoldi, calls);
-    case 7: return launch_dfr_batch_form<7>(s, st, complex_step, fp32, arnoldi, calls);
-    case 8: return launch_dfr_batch_form<8>(s, st, complex_step, fp32, arnoldi, calls);
+    case 2: return launch_dfr_batch_form<2>(s, st, complex_step, fp32, arnoldi, basis32, calls);
+    case 3: return launch_dfr_batch_form<3>(s, st, complex_step, fp32, arnoldi, basis32, calls);
+    case 4: return launch_dfr_batch_form<4>(s, st, complex_step, fp32, arnoldi, basis32, calls);
+    case 5: return launch_dfr_batch_form<5>(s, st, complex_step, fp32, arnoldi, basis32, calls);
+    case 6: return launch_dfr_batch_form<6>(s, st, complex_step, fp32, arnoldi, basis32, calls);
+    case 7: return launch_dfr_batch_form<7>(s, st, complex_step, fp32, arnoldi, basis32, calls);
+    case 8: return launch_dfr_batch_form<8>(s, st, complex_step, fp32, arnoldi, basis32, calls);
     default: set_error("unsupported number of GL points"); return DFR_E_INVAL;
   }
 }
@@ -1933,17 +1945,21 @@ static int launch_calls(hipStream_t s, Stage &st, std::vector<C> &calls, K kerne
   });
 }
 
-int launch_first_batch(hipStream_t s, Stage &st, std::vector<FirstCall> &calls) {
-  return launch_calls(s, st, calls, arnoldi_first_batch);
+int launch_first_batch(hipStream_t s, Stage &st, bool basis32, std::vector<FirstCall> &calls) {
+  return basis32 ? launch_calls(s, st, calls, arnoldi_first_batch<float>)
+                 : launch_calls(s, st, calls, arnoldi_first_batch<double>);
 }
-int launch_update_batch(hipStream_t s, Stage &st, std::vector<UpdateCall> &calls) {
-  return launch_calls(s, st, calls, arnoldi_update_batch);
+int launch_update_batch(hipStream_t s, Stage &st, bool basis32, std::vector<UpdateCall> &calls) {
+  return basis32 ? launch_calls(s, st, calls, arnoldi_update_batch<float>)
+                 : launch_calls(s, st, calls, arnoldi_update_batch<double>);
 }
-int launch_start_batch(hipStream_t s, Stage &st, std::vector<StartCall> &calls) {
-  return launch_calls(s, st, calls, arnoldi_start_batch);
+int launch_start_batch(hipStream_t s, Stage &st, bool basis32, std::vector<StartCall> &calls) {
+  return basis32 ? launch_calls(s, st, calls, arnoldi_start_batch<float>)
+                 : launch_calls(s, st, calls, arnoldi_start_batch<double>);
 }
-int launch_combine_batch(hipStream_t s, Stage &st, std::vector<CombineCall> &calls) {
-  return launch_calls(s, st, calls, arnoldi_combine_batch);
+int launch_combine_batch(hipStream_t s, Stage &st, bool basis32, std::vector<CombineCall> &calls) {
+  return basis32 ? launch_calls(s, st, calls, arnoldi_combine_batch<float>)
+                 : launch_calls(s, st, calls, arnoldi_combine_batch<double>);
 }
 
 int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, size_t lds) {

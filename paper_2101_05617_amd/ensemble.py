@@ -20,7 +20,7 @@ from . import dfrsw, inputs
 
 class Ensemble:
     """Members built from `inputs.Workload`s (same order, dt and start-up for
-    the batched form); `prec` is "fp64" or "fp32_jv".  autotune: pick each
+    the batched form); `prec` is "fp64", "fp32_jv" or "fp32_jv_basis32".  autotune: pick each
     member's tiles by timing (dfr_autotune).  frames: optional per-member
     (P, B1, B2) node frames for the initial states (default: the library's)."""
 
@@ -52,7 +52,7 @@ class Ensemble:
                 raise ValueError("ensemble members without orography only")
             q0s.append(torch.from_numpy(Q).cuda())
         torch.cuda.synchronize()
-        self.eps = [w.eps if prec == "fp32_jv" else 1e-150 for w in self.workloads]
+        self.eps = [w.eps if prec != "fp64" else 1e-150 for w in self.workloads]
         if form == "batched":
             w0 = self.workloads[0]
             self.x = dfrsw.epi_ensemble_create(self.eg, w0.order, w0.dt_nd, q0s, startup_substeps=w0.startup_substeps,

@@ -76,21 +76,35 @@ def test_basis32_product_alone_equals_fp32_form():
     assert np.array_equal(a, b)
 
 
-def test_batched_ensemble_rejects_fp32_basis():
+def test_batched_ensemble_fp32_basis_matches_members_run_alone():
+    # the batched form with FP32 products and FP32 bases against the same
+    # precision member by member (same tiles, same decisions), and against
+    # plain FP64 member by member
+    import torch
+    from dataclasses import replace
+    from paper_2101_05617_amd.ensemble import Ensemble
+    ws = [small(C2, 2, 4), small(C2, 3, 5), small(C2, 2, 6)]
+    ws = [replace(w, order=4, dt_s=900.0, m_max=32) for w in ws]
     from paper_2101_05617_amd import dfrsw
-    torch = torch_dev()
-    ms = inputs.ensemble_members(2)
-    eg = dfrsw.EnsembleGrid([dict(ne=2, p=m.p, radius=c[0], omega=c[1], gravity=c[2])
-                             for m in ms for c in [m.constants()]])
+    opts = dfrsw.kiops_opts(tol=1e-10, m_max=32)
+    ref64 = Ensemble(ws, prec="fp64", form="sequential", autotune=False)
+    seq = Ensemble(ws, prec="fp32_jv_basis32", form="sequential", autotune=False)
+    bat = Ensemble(ws, prec="fp32_jv_basis32", form="batched", autotune=False)
     try:
-        q0 = []
-        for mb in eg.members:
-            q = torch.zeros(3 * mb.N, dtype=torch.float64, device="cuda")
-            q[: mb.N] = 1.0
-            q0.append(q)
-        with pytest.raises(dfrsw.DfrError) as e:
-            dfrsw.epi_ensemble_create(eg, 4, ms[0].dt_nd, q0, startup_substeps=2, eps=1e-20, prec="fp32_jv_basis32")
-        assert e.value.code == -1
+        for _ in range(5):
+            ref64.step(opts)
+            ss = seq.step(opts)
+            sb = bat.step(opts)
+            assert [x["n_matvec"] for x in sb] == [x["n_matvec"] for x in ss]
+        for k in range(len(ws)):
+            a, b, c = seq.state(k), bat.state(k), ref64.state(k)
+            N = len(a) // 3
+            e_seq = np.linalg.norm(b[:N] - a[:N]) / np.linalg.norm(a[:N])
+            e_64 = np.linalg.norm(b[:N] - c[:N]) / np.linalg.norm(c[:N])
+            record(f"ensemble_basis32_member{k}_vs_alone_h", e_seq)
+            record(f"ensemble_basis32_member{k}_vs_fp64_h", e_64)
+            assert e_seq < 1e-9 and e_64 < 1e-6, (k, e_seq, e_64)
     finally:
+        for z in (ref64, seq, bat):
+            z.close()
         torch.cuda.synchronize()
-        eg.close()
