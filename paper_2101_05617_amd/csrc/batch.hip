@@ -54,6 +54,13 @@ __global__ void gather_err_kernel(int *const *ptrs, int n, int *out) {
 }
 
 static constexpr size_t STAGE_BYTES = 64u << 20;
+// workgroups of a member's Gram-Schmidt update in the batched form: each one
+// finishes the member's partial inner products itself, so fewer, fuller
+// workgroups spend less on that (the batched update is bandwidth-bound)
+#ifndef DFR_UPDATE_BLOCKS_BATCHED
+#define DFR_UPDATE_BLOCKS_BATCHED 256
+#endif
+static constexpr int UPDATE_BLOCKS_BATCHED = DFR_UPDATE_BLOCKS_BATCHED;
 
 static DfrCall make_call(dfr_ensemble &E, int i, bool arnoldi, const void *q, const void *v, double eps,
                          void *out, const ArnoldiArgs *ar) {
@@ -340,7 +347,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
           k.npA = (int)dfr_num_tiles(&c, true);
         }
         UpdateCall u{};
-        u.nblk = vec_blocks(n3);
+        u.nblk = std::min(vec_blocks(n3), UPDATE_BLOCKS_BATCHED);
         u.n3 = n3;
         u.j = k.j;
         u.p = k.p;
