@@ -239,7 +239,8 @@ int epi_load(dfr_ctx *ctx, const void *host_buf, size_t nbytes, epi_state **out)
  * keeps its own KIOPS controller, and members take Arnoldi steps in lockstep
  * rounds with one read-back per round in which some member's sweep reaches
  * its exponential.  Member results equal those of epi_step on the member
- * alone up to rounding (same kernels and reduction orders).  All members of
+ * alone with the same tiles, bit for bit (same kernels, reduction orders and
+ * EPI combinations).  All members of
  * an epi_ensemble must share order, dt, start-up sub-steps and precision
  * (DFR_E_INVAL otherwise).  q0: host array of n device pointers (3 N_i
  * doubles each, copied).  stats: NULL or n entries.  dfr_ensemble_member

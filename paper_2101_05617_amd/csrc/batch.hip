@@ -765,29 +765,42 @@ int epi_ensemble_step(dfr_ensemble *E, epi_ensemble *X, const kiops_opts *o, kio
       for (int i = 0; i < n; ++i)
         c.push_back(make_call(*E, i, false, (const void *)st(i)->q, st(i)->d, eps, st(i)->jd, nullptr));
       if ((rc = launch_dfr_groups(*E, all, c, true, false, false))) return rc;
-      if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->hF[r], -1.0, st(i)->F, st(i)->R[r]); }))) return rc;
-      if ((rc = vec([&](int i) { return vcall(n3(i), 1.0, st(i)->R[r], -1.0, st(i)->jd, st(i)->R[r]); }))) return rc;
-    }
-    // b_1 = F_n, b_m = sum_i alpha_{m,i} R_i / dt^{m-1}
-    for (int m = 2; m <= s0->M; ++m) {
-      bool first = true;
-      for (int r = 1; r <= s0->P; ++r) {
-        const double a = s0->A[m - 1][r - 1];
-        if (a == 0.0) continue;
-        rc = vec([&](int i) {
-          double *bm = st(i)->bm[m - 1];
-          return first ? vcall(n3(i), a, st(i)->R[r - 1], 0.0, nullptr, bm)
-                       : vcall(n3(i), 1.0, bm, a, st(i)->R[r - 1], bm);
-        });
-        if (rc) return rc;
-        first = false;
+      // R_r = hF_r - F_n - jd in one pass (the combination epi_step makes)
+      std::vector<LinCombCall> lc(n);
+      for (int i = 0; i < n; ++i) {
+        LinCombCall &l = lc[i];
+        l.nblk = vec_blocks(n3(i));
+        l.n = n3(i);
+        l.lc.nin = 3;
+        l.lc.nout = 1;
+        l.lc.in[0] = st(i)->hF[r];
+        l.lc.in[1] = st(i)->F;
+        l.lc.in[2] = st(i)->jd;
+        l.lc.out[0] = st(i)->R[r];
+        l.lc.a[0][0] = 1.0;
+        l.lc.a[0][1] = -1.0;
+        l.lc.a[0][2] = -1.0;
       }
-      const double sc = 1.0 / std::pow(s0->dt, (double)(m - 1));
-      rc = vec([&](int i) {
-        double *bm = st(i)->bm[m - 1];
-        return first ? vcall(n3(i), 0.0, nullptr, 0.0, nullptr, bm) : vcall(n3(i), sc, bm, 0.0, nullptr, bm);
-      });
-      if (rc) return rc;
+      if ((rc = launch_lincomb_batch(S, ST, lc))) return rc;
+    }
+    // b_1 = F_n, b_m = sum_i alpha_{m,i} R_i / dt^{m-1}: one pass over the
+    // remainders for every b_m (the combination epi_step makes)
+    if (s0->M >= 2) {
+      std::vector<LinCombCall> lc(n);
+      for (int i = 0; i < n; ++i) {
+        LinCombCall &l = lc[i];
+        l.nblk = vec_blocks(n3(i));
+        l.n = n3(i);
+        l.lc.nin = s0->P;
+        l.lc.nout = s0->M - 1;
+        for (int r = 0; r < s0->P; ++r) l.lc.in[r] = st(i)->R[r];
+        for (int m = 2; m <= s0->M; ++m) {
+          const double sc = 1.0 / std::pow(s0->dt, (double)(m - 1));
+          l.lc.out[m - 2] = st(i)->bm[m - 1];
+          for (int r = 0; r < s0->P; ++r) l.lc.a[m - 2][r] = s0->A[m - 1][r] * sc;
+        }
+      }
+      if ((rc = launch_lincomb_batch(S, ST, lc))) return rc;
     }
     rc = kiops([&](int i) { return (const double *)st(i)->q; }, s0->dt, s0->M, [&](int i, int j) {
       return j == 0 ? (const double *)nullptr : (j == 1 ? (const double *)st(i)->F : (const double *)st(i)->bm[j - 1]);

@@ -405,6 +405,12 @@ struct LinComb {
   double a[4][4];
 };
 int launch_lincomb(Ctx *c, int64_t n, const LinComb &lc);
+struct LinCombCall {     // one member's linear combination in a batched launch
+  int b0, nblk;
+  int64_t n;
+  LinComb lc;
+};
+int launch_lincomb_batch(hipStream_t s, Stage &st, std::vector<LinCombCall> &calls);
 int launch_sum(Ctx *c, int np, const double *partials, double *out);
 
 }  // namespace dfrsw

@@ -2154,8 +2154,8 @@ int launch_norms2(Ctx *c, int64_t n, int k, const double *const *x, double *part
   return DFR_OK;
 }
 
-__global__ __launch_bounds__(BLOCK) void lincomb_kernel(int64_t n, const LinComb lc) {
-  for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
+__device__ __forceinline__ void lincomb_body(int blk, int nblk, int64_t n, const LinComb &lc) {
+  for (int64_t j = (int64_t)blk * BLOCK + threadIdx.x; j < n; j += (int64_t)nblk * BLOCK) {
     double x[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) x[i] = i < lc.nin ? lc.in[i][j] : 0.0;
@@ -2170,6 +2170,13 @@ __global__ __launch_bounds__(BLOCK) void lincomb_kernel(int64_t n, const LinComb
     }
   }
 }
+__global__ __launch_bounds__(BLOCK) void lincomb_kernel(int64_t n, const LinComb lc) {
+  lincomb_body(blockIdx.x, gridDim.x, n, lc);
+}
+__global__ __launch_bounds__(BLOCK) void lincomb_batch(const LinCombCall *__restrict__ calls, int ncalls) {
+  const LinCombCall &c = calls[find_call(calls, ncalls)];
+  lincomb_body(blockIdx.x - c.b0, c.nblk, c.n, c.lc);
+}
 
 int launch_lincomb(Ctx *c, int64_t n, const LinComb &lc) {
   if (lc.nin < 1 || lc.nin > 4 || lc.nout < 1 || lc.nout > 4) {
@@ -2179,6 +2186,15 @@ int launch_lincomb(Ctx *c, int64_t n, const LinComb &lc) {
   dfr_launch(c, DFR_K_OTHER, lincomb_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, n, lc);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
+}
+
+int launch_lincomb_batch(hipStream_t s, Stage &st, std::vector<LinCombCall> &calls) {
+  for (auto &c : calls)
+    if (c.lc.nin < 1 || c.lc.nin > 4 || c.lc.nout < 1 || c.lc.nout > 4) {
+      set_error("launch_lincomb_batch: one to four inputs and outputs");
+      return DFR_E_INVAL;
+    }
+  return launch_calls(s, st, calls, lincomb_batch);
 }
 
 }  // namespace dfrsw

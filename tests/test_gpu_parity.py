@@ -412,7 +412,8 @@ def test_ensemble_forms_match_members_run_alone():
         assert np.array_equal(a, c), (k, np.abs(a - c).max())
         eb = rel_fields(b, a, len(a) // 3)
         record(f"ensemble_batched_vs_single_member{k}", eb)
-        assert eb <= 1e-14, (k, eb)
+        # same kernels, tiles, reduction orders and EPI combinations
+        assert np.array_equal(a, b), (k, eb)
         G = oracle.OracleGrid(w.ne, w.ns, *w.constants())
         Q, _ = inputs.initial_state(w, *frames[k])
         E = oepi.EPI(G.rhs, lambda q, v: G.jvp(q, v), w.order, w.dt_nd, Q, startup_substeps=w.startup_substeps,
