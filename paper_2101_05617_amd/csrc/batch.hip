@@ -6,7 +6,8 @@
 // controller (the state machine of kiops.hip); members take Arnoldi steps in
 // lockstep rounds, and a round ends with one read-back for all members whose
 // sweep reached its exponential.  Results are those of the single-grid path
-// member by member (same kernels, same reduction orders).
+// member by member, bit for bit with the same tiles (same kernels, reduction
+// orders and EPI combinations).
 #include "dfrsw_internal.h"
 
 #include <algorithm>

@@ -348,13 +348,12 @@ struct epi_state;
 namespace dfrsw {
 void epi_rotate(epi_state *st, double *q_new);
 
-// Staging of call tables for batched launches: a pinned host arena and its
-// device mirror; each table is copied on the stream before its launch.  The
-// arena is reset (reset_stage) only after the stream has been synchronised.
-// Staging arena for the call tables of batched launches (pinned host copy,
-// device copy).  In deferred mode the tables put since stage_defer() are
-// copied to the device by one transfer in stage_flush(), which then issues
-// the launches queued meanwhile, in their order.
+// Staging arena for the call tables of batched launches: a pinned host arena
+// and its device mirror.  Each table is copied on the stream before its
+// launch; in deferred mode the tables put since stage_defer() go to the
+// device in one transfer in stage_flush(), which then issues the launches
+// queued meanwhile, in their order.  The arena is reset (reset_stage) only
+// after the stream has been synchronised.
 struct Stage {
   char *h = nullptr, *d = nullptr;
   size_t cap = 0, used = 0;

@@ -2,9 +2,10 @@
 // multistep EPI integrators (Sec. 4, Eqs. 25, 30, 34-38) on the GPU.
 //
 // Host code here only takes control decisions (sub-step size tau, Krylov
-// dimension m, accept/reject) from a few scalars read back once per small
-// exponential; every vector operation, inner product, norm, the Hessenberg
-// matrix and its exponential live on the device.
+// dimension m, accept/reject) from a few scalars that the exponential kernel
+// writes into mapped host memory once per small exponential; every vector
+// operation, inner product, norm, the Hessenberg matrix and its exponential
+// live on the device.
 //
 // Controller (the paper defers KIOPS's internals to its own publication; this
 // is a complete statement of the one used here):
@@ -320,7 +321,7 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
     }
   }
   st = k.st;
-  return latched_error(c);   // synchronises the stream
+  return latched_error(c);   // every earlier operation on the stream has finished
 }
 
 // ---------------------------------------------------------------------------
@@ -697,7 +698,7 @@ int epi_step(dfr_ctx *h, epi_state *st, const kiops_opts *o, double *q_out, kiop
   }
   epi_rotate(st, q_new);
   if (q_out) DFR_HIP(hipMemcpyAsync(q_out, st->q, sizeof(double) * n3, hipMemcpyDeviceToDevice, c.stream));
-  return latched_error(c);   // synchronises the stream
+  return latched_error(c);   // every earlier operation on the stream has finished
 }
 
 int epi_step_concurrent(int n, dfr_ctx *const *ctxs, epi_state *const *states, const kiops_opts *o, int n_workers,
