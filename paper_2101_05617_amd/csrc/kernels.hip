@@ -1042,8 +1042,18 @@ __device__ __forceinline__ void arnoldi_combine_body(int blk, int nblk, int64_t 
   for (int k = threadIdx.x; k < J; k += blockDim.x) cf[k] = kd->sigma[k] * kd->E0[k];
   __syncthreads();
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
+    // added in k order; the loads of each group of 16 vectors are issued
+    // together (one memory round trip per group, not per few vectors)
     double acc = 0.0;
-    for (int k = 0; k < J; ++k) acc += (double)V[k * ldv + i] * cf[k];
+    int k = 0;
+    for (; k + 16 <= J; k += 16) {
+      TV xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xv[u] = V[(int64_t)(k + u) * ldv + i];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += (double)xv[u] * cf[k + u];
+    }
+    for (; k < J; ++k) acc += (double)V[(int64_t)k * ldv + i] * cf[k];
     x[i] = beta * acc;
   }
 }
