@@ -1160,9 +1160,24 @@ __device__ __forceinline__ void expm_body(KDev *kd, double tau, KHost *res, int 
   const int nn = P * ld;
   double *A = lds, *A2 = lds + nn, *Pm = lds + 2 * nn, *Qm = lds + 3 * nn;
   const int hld = MAX_M + 2;
-  for (int idx = tid; idx < P * P; idx += blockDim.x) {
-    const int i = idx / P, j = idx - i * P;
-    A[i * ld + j] = (i < J && j < J) ? tau * kd->H[i * hld + j] : 0.0;
+  // A = tau H (zero-padded to P x P): each thread's loads of a group of four
+  // entries issued together (every index i, j < P <= MAX_M is inside H)
+  for (int base = 0; base < P * P; base += 4 * (int)blockDim.x) {
+    double hv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = min(base + u * (int)blockDim.x + tid, P * P - 1);
+      const int i = idx / P, j = idx - i * P;
+      hv[u] = kd->H[i * hld + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * (int)blockDim.x + tid;
+      if (idx < P * P) {
+        const int i = idx / P, j = idx - i * P;
+        A[i * ld + j] = (i < J && j < J) ? tau * hv[u] : 0.0;
+      }
+    }
   }
   __syncthreads();
   // 1-norm of tau H_aug: the column sums of A, and |tau| for the last column
