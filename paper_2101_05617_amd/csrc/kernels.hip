@@ -434,10 +434,18 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   const int tcol = lb - p * ntx * nty - trow * ntx;
   const int ej0 = trow * TY, ei0 = tcol * TX;
 
-  for (int k = tid; k < NS * (NS + 2); k += blockDim.x) sD[k / (NS + 2)][k % (NS + 2)] = (T)ops.Dt[k / (NS + 2)][k % (NS + 2)];
-  if (tid < NS) {
-    slm[tid] = (T)ops.lm[tid];
-    slp[tid] = (T)ops.lp[tid];
+  {
+    // the 1-D operators to LDS: each thread's first entry and its lm / lp
+    // entries loaded together (one round trip), then any further entries
+    constexpr int ND = NS * (NS + 2);
+    const int k0 = min(tid, ND - 1), t0 = min(tid, NS - 1);
+    const double d0 = ops.Dt[k0 / (NS + 2)][k0 % (NS + 2)], m0 = ops.lm[t0], p0 = ops.lp[t0];
+    if (tid < ND) sD[k0 / (NS + 2)][k0 % (NS + 2)] = (T)d0;
+    if (tid < NS) {
+      slm[tid] = (T)m0;
+      slp[tid] = (T)p0;
+    }
+    for (int k = tid + (int)blockDim.x; k < ND; k += blockDim.x) sD[k / (NS + 2)][k % (NS + 2)] = (T)ops.Dt[k / (NS + 2)][k % (NS + 2)];
   }
   // face table: vertical faces (x^1 normal) id = fx*TY + row, fx = 0..TX;
   // then horizontal faces id = nvf + fy*TX + col, fy = 0..TY.  Halo slots:
@@ -491,20 +499,35 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     double uw[4];   // the bottom entries paired with the interleaved columns (0 beyond p)
 #pragma unroll
     for (int k = 0; k < 4; ++k) uw[k] = k < ar.p ? (ar.start ? ar.ybot[k] : ub[k]) : 0.0;
+    if (ar.wil) {
+      // four interleaved columns, two 16-byte loads per value: every load of
+      // the three fields first (one memory round trip), then the sums.
+      // Without a previous vector the direction v is read for a zero term.
+      const TV *vpp = ar.vprev ? static_cast<const TV *>(ar.vprev) : v;
+      double2 x0[3], x1[3];
+      double pv[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const int id = f * N + gidx;
-      double a = 0.0;
-      if (ar.wil) {
-        // four interleaved columns: two 16-byte loads per value
+      for (int f = 0; f < 3; ++f) {
+        const int id = f * N + gidx;
         const double2 *w2 = reinterpret_cast<const double2 *>(ar.W[0]) + 2 * (int64_t)id;
-        const double2 x0 = w2[0], x1 = w2[1];
-        a = ((x0.x * uw[0] + x0.y * uw[1]) + x1.x * uw[2]) + x1.y * uw[3];
-      } else {
-        for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
+        x0[f] = w2[0];
+        x1[f] = w2[1];
+        pv[f] = (double)vpp[id];
       }
-      wb[f] = a;
-      if (ar.vprev) vp[f] = sp * (double)static_cast<const TV *>(ar.vprev)[id];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        wb[f] = ((x0[f].x * uw[0] + x0[f].y * uw[1]) + x1[f].x * uw[2]) + x1[f].y * uw[3];
+        vp[f] = sp * pv[f];
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const int id = f * N + gidx;
+        double a = 0.0;
+        for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
+        wb[f] = a;
+        if (ar.vprev) vp[f] = sp * (double)static_cast<const TV *>(ar.vprev)[id];
+      }
     }
   }
 
