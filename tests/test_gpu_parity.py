@@ -269,6 +269,26 @@ def test_c1_full_size_rhs_jvp_parity():
     assert rel_fields(got32, ref, G.N) < 2e-5
 
 
+def test_c2_full_size_rhs_jvp_parity():
+    # ne = 60, p = 6 (1,058,400 nodes), mid-latitude jet: every element of F
+    # and J v, FP64 and complex-FP32, in the autotuned tiles of the J v timing
+    G, D, Q = pair(C2)
+    from paper_2101_05617_amd import dfrsw
+    dfrsw.dfr_autotune(D, "fp64")
+    e_rhs = rel_fields(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G.rhs(Q), G.N)
+    record("c2_rhs_fp64", e_rhs)
+    assert e_rhs < rhs_bar(G, Q)
+    V = inputs.random_direction(3 * G.N, 21)
+    ref = G.jvp(Q, V)
+    got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V)))
+    record("c2_jvp_fp64", rel_fields(got, ref, G.N))
+    assert rel_fields(got, ref, G.N) < 1e-12
+    dfrsw.dfr_autotune(D, "fp32_jv")
+    got32 = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
+    record("c2_jvp_fp32", rel_fields(got32, ref, G.N))
+    assert rel_fields(got32, ref, G.N) < 2e-5
+
+
 def test_c4_full_size_rhs_jvp_parity():
     # ne = 120, p = 6 (4,233,600 nodes), Gaussian mountain (orography): every
     # element of F and J v, FP64 and complex-FP32, in the autotuned tiles
