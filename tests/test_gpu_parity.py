@@ -408,6 +408,31 @@ def test_mixed_precision_kiops_against_fp64():
     assert err < 1e-5
 
 
+def test_c2_full_size_kiops_parity():
+    # ne = 60, p = 6 jet (3,175,200 unknowns): one phi_1 product in the
+    # autotuned Krylov-form tiles, FP64 (identical decisions, the plain-FP64
+    # bar) and with the complex-FP32 product (FP32 bar).  tau = dt/8 keeps
+    # the oracle's run to about 20 J v (one sub-step after two rejections).
+    G, D, Q = pair(C2)
+    from paper_2101_05617_amd import dfrsw
+    dfrsw.dfr_autotune(D, "fp64")
+    F = G.rhs(Q)
+    tau = C2.dt_nd / 8
+    ref, rst = okiops.kiops(tau, lambda v: G.jvp(Q, v), [None, F], tol=C2.tol, m_max=C2.m_max)
+    assert rst.n_rejected > 0
+    got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(C2.tol, C2.m_max))
+    assert (gst["n_substeps"], gst["n_rejected"], gst["n_matvec"]) == (rst.n_substeps, rst.n_rejected, rst.n_matvec)
+    err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
+    record("kiops_c2_full_fp64", err)
+    assert err <= 1e-11
+    dfrsw.dfr_autotune(D, "fp32_jv")
+    got32, _ = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(C2.tol, C2.m_max), C2.eps,
+                                     "fp32_jv")
+    err32 = np.linalg.norm(to_host(got32) - ref) / np.linalg.norm(ref)
+    record("kiops_c2_full_fp32_jv", err32)
+    assert err32 < 1e-5
+
+
 def test_ensemble_forms_match_members_run_alone():
     # the batched form (one launch per operation for all members) and the
     # concurrent form give what epi_step gives member by member, and the
