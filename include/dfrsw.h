@@ -59,6 +59,15 @@ enum {
  * ensemble form; dfr_jvp_complex_step treats it as DFR_FP32_JV. */
 typedef enum { DFR_FP64 = 0, DFR_FP32_JV = 1, DFR_FP32_JV_BASIS32 = 2 } dfr_precision;
 
+/* Smallest complex-step eps accepted with DFR_FP32_JV and DFR_FP32_JV_BASIS32
+ * (dfr_jvp_complex_step, kiops_phi_apply, epi_create and the ensemble
+ * creation return DFR_E_INVAL below it).  Inside KIOPS the product is applied
+ * to unit-norm vectors, whose typical entry is about 1/sqrt(3N); at this eps
+ * their FP32 imaginary parts stay about four orders above FP32's smallest
+ * normal number (1.2e-38) up to N ~ 1e7.  An FP64 eps such as 1e-150 would
+ * make them zero. */
+#define DFR_FP32_EPS_MIN 1e-30
+
 typedef struct dfr_ctx dfr_ctx;
 typedef struct epi_state epi_state;
 
@@ -181,7 +190,8 @@ int dfr_diagnostics(dfr_ctx *ctx, const double *q, double *zeta, double *fcor, d
 /* jv = Im F(q + i eps v) / eps (Eq. 28), one complex evaluation of the same
  * right-hand side.  prec = DFR_FP64: complex FP64.  prec = DFR_FP32_JV: the
  * complex evaluation runs in FP32 on FP32 roundings of q and v (eps must
- * keep eps*|v| far above 1e-38 on the caller's scale); jv is written in FP64.
+ * keep eps*|v| far above 1e-38 on the caller's scale, and eps >=
+ * DFR_FP32_EPS_MIN); jv is written in FP64.
  * Branches of the interface flux (|.|, max(.,.), the AUSM split ranges)
  * are those of the real evaluation at q.  q, v, jv: device, 3N doubles; jv may not alias q or v. */
 int dfr_jvp_complex_step(dfr_ctx *ctx, const double *q, const double *v, double eps,

@@ -937,9 +937,8 @@ int dfr_jvp_complex_step(dfr_ctx *h, const double *q, const double *v, double ep
     set_error("dfr_jvp_complex_step: test problems take the exact Jacobian in FP64 (DFR_FP64)");
     return DFR_E_INVAL;
   }
-  if (!h || !q || !v || !jv || jv == q || jv == v || !(eps > 0.0) ||
-      (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
-    set_error("invalid argument");
+  if (!h || !q || !v || !jv || jv == q || jv == v || !eps_prec_ok(eps, prec)) {
+    set_error("dfr_jvp_complex_step: invalid argument (an FP32 form needs eps >= DFR_FP32_EPS_MIN)");
     return DFR_E_INVAL;
   }
   Ctx &c = h->c;

@@ -25,6 +25,14 @@ constexpr int EXPM_BLOCK = DFR_EXPM_BLOCK;  // one workgroup of the small expone
 
 void set_error(const std::string &msg);
 
+// A valid precision with an eps that the complex evaluation can carry: any
+// positive eps in FP64, at least DFR_FP32_EPS_MIN in the FP32 forms.
+inline bool eps_prec_ok(double eps, dfr_precision prec) {
+  if (prec == DFR_FP64) return eps > 0.0;
+  if (prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32) return false;
+  return eps >= DFR_FP32_EPS_MIN;
+}
+
 #define DFR_HIP(call)                                                               \
   do {                                                                              \
     hipError_t e_ = (call);                                                         \

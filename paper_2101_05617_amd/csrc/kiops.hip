@@ -395,9 +395,8 @@ extern "C" {
 
 int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, const double *const *b, const kiops_opts *o,
                     double eps, dfr_precision prec, double *w, kiops_stats *stats) {
-  if (!h || !q || !b || !o || !w || !(eps > 0.0) ||
-      (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
-    set_error("kiops_phi_apply: invalid argument");
+  if (!h || !q || !b || !o || !w || !eps_prec_ok(eps, prec)) {
+    set_error("kiops_phi_apply: invalid argument (an FP32 form needs eps >= DFR_FP32_EPS_MIN)");
     return DFR_E_INVAL;
   }
   for (int k = 0; k <= n_phi && k <= MAX_P; ++k)
@@ -426,9 +425,9 @@ int kiops_phi_apply(dfr_ctx *h, const double *q, double tau_out, int n_phi, cons
 
 int epi_create(dfr_ctx *h, int order, double dt, int startup_substeps, const double *q0, double eps, dfr_precision prec,
                epi_state **out) {
-  if (!h || !q0 || !out || order < 2 || order > 6 || !(dt > 0.0) || startup_substeps < 1 || !(eps > 0.0) ||
-      (prec != DFR_FP64 && prec != DFR_FP32_JV && prec != DFR_FP32_JV_BASIS32)) {
-    set_error("epi_create: invalid argument");
+  if (!h || !q0 || !out || order < 2 || order > 6 || !(dt > 0.0) || startup_substeps < 1 ||
+      !eps_prec_ok(eps, prec)) {
+    set_error("epi_create: invalid argument (an FP32 form needs eps >= DFR_FP32_EPS_MIN)");
     return DFR_E_INVAL;
   }
   *out = nullptr;

@@ -47,6 +47,53 @@ def test_basis32_kiops_against_fp64():
     assert err < 1e-5
 
 
+def test_c4_full_size_kiops_fp64_and_basis32():
+    # ne = 120, p = 6 mountain (12,700,800 unknowns): one phi_1 product in the
+    # autotuned tiles of each form, FP64 (identical decisions, 1e-11) and
+    # with FP32 products and an FP32 basis (1e-5); tau = dt/4 bounds the
+    # oracle's run
+    G, D, Q = pair(C4)
+    from paper_2101_05617_amd import dfrsw
+    F = G.rhs(Q)
+    tau = C4.dt_nd / 4
+    opts = dfrsw.kiops_opts(tol=C4.tol, m_max=C4.m_max)
+    ref, rst = okiops.kiops(tau, lambda v: G.jvp(Q, v), [None, F], tol=C4.tol, m_max=C4.m_max)
+    dfrsw.dfr_autotune(D, "fp64")
+    got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], opts)
+    assert (gst["n_substeps"], gst["n_rejected"], gst["n_matvec"]) == (rst.n_substeps, rst.n_rejected, rst.n_matvec)
+    err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
+    record("kiops_c4_full_fp64", err)
+    assert err <= 1e-11
+    dfrsw.dfr_autotune(D, "fp32_jv_basis32")
+    got32, _ = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], opts, 1e-20, "fp32_jv_basis32")
+    err32 = np.linalg.norm(to_host(got32) - ref) / np.linalg.norm(ref)
+    record("kiops_c4_full_basis32", err32)
+    assert err32 < 1e-5
+
+
+def test_fp32_forms_reject_an_eps_that_underflows():
+    # an FP64 step (1e-150) would zero the FP32 imaginary parts of unit-norm
+    # Krylov vectors: every FP32 entry point refuses eps < DFR_FP32_EPS_MIN
+    from paper_2101_05617_amd import dfrsw
+    G, D, Q = pair(small(C2, 2, 3))
+    q, F = to_dev(Q), to_dev(G.rhs(Q))
+    opts = dfrsw.kiops_opts(tol=1e-8, m_max=16)
+    for prec in ("fp32_jv", "fp32_jv_basis32"):
+        with pytest.raises(dfrsw.DfrError) as e:
+            dfrsw.dfr_jvp_complex_step(D, q, F, 1e-150, prec)
+        assert e.value.code == -1 and "DFR_FP32_EPS_MIN" in str(e.value)
+        with pytest.raises(dfrsw.DfrError) as e:
+            dfrsw.kiops_phi_apply(D, q, 0.01, [None, F], opts, 1e-31, prec)
+        assert e.value.code == -1
+        with pytest.raises(dfrsw.DfrError) as e:
+            dfrsw.epi_create(D, 4, 0.01, q, startup_substeps=1, eps=1e-150, prec=prec)
+        assert e.value.code == -1
+        # the bound itself is accepted, and FP64 takes any positive eps
+        dfrsw.dfr_jvp_complex_step(D, q, F, 1e-30, prec)
+    dfrsw.dfr_jvp_complex_step(D, q, F, 1e-300, "fp64")
+    dfrsw.dfr_sync(D)
+
+
 @pytest.mark.parametrize("w", [small(C2, 4), small(C4, 4)], ids=["jet", "mountain"])
 def test_basis32_epi6_against_fp64_oracle(w):
     G, D, Q = pair(w)
