@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libdfrsw.so")
 DFR_FP64 = 0
 DFR_FP32_JV = 1
 DFR_FP32_JV_BASIS32 = 2
+DFR_FP32_EPS_MIN = 1e-30   # smallest complex-step eps of the FP32 forms (as in the header)
 _PREC = {"fp64": DFR_FP64, "fp32_jv": DFR_FP32_JV, "fp32_jv_basis32": DFR_FP32_JV_BASIS32,
          DFR_FP64: DFR_FP64, DFR_FP32_JV: DFR_FP32_JV, DFR_FP32_JV_BASIS32: DFR_FP32_JV_BASIS32}
 

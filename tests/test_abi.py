@@ -36,3 +36,14 @@ def test_binding_names_match_header():
     from paper_2101_05617_amd import dfrsw
     for n in dfrsw.exported_symbols():
         assert n in declared()
+
+
+def test_constants_match_header():
+    # the precision codes and the FP32 forms' eps bound as the binding has them
+    from paper_2101_05617_amd import dfrsw
+    src = open(HEADER).read()
+    m = re.search(r"#define\s+DFR_FP32_EPS_MIN\s+([0-9.eE+-]+)", src)
+    assert m and float(m.group(1)) == dfrsw.DFR_FP32_EPS_MIN
+    for name in ("DFR_FP64", "DFR_FP32_JV", "DFR_FP32_JV_BASIS32"):
+        v = re.search(name + r"\s*=\s*(\d+)", src)
+        assert v and int(v.group(1)) == getattr(dfrsw, name)
