@@ -300,6 +300,14 @@ enum { DFR_K_JV_ARNOLDI = 0, DFR_K_JV = 1, DFR_K_RHS = 2, DFR_K_UPDATE = 3, DFR_
        DFR_K_FINALIZE = 6, DFR_K_NKINDS = 7 };
 int dfr_timing_enable(dfr_ctx *ctx, int enable);
 int dfr_timing_read(dfr_ctx *ctx, int kind, double *total_ms, int64_t *launches);
+/* The same for the batched launches of an ensemble (epi_ensemble_step; not
+ * the tuning launches of dfr_ensemble_autotune), which run on the stream
+ * given to dfr_ensemble_create.  *nodes (may be NULL) receives the grid
+ * nodes the DFR launches of that kind covered, summed over launches and
+ * members (0 for the other kinds), so that bytes per node times nodes over
+ * the summed duration is the launches' algorithmic bandwidth. */
+int dfr_ensemble_timing_enable(dfr_ensemble *e, int enable);
+int dfr_ensemble_timing_read(dfr_ensemble *e, int kind, double *total_ms, int64_t *launches, double *nodes);
 
 const char *dfr_last_error(void);
 

@@ -461,50 +461,60 @@ static void free_ctx(Ctx &c) {
   (void)hipFree(c.d_tmp);
 }
 
-bool timing_slot(Ctx *c, int kind, hipEvent_t *start, hipEvent_t *stop) {
-  if (!c->timing) return false;
-  if (c->evused == c->evpool.size()) {
-    Ctx::EvPair e{};
+bool timing_slot(KTimer *t, int kind, double units, hipEvent_t *start, hipEvent_t *stop) {
+  if (!t->on) return false;
+  if (t->used == t->pool.size()) {
+    KTimer::EvPair e{};
     if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
-      c->timing = false;
+      t->on = false;
       return false;
     }
-    c->evpool.push_back(e);
+    t->pool.push_back(e);
   }
-  Ctx::EvPair &e = c->evpool[c->evused];
+  KTimer::EvPair &e = t->pool[t->used];
   e.kind = kind;
+  e.units = units;
   *start = e.a;
   *stop = e.b;
   return true;
 }
 
-void timing_done(Ctx *c) {
-  c->evused++;
-  // fold finished pairs back periodically so the pool stays small
-  if (c->evused >= 4096) {
-    (void)hipEventSynchronize(c->evpool[c->evused - 1].b);
-    for (size_t k = 0; k < c->evused; ++k) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->evpool[k].a, c->evpool[k].b) == hipSuccess) {
-        c->t_ms[c->evpool[k].kind] += ms;
-        c->t_n[c->evpool[k].kind] += 1;
-      }
+void timing_fold(KTimer &t) {
+  if (t.used == 0) return;
+  (void)hipEventSynchronize(t.pool[t.used - 1].b);
+  for (size_t k = 0; k < t.used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.pool[k].a, t.pool[k].b) == hipSuccess) {
+      t.t_ms[t.pool[k].kind] += ms;
+      t.t_n[t.pool[k].kind] += 1;
+      t.t_units[t.pool[k].kind] += t.pool[k].units;
     }
-    c->evused = 0;
   }
+  t.used = 0;
 }
 
-static void timing_fold(Ctx &c) {
-  if (c.evused == 0) return;
-  (void)hipEventSynchronize(c.evpool[c.evused - 1].b);
-  for (size_t k = 0; k < c.evused; ++k) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c.evpool[k].a, c.evpool[k].b) == hipSuccess) {
-      c.t_ms[c.evpool[k].kind] += ms;
-      c.t_n[c.evpool[k].kind] += 1;
-    }
+void timing_done(KTimer *t) {
+  // fold finished pairs back periodically so the pool stays small
+  if (++t->used >= 4096) timing_fold(*t);
+}
+
+void timing_reset(KTimer &t, bool on) {
+  timing_fold(t);
+  for (int k = 0; k < DFR_K_NKINDS; ++k) {
+    t.t_ms[k] = 0.0;
+    t.t_n[k] = 0;
+    t.t_units[k] = 0.0;
   }
-  c.evused = 0;
+  t.on = on;
+}
+
+void timing_free(KTimer &t) {
+  for (auto &e : t.pool) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  t.pool.clear();
+  t.used = 0;
 }
 
 // Wait for the kernel result numbered seq in the context's host mail: poll
@@ -697,32 +707,23 @@ int64_t dfr_num_unknowns(const dfr_ctx *h) { return h ? h->c.n3 : -1; }
 
 int dfr_timing_enable(dfr_ctx *h, int enable) {
   if (!h) return DFR_E_INVAL;
-  Ctx &c = h->c;
-  timing_fold(c);
-  for (int k = 0; k < DFR_K_NKINDS; ++k) {
-    c.t_ms[k] = 0.0;
-    c.t_n[k] = 0;
-  }
-  c.timing = enable != 0;
+  timing_reset(h->c.tm, enable != 0);
   return DFR_OK;
 }
 
 int dfr_timing_read(dfr_ctx *h, int kind, double *total_ms, int64_t *launches) {
   if (!h || kind < 0 || kind >= DFR_K_NKINDS || !total_ms || !launches) return DFR_E_INVAL;
-  Ctx &c = h->c;
-  timing_fold(c);
-  *total_ms = c.t_ms[kind];
-  *launches = c.t_n[kind];
+  KTimer &t = h->c.tm;
+  timing_fold(t);
+  *total_ms = t.t_ms[kind];
+  *launches = t.t_n[kind];
   return DFR_OK;
 }
 
 int dfr_destroy(dfr_ctx *h) {
   if (!h) return DFR_OK;
   (void)hipStreamSynchronize(h->c.stream);
-  for (auto &e : h->c.evpool) {
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
-  }
+  timing_free(h->c.tm);
   free_ctx(h->c);
   delete h;
   return DFR_OK;
@@ -858,8 +859,8 @@ int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
   const int keep[4] = {c.tile_tx, c.tile_ty, c.ar_tx, c.ar_ty};
   float best = 1e30f, best_ar = 1e30f;
   int bt[4] = {keep[0], keep[1], keep[2], keep[3]};
-  const bool was_timing = c.timing;
-  c.timing = false;
+  const bool was_timing = c.tm.on;
+  c.tm.on = false;
   for (const auto &t : tile_candidates(c)) {
     c.tile_tx = c.ar_tx = t.first;
     c.tile_ty = c.ar_ty = t.second;
@@ -886,7 +887,7 @@ int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
       bt[3] = t.second;
     }
   }
-  c.timing = was_timing;
+  c.tm.on = was_timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const int *use = rc ? keep : bt;

@@ -33,6 +33,7 @@ struct dfr_ensemble {
   int **d_errp = nullptr;            // the members' error flags
   int *d_errv = nullptr, *h_errv = nullptr;
   std::vector<hipEvent_t> evfree;    // events for read-backs in flight
+  KTimer tm;                         // event timing of the batched launches (dfr_ensemble_timing_*)
 };
 
 struct epi_ensemble {
@@ -318,6 +319,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
           s.x = k.w;
           s.v0 = c.d_V;
           s.pout = c.d_partials2;
+          s.kd = c.d_kd;
           starts.push_back(s);
           k.npB = s.nblk;
         }
@@ -432,6 +434,7 @@ static int ensemble_errors(dfr_ensemble &E) {
 static void free_ensemble(dfr_ensemble *E) {
   if (!E) return;
   if (E->stream) (void)hipStreamSynchronize(E->stream);
+  timing_free(E->tm);
   for (dfr_ctx *m : E->mem) dfr_destroy(m);
   (void)hipFree(E->d_ga);
   (void)hipFree(E->d_ops);
@@ -499,6 +502,7 @@ int dfr_ensemble_create(int n, const dfr_grid_desc *members, void *hip_stream, d
     return fail(DFR_E_NOMEM);
   }
   E->stage.cap = STAGE_BYTES;
+  E->stage.timer = &E->tm;
   if (hipMemcpy(E->d_ga, ga.data(), sizeof(GridArgs) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(E->d_ops, ops.data(), sizeof(Ops1D) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(E->d_errp, errp.data(), sizeof(int *) * n, hipMemcpyHostToDevice) != hipSuccess) {
@@ -511,6 +515,21 @@ int dfr_ensemble_create(int n, const dfr_grid_desc *members, void *hip_stream, d
 
 int dfr_ensemble_destroy(dfr_ensemble *E) {
   free_ensemble(E);
+  return DFR_OK;
+}
+
+int dfr_ensemble_timing_enable(dfr_ensemble *E, int enable) {
+  if (!E) return DFR_E_INVAL;
+  timing_reset(E->tm, enable != 0);
+  return DFR_OK;
+}
+
+int dfr_ensemble_timing_read(dfr_ensemble *E, int kind, double *total_ms, int64_t *launches, double *nodes) {
+  if (!E || kind < 0 || kind >= DFR_K_NKINDS || !total_ms || !launches) return DFR_E_INVAL;
+  timing_fold(E->tm);
+  *total_ms = E->tm.t_ms[kind];
+  *launches = E->tm.t_n[kind];
+  if (nodes) *nodes = E->tm.t_units[kind];
   return DFR_OK;
 }
 
@@ -532,6 +551,13 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
   const bool fp32 = prec != DFR_FP64, b32 = prec == DFR_FP32_JV_BASIS32;
   const int n = E->n;
   int rc = DFR_OK;
+  // the tuning launches are not timed
+  struct NoTiming {
+    Stage &st;
+    KTimer *keep;
+    explicit NoTiming(Stage &s) : st(s), keep(s.timer) { st.timer = nullptr; }
+    ~NoTiming() { st.timer = keep; }
+  } no_timing(E->stage);
   // a smooth state and a direction in every member's Krylov workspace, and
   // four b-columns interleaved as KIOPS keeps them
   for (int i = 0; i < n && !rc; ++i) {

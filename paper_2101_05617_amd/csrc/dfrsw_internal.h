@@ -151,6 +151,7 @@ struct StartCall {
   const double *x;
   void *v0;
   double *pout;
+  struct KDev *kd;        // its happy-breakdown flag is cleared
 };
 struct CombineCall {
   int b0, nblk;
@@ -217,6 +218,30 @@ struct HostMail {
   unsigned seq;
 };
 
+// Per-kernel timing with HIP events: while on, each launch takes a start /
+// stop event pair that the runtime stamps at the kernel's own dispatch and
+// completion (hipExtLaunchKernelGGL), so no marker packets enter the stream.
+// Launches are classified by kind (DFR_K_*); `units` is a per-launch count
+// the caller chooses (the batched DFR launches record their nodes).
+struct KTimer {
+  bool on = false;
+  struct EvPair {
+    hipEvent_t a, b;
+    int kind;
+    double units;
+  };
+  std::vector<EvPair> pool;
+  size_t used = 0;
+  double t_ms[DFR_K_NKINDS] = {0};
+  int64_t t_n[DFR_K_NKINDS] = {0};
+  double t_units[DFR_K_NKINDS] = {0};
+};
+bool timing_slot(KTimer *t, int kind, double units, hipEvent_t *start, hipEvent_t *stop);
+void timing_done(KTimer *t);
+void timing_fold(KTimer &t);       // wait for the recorded launches and add them up
+void timing_reset(KTimer &t, bool on);
+void timing_free(KTimer &t);
+
 struct Ctx {
   int ne, ns, p_deg;
   int64_t n, nelem;
@@ -263,30 +288,26 @@ struct Ctx {
   double *d_qf32 = nullptr;       // FP32 copy of the linearisation state (as float*)
   double *d_tmp = nullptr;        // scratch vector 3N
   // optional per-kernel event timing
-  bool timing = false;
-  struct EvPair { hipEvent_t a, b; int kind; };
-  std::vector<EvPair> evpool;
-  size_t evused = 0;
-  double t_ms[DFR_K_NKINDS] = {0};
-  int64_t t_n[DFR_K_NKINDS] = {0};
+  KTimer tm;
 };
 
-// Per-kernel timing: when enabled, a launch takes a start/stop event pair
-// that the runtime stamps at the kernel's own dispatch and completion
-// (hipExtLaunchKernelGGL), so no marker packets are added to the stream.
-bool timing_slot(Ctx *c, int kind, hipEvent_t *start, hipEvent_t *stop);
-void timing_done(Ctx *c);
+// a launch on timer t's terms (timed while t is on), on stream s
+template <typename... KArgs, typename... Args>
+inline void timed_launch(KTimer *t, int kind, double units, hipStream_t s, void (*kernel)(KArgs...), dim3 grid,
+                         dim3 block, size_t shmem, Args... args) {
+  hipEvent_t e0, e1;
+  if (t && timing_slot(t, kind, units, &e0, &e1)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, s, e0, e1, 0, args...);
+    timing_done(t);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
+}
 
 template <typename... KArgs, typename... Args>
 inline void dfr_launch(Ctx *c, int kind, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem,
                        Args... args) {
-  hipEvent_t e0, e1;
-  if (timing_slot(c, kind, &e0, &e1)) {
-    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, c->stream, e0, e1, 0, args...);
-    timing_done(c);
-  } else {
-    hipLaunchKernelGGL(kernel, grid, block, shmem, c->stream, args...);
-  }
+  timed_launch(&c->tm, kind, 0.0, c->stream, kernel, grid, block, shmem, args...);
 }
 
 // kernels.hip
@@ -363,6 +384,7 @@ void epi_rotate(epi_state *st, double *q_new);
 // queued meanwhile, in their order.  The arena is reset (reset_stage) only
 // after the stream has been synchronised.
 struct Stage {
+  KTimer *timer = nullptr;                        // times the batched launches while on
   char *h = nullptr, *d = nullptr;
   size_t cap = 0, used = 0;
   bool defer = false;

@@ -1030,11 +1030,16 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *
                       static_cast<const TV *>(c.vprev), c.pin, c.np_in, c.pout, c.kd);
 }
 
-// start of a sub-step: v~_0 = x (copied), partial ||x||^2 per workgroup
+// start of a sub-step: v~_0 = x (copied), partial ||x||^2 per workgroup.
+// Workgroup 0 also clears the happy-breakdown flag of the previous sub-step
+// (or of an earlier call on the context): every later kernel of the sweep
+// reads it in stream order, and the Krylov-form products return at once
+// while it is set.
 template <typename TV>
 __device__ __forceinline__ void arnoldi_start_body(int blk, int nblk, int64_t n3, const double *x, TV *v0,
-                                                   double *pout) {
+                                                   double *pout, KDev *kd) {
   __shared__ double red[BLOCK / 64];
+  if (blk == 0 && threadIdx.x == 0) kd->happy = 0;
   double acc = 0.0;
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     const TV xv = (TV)x[i];
@@ -1045,13 +1050,14 @@ __device__ __forceinline__ void arnoldi_start_body(int blk, int nblk, int64_t n3
   if (threadIdx.x == 0) pout[blk] = b;
 }
 template <typename TV>
-__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, TV *v0, double *pout) {
-  arnoldi_start_body(blockIdx.x, gridDim.x, n3, x, v0, pout);
+__global__ __launch_bounds__(BLOCK) void arnoldi_start_kernel(int64_t n3, const double *x, TV *v0, double *pout,
+                                                              KDev *kd) {
+  arnoldi_start_body(blockIdx.x, gridDim.x, n3, x, v0, pout, kd);
 }
 template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_start_batch(const StartCall *__restrict__ calls, int ncalls) {
   const StartCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_start_body(blockIdx.x - c.b0, c.nblk, c.n3, c.x, static_cast<TV *>(c.v0), c.pout);
+  arnoldi_start_body(blockIdx.x - c.b0, c.nblk, c.n3, c.x, static_cast<TV *>(c.v0), c.pout, c.kd);
 }
 
 // accepted sub-step: x = beta * sum_{k<J} sigma_k v~_k E[k][0]; the
@@ -1797,9 +1803,11 @@ int launch_start(Ctx *c, const double *x, void *v0, double *pout, int *np_out) {
   const int64_t n3 = c->n3;
   const int nb = grid_reduce(n3);
   if (c->basis32)
-    dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<float *>(v0), pout);
+    dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<float>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<float *>(v0), pout,
+               c->d_kd);
   else
-    dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<double>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<double *>(v0), pout);
+    dfr_launch(c, DFR_K_OTHER, arnoldi_start_kernel<double>, dim3(nb), dim3(BLOCK), 0, n3, x, static_cast<double *>(v0), pout,
+               c->d_kd);
   DFR_HIP(hipGetLastError());
   *np_out = nb;
   return DFR_OK;
@@ -1926,10 +1934,12 @@ template <int NS, typename T, typename TQ, bool CS, bool AR, typename TV>
 static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &calls) {
   int nlog = 0, threads = 256;
   size_t lds = 0;
+  double nodes = 0.0;
   for (auto &c : calls) {
     c.b0 = nlog;
     c.ntiles = 6 * (c.g_ne / c.TX) * (c.g_ne / c.TY);
     nlog += c.ntiles;
+    nodes += (double)c.ntiles * c.TX * c.TY * NS * NS;
     threads = std::max(threads, ((c.TX * c.TY * NS * NS + 63) / 64) * 64);
     lds = std::max(lds, (size_t)dfr_lds_layout(NS, c.TX, c.TY, CS ? 2 : 1, (int)sizeof(T)).total * sizeof(T));
   }
@@ -1938,9 +1948,11 @@ static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &c
   if (rc) return rc;
   const int grid = ((nlog + 7) / 8) * 8;
   const int n = (int)calls.size();
+  const int kind = AR ? DFR_K_JV_ARNOLDI : (CS ? DFR_K_JV : DFR_K_RHS);
+  KTimer *tm = st.timer;
   return stage_launch(st, [=]() -> int {
-    hipLaunchKernelGGL((dfr_kernel_batch<NS, T, TQ, CS, AR, TV>), dim3(grid), dim3(threads), lds, s, (const DfrCall *)d,
-                       n, nlog);
+    timed_launch(tm, kind, nodes, s, dfr_kernel_batch<NS, T, TQ, CS, AR, TV>, dim3(grid), dim3(threads), lds,
+                 (const DfrCall *)d, n, nlog);
     DFR_HIP(hipGetLastError());
     return DFR_OK;
   });
@@ -1979,15 +1991,16 @@ int launch_dfr_batch(hipStream_t s, Stage &st, int ns, bool complex_step, bool f
 }
 
 template <typename C, typename K>
-static int launch_calls(hipStream_t s, Stage &st, std::vector<C> &calls, K kernel) {
+static int launch_calls(hipStream_t s, Stage &st, std::vector<C> &calls, K kernel, int kind = DFR_K_OTHER) {
   if (calls.empty()) return DFR_OK;
   const int nb = set_b0(calls);
   void *d = nullptr;
   int rc = stage_put(st, s, calls.data(), sizeof(C) * calls.size(), &d);
   if (rc) return rc;
   const int n = (int)calls.size();
+  KTimer *tm = st.timer;
   return stage_launch(st, [=]() -> int {
-    hipLaunchKernelGGL(kernel, dim3(nb), dim3(BLOCK), 0, s, (const C *)d, n);
+    timed_launch(tm, kind, 0.0, s, kernel, dim3(nb), dim3(BLOCK), 0, (const C *)d, n);
     DFR_HIP(hipGetLastError());
     return DFR_OK;
   });
@@ -1998,8 +2011,8 @@ int launch_first_batch(hipStream_t s, Stage &st, bool basis32, std::vector<First
                  : launch_calls(s, st, calls, arnoldi_first_batch<double>);
 }
 int launch_update_batch(hipStream_t s, Stage &st, bool basis32, std::vector<UpdateCall> &calls) {
-  return basis32 ? launch_calls(s, st, calls, arnoldi_update_batch<float>)
-                 : launch_calls(s, st, calls, arnoldi_update_batch<double>);
+  return basis32 ? launch_calls(s, st, calls, arnoldi_update_batch<float>, DFR_K_UPDATE)
+                 : launch_calls(s, st, calls, arnoldi_update_batch<double>, DFR_K_UPDATE);
 }
 int launch_start_batch(hipStream_t s, Stage &st, bool basis32, std::vector<StartCall> &calls) {
   return basis32 ? launch_calls(s, st, calls, arnoldi_start_batch<float>)
@@ -2016,8 +2029,9 @@ int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, si
   int rc = stage_put(st, s, calls.data(), sizeof(ExpmCall) * calls.size(), &d);
   if (rc) return rc;
   const unsigned n = (unsigned)calls.size();
+  KTimer *tm = st.timer;
   return stage_launch(st, [=]() -> int {
-    hipLaunchKernelGGL(expm_batch, dim3(n), dim3(EXPM_BLOCK), lds, s, (const ExpmCall *)d);
+    timed_launch(tm, DFR_K_EXPM, 0.0, s, expm_batch, dim3(n), dim3(EXPM_BLOCK), lds, (const ExpmCall *)d);
     DFR_HIP(hipGetLastError());
     return DFR_OK;
   });
@@ -2035,8 +2049,9 @@ int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> 
       int rc = stage_put(st, s, calls.data(), sizeof(AxpbyCall) * calls.size(), &d);
       if (rc) return rc;
       const unsigned n = (unsigned)calls.size();
+      KTimer *tm = st.timer;
       return stage_launch(st, [=]() -> int {
-        hipLaunchKernelGGL(sum_batch, dim3(n), dim3(BLOCK), 0, s, (const AxpbyCall *)d);
+        timed_launch(tm, DFR_K_FINALIZE, 0.0, s, sum_batch, dim3(n), dim3(BLOCK), 0, (const AxpbyCall *)d);
         DFR_HIP(hipGetLastError());
         return DFR_OK;
       });

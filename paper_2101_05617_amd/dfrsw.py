@@ -107,6 +107,8 @@ def lib():
             "dfr_autotune": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_timing_enable": (i, [vp, i]),
             "dfr_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64)]),
+            "dfr_ensemble_timing_enable": (i, [vp, i]),
+            "dfr_ensemble_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(d)]),
             "dfr_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -123,7 +125,7 @@ def exported_symbols():
             "epi_num_steps", "epi_destroy", "epi_save", "epi_load", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
             "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_diagnostics", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
-            "dfr_timing_read", "dfr_last_error"]
+            "dfr_timing_read", "dfr_ensemble_timing_enable", "dfr_ensemble_timing_read", "dfr_last_error"]
 
 
 def _check(rc):
@@ -456,6 +458,18 @@ def dfr_ensemble_create(members):
 def dfr_ensemble_autotune(eg: EnsembleGrid, prec="fp64"):
     _check(lib().dfr_ensemble_autotune(eg.handle, _PREC[prec]))
     return [dfr_get_krylov_tile(m) for m in eg.members]
+
+
+def dfr_ensemble_timing_enable(eg: EnsembleGrid, enable=True):
+    _check(lib().dfr_ensemble_timing_enable(eg.handle, int(bool(enable))))
+
+
+def dfr_ensemble_timing_read(eg: EnsembleGrid, kind):
+    """(summed ms, launches, nodes covered) of the batched launches of one kind."""
+    ms, n, nodes = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().dfr_ensemble_timing_read(eg.handle, KERNEL_KINDS.get(kind, kind), ctypes.byref(ms), ctypes.byref(n),
+                                          ctypes.byref(nodes)))
+    return ms.value, n.value, nodes.value
 
 
 def epi_ensemble_create(eg, order, dt, q0s, startup_substeps=10, eps=1e-150, prec="fp64"):
