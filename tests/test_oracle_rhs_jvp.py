@@ -24,7 +24,8 @@ def rel(a, b):
 
 @pytest.mark.parametrize("ne,p", [(2, 3), (4, 4), (3, 6)])
 def test_mass_conserved_to_roundoff(ne, p):
-    # the discrete mass tendency sums to zero for any state
+    # Sec. 5.4, Eq. 44 (mass conservation): the discrete mass tendency sums
+    # to zero for any state
     w = replace(C0, ne=ne, p=p, h_amp=0.05, u_amp=5.0, h_lmax=6)
     G, Q, _ = grid_and_state(w)
     F = G.rhs(Q)
