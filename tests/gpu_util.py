@@ -55,6 +55,91 @@ def rel_fields(a, b, N):
     return out
 
 
+def node_name(i, ne, ns):
+    """(field, panel, element row, element column, node row, node column) of
+    state index i in the field-major layout."""
+    N = 6 * ne * ne * ns * ns
+    f, k = divmod(int(i), N)
+    e, node = divmod(k, ns * ns)
+    panel, r = divmod(e, ne * ne)
+    ej, ei = divmod(r, ne)
+    nj, ni = divmod(node, ns)
+    return dict(field=f, panel=panel, ej=ej, ei=ei, nj=nj, ni=ni)
+
+
+def edge_mask(ne, ns):
+    """Nodes of the elements that touch a panel edge (the App. C maps act
+    on their faces), for one field of N values."""
+    e = np.arange(6 * ne * ne)
+    ei, ej = e % ne, (e // ne) % ne
+    el = (ei == 0) | (ei == ne - 1) | (ej == 0) | (ej == ne - 1)
+    return np.repeat(el, ns * ns)
+
+
+def field_metrics(a, b, ne, ns):
+    """Per-field relative errors of a against b, each the maximum over the
+    three fields:
+      l2        ||a_f - b_f||_2 / ||b_f||_2
+      max       max_i |a_f,i - b_f,i| / max_i |b_f,i|      (element-wise)
+      edge_l2   the l2 measure over the nodes of panel-edge elements
+      edge_max  the element-wise measure over those nodes, against max |b_f|
+    and the index of the worst element-wise difference (relative to its
+    field's max |b_f|)."""
+    N = 6 * ne * ne * ns * ns
+    a = np.asarray(a).reshape(3, N)
+    b = np.asarray(b).reshape(3, N)
+    m = edge_mask(ne, ns)
+    out = dict(l2=0.0, max=0.0, edge_l2=0.0, edge_max=0.0)
+    worst, wval = 0, -1.0
+    for f in range(3):
+        d = np.abs(a[f] - b[f])
+        den2 = np.linalg.norm(b[f])
+        denm = np.max(np.abs(b[f]))
+        den2e = np.linalg.norm(b[f][m])
+        r = d / denm if denm > 0 else d
+        out["l2"] = max(out["l2"], np.linalg.norm(d) / den2 if den2 > 0 else np.linalg.norm(d))
+        out["max"] = max(out["max"], float(r.max()))
+        out["edge_l2"] = max(out["edge_l2"], np.linalg.norm(d[m]) / den2e if den2e > 0 else np.linalg.norm(d[m]))
+        out["edge_max"] = max(out["edge_max"], float(r[m].max()))
+        k = int(np.argmax(r))
+        if r[k] > wval:
+            wval, worst = float(r[k]), f * N + k
+    out["worst"] = worst
+    return out
+
+
+def check_fields(got, ref, G, bar, key=None, bar_max=None):
+    """Assert that got matches ref node by node: the relative L2 measure per
+    field, the element-wise maximum per field (against the field's largest
+    value) and both measures over the panel-edge elements alone, each below
+    its bar (bar_max for the two element-wise measures, default bar).  On
+    failure the message names the worst node.  G: the oracle grid (ne, ns).
+    Records the measures under key."""
+    fm = field_metrics(got, ref, G.ne, G.ns)
+    bm = bar if bar_max is None else bar_max
+    if key is not None:
+        for k in ("l2", "max", "edge_l2", "edge_max"):
+            record(f"{key}_{k}" if k != "l2" else key, fm[k])
+    ok = fm["l2"] < bar and fm["edge_l2"] < bar and fm["max"] < bm and fm["edge_max"] < bm
+    assert ok, (f"{key}: l2 {fm['l2']:.3e} edge_l2 {fm['edge_l2']:.3e} (bar {bar:.1e}); max {fm['max']:.3e} "
+                f"edge_max {fm['edge_max']:.3e} (bar {bm:.1e}); worst node {node_name(fm['worst'], G.ne, G.ns)}")
+    return fm
+
+
+def check_krylov(got, ref, G, bar, key=None):
+    """check_fields for a result of the Krylov path (a phi-combination, an
+    EPI state): the L2 measures at bar, the element-wise ones a decade
+    above.  Rounding differences of such results do not spread evenly: they
+    gather where the metric terms are largest (panel corners, X = Y = +-1) and
+    where the Krylov combination cancels most (large tau ||J||), so that
+    the largest single-node difference reaches 20-25 times the relative L2
+    difference in these tests (1.3e-11 against 6.3e-13 for an EPI2 step of
+    4 h).  A mistake in the panel-edge maps or the halo indices moves the
+    nodes it touches by the size of the terms involved, decades above the
+    element-wise bar."""
+    return check_fields(got, ref, G, bar, key, bar_max=10.0 * bar)
+
+
 def small(w, ne, p=None, **kw):
     return replace(w, ne=ne, p=w.p if p is None else p, **kw)
 
@@ -71,6 +156,23 @@ def rhs_rounding_floor(G, Q):
 
 def rhs_bar(G, Q):
     return max(1e-11, 4.0 * rhs_rounding_floor(G, Q))
+
+
+def rhs_bars(G, Q):
+    """(L2 bar, element-wise bar) of an F(q) comparison: each max(1e-11, 4 x
+    the oracle's own change in that measure under a random 1-ulp
+    perturbation of q)."""
+    rng = np.random.default_rng(12345)
+    Qp = Q * (1.0 + 2.0 ** -52 * rng.standard_normal(Q.shape))
+    fm = field_metrics(G.rhs(Qp), G.rhs(Q), G.ne, G.ns)
+    return (max(1e-11, 4.0 * max(fm["l2"], fm["edge_l2"])), max(1e-11, 4.0 * max(fm["max"], fm["edge_max"])))
+
+
+def check_rhs(got, G, Q, key=None):
+    """F(q) from the library against the oracle's, node by node, at the
+    conditioning bars of rhs_bars."""
+    b2, bm = rhs_bars(G, Q)
+    return check_fields(got, G.rhs(Q), G, b2, key, bar_max=bm)
 
 
 METRICS = {}

@@ -3,16 +3,17 @@ where KIOPS needs several sub-steps, rejections and large Krylov spaces, with
 EPI2 (Eq. 25), EPI3 (Eq. 30) and EPI6 (Eqs. 34-38) -- the GPU path against
 the oracle after every step, with the same controller decisions.
 
-Bar: 1e-11 relative L2 per field (the plain-FP64 target); both sides take
+Bar: 1e-11 per field (the plain-FP64 target) in relative L2 and 1e-10
+element by element (check_krylov), over all nodes and over the panel-edge
+elements; both sides take
 the same sub-steps and Krylov sizes, so they differ only by rounding."""
 from dataclasses import replace
 
-import numpy as np
 import pytest
 
 from oracle import epi as oepi
 from paper_2101_05617_amd import inputs
-from tests.gpu_util import pair, record, rel_fields, to_dev, to_host, torch_dev
+from tests.gpu_util import check_krylov, pair, to_dev, to_host, torch_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +46,6 @@ def test_large_dt_epi_parity_and_adaptivity(order, steps):
         sub += gst["n_substeps"]
         rej += gst["n_rejected"]
         calls += len(ost)
-        err = rel_fields(to_host(dfrsw.epi_get_state(st)), E.q, G.N)
-        record(f"large_dt_epi{order}_step{k + 1}", err)
-        assert err < 1e-11, (k, err)
+        check_krylov(to_host(dfrsw.epi_get_state(st)), E.q, G, 1e-11, f"large_dt_epi{order}_step{k + 1}")
     # the controller was exercised: sub-stepping or rejections
     assert sub > calls or rej > 0

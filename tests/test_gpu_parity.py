@@ -1,21 +1,30 @@
 """GPU parity: the HIP library against the FP64 oracle on identical seeded
 inputs, element by element, through the C ABI.
 
-Tolerances (relative L2 per field, maximum over the three fields):
+Every comparison of a state-sized result applies its bar to four measures
+per field (tests/gpu_util.check_fields): the relative L2 difference, the
+element-wise maximum difference against the field's largest value, and both
+over the nodes of the elements that touch a panel edge, where the App. C
+maps act; a failure names the worst node (field, panel, element, node).
+
+Tolerances (each measure per field, maximum over the three fields):
   FP64 J v            1e-12.  Both sides evaluate the same formulas in FP64;
       they differ only in operation order, FMA contraction and the division /
       square-root sequences, i.e. O(1e-16) per operation; J v of a random
       direction is well conditioned (a 1-ulp input perturbation moves it by
       ~5e-16), so 1e-12 leaves three orders of margin.
   FP64 F(q)           max(1e-11, 4 x floor), floor = the oracle's own relative
-      change under a random 1-ulp perturbation of q.  The tendency of a
-      near-balanced state is a residual of flux terms 1e3-1e5 times larger:
+      change under a random 1-ulp perturbation of q (in the same measure).
+      The tendency of a near-balanced state is a residual of flux terms
+      1e3-1e5 times larger:
       its condition makes any two correct FP64 evaluations differ by ~floor
       (2.6e-11 at ne = 30, p = 5; 6e-11 at ne = 4, p = 4).
   FP32 J v            2e-5.  Complex FP32 evaluation (unit roundoff 6e-8)
       with the same cancellation factor (~1e2-1e3).
   KIOPS, EPI          1e-11 after every step (the plain-FP64 target), with
-      identical controller decisions (sub-steps, rejections, Krylov size).
+      identical controller decisions (sub-steps, rejections, Krylov size);
+      the element-wise measures a decade above (check_krylov: rounding of
+      Krylov results gathers at a few nodes).
 """
 from dataclasses import replace
 
@@ -26,8 +35,8 @@ import oracle
 from oracle import epi as oepi
 from oracle import kiops as okiops
 from paper_2101_05617_amd import inputs
-from tests.gpu_util import (dump_metrics, pair, record, rel_fields, rhs_bar, small, to_dev, to_host,
-                            torch_dev)
+from tests.gpu_util import (check_fields, check_krylov, check_rhs, dump_metrics, field_metrics, pair, record, small, to_dev,
+                            to_host, torch_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -54,12 +63,9 @@ def test_rhs_parity(ne, p):
     w = small(C0, ne, p, u_amp=2.0)
     G, D, Q = pair(w)
     from paper_2101_05617_amd import dfrsw
-    ref = G.rhs(Q)
     got = to_host(dfrsw.dfr_rhs(D, to_dev(Q)))
     dfrsw.dfr_sync(D)
-    err = rel_fields(got, ref, G.N)
-    record(f"rhs_fp64_ne{ne}_p{p}", err)
-    assert err < rhs_bar(G, Q)
+    check_rhs(got, G, Q, f"rhs_fp64_ne{ne}_p{p}")
 
 
 @pytest.mark.parametrize("ne,p", GRIDS)
@@ -71,9 +77,7 @@ def test_jvp_parity_fp64(ne, p):
     ref = G.jvp(Q, V, 1e-150)
     got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-150, "fp64"))
     dfrsw.dfr_sync(D)
-    err = rel_fields(got, ref, G.N)
-    record(f"jvp_fp64_ne{ne}_p{p}", err)
-    assert err < 1e-12
+    check_fields(got, ref, G, 1e-12, f"jvp_fp64_ne{ne}_p{p}")
 
 
 def test_jvp_eps_independence_and_linearity():
@@ -97,9 +101,7 @@ def test_jvp_parity_fp32(ne, p):
     ref = G.jvp(Q, V, 1e-150)
     got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
     dfrsw.dfr_sync(D)
-    err = rel_fields(got, ref, G.N)
-    record(f"jvp_fp32_ne{ne}_p{p}", err)
-    assert err < 2e-5
+    check_fields(got, ref, G, 2e-5, f"jvp_fp32_ne{ne}_p{p}")
 
 
 def test_mass_conservation_on_gpu():
@@ -118,22 +120,17 @@ def test_orography_parity():
     w = replace(inputs.WORKLOADS["c4_ne120_p6_mountain"], ne=3, h_amp=0.01, h_lmax=6, u_amp=2.0)
     G, D, Q = pair(w)
     from paper_2101_05617_amd import dfrsw
-    ref = G.rhs(Q)
     got = to_host(dfrsw.dfr_rhs(D, to_dev(Q)))
-    record("rhs_mountain_perturbed", rel_fields(got, ref, G.N))
-    assert rel_fields(got, ref, G.N) < rhs_bar(G, Q)
+    check_rhs(got, G, Q, "rhs_mountain_perturbed")
     # the unperturbed state is nearly in balance: its tendency (~1e-6) is a
     # cancellation of gravity and orography terms ~4e5 times larger
     w0 = replace(inputs.WORKLOADS["c4_ne120_p6_mountain"], ne=3)
     G0, D0, Q0 = pair(w0)
-    ref0 = G0.rhs(Q0)
     got0 = to_host(dfrsw.dfr_rhs(D0, to_dev(Q0)))
-    record("rhs_mountain_balanced", rel_fields(got0, ref0, G0.N))
-    assert rel_fields(got0, ref0, G0.N) < rhs_bar(G0, Q0)
+    check_rhs(got0, G0, Q0, "rhs_mountain_balanced")
     V = inputs.random_direction(3 * G.N, 4)
-    err = rel_fields(to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V))), G.jvp(Q, V), G.N)
-    record("jvp_mountain", err)
-    assert err < 1e-12
+    check_fields(to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V))), G.jvp(Q, V), G, 1e-12,
+                 "jvp_mountain")
 
 
 @pytest.mark.parametrize("rot", [(0.0, 0.0, 0.0), (0.3, 0.5, 0.2)])
@@ -141,7 +138,7 @@ def test_other_rotations(rot):
     w = small(C0, 3, 4, u_amp=1.0)
     G, D, Q = pair(w, rotation=rot)
     from paper_2101_05617_amd import dfrsw
-    assert rel_fields(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G.rhs(Q), G.N) < rhs_bar(G, Q)
+    check_rhs(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G, Q, f"rhs_rotation_{rot[0]}_{rot[1]}_{rot[2]}")
 
 
 def test_invalid_depth_is_reported():
@@ -185,8 +182,7 @@ def test_kiops_parity(nphi, with_b0):
     got = to_host(got)
     assert (gst["n_substeps"], gst["n_rejected"], gst["m_last"]) == (rst.n_substeps, rst.n_rejected, rst.m_last)
     assert gst["n_matvec"] == rst.n_matvec
-    record(f"kiops_nphi{nphi}_b0{int(with_b0)}", np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
+    check_krylov(got, ref, G, 1e-11, f"kiops_nphi{nphi}_b0{int(with_b0)}")
 
 
 def test_kiops_substepping_parity():
@@ -200,7 +196,7 @@ def test_kiops_substepping_parity():
     got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(1e-10, 12, m_init=8, m_min=4))
     assert rst.n_substeps > 1
     assert (gst["n_substeps"], gst["n_rejected"]) == (rst.n_substeps, rst.n_rejected)
-    assert np.linalg.norm(to_host(got) - ref) <= 1e-11 * np.linalg.norm(ref)
+    check_krylov(to_host(got), ref, G, 1e-11, "kiops_substepping")
 
 
 def test_kiops_iop1_parity_and_invalid_iop():
@@ -213,9 +209,7 @@ def test_kiops_iop1_parity_and_invalid_iop():
     ref, rst = okiops.kiops(tau, lambda v: G.jvp(Q, v), [None, F], tol=1e-12, m_max=32, iop=1)
     got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(1e-12, 32, iop=1))
     assert (gst["n_substeps"], gst["n_rejected"], gst["n_matvec"]) == (rst.n_substeps, rst.n_rejected, rst.n_matvec)
-    err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
-    record("kiops_iop1", err)
-    assert err <= 1e-11
+    check_krylov(to_host(got), ref, G, 1e-11, "kiops_iop1")
     with pytest.raises(dfrsw.DfrError) as e:
         dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(1e-12, 32, iop=3))
     assert e.value.code == -1
@@ -232,10 +226,12 @@ def _epi_compare(w, steps, s, tol_rel=1e-11, prec="fp64", eps=1e-150, check_ever
         E.step()
         stats = dfrsw.epi_step(D, st, _kopts(w.tol, w.m_max))
         got = to_host(dfrsw.epi_get_state(st))
-        errs.append(rel_fields(got, E.q, G.N))
-        record(f"epi{w.order}_{w.name}_ne{w.ne}_p{w.p}_step{k + 1}", errs[-1])
+        key = f"epi{w.order}_{w.name}_ne{w.ne}_p{w.p}_step{k + 1}"
         if check_every:
-            assert errs[-1] < tol_rel, (k, errs)
+            errs.append(check_krylov(got, E.q, G, tol_rel, key)["l2"])
+        else:
+            errs.append(field_metrics(got, E.q, G.ne, G.ns)["l2"])
+            record(key, errs[-1])
     return errs
 
 
@@ -256,17 +252,13 @@ def test_c1_full_size_rhs_jvp_parity():
     # ne = 30, p = 5 (194,400 nodes): every element of F and J v
     G, D, Q = pair(C1)
     from paper_2101_05617_amd import dfrsw
-    e_rhs = rel_fields(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G.rhs(Q), G.N)
-    record("c1_rhs_fp64", e_rhs)
-    assert e_rhs < rhs_bar(G, Q)
+    check_rhs(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G, Q, "c1_rhs_fp64")
     V = inputs.random_direction(3 * G.N, 31)
     ref = G.jvp(Q, V)
     got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V)))
-    record("c1_jvp_fp64", rel_fields(got, ref, G.N))
-    assert rel_fields(got, ref, G.N) < 1e-12
+    check_fields(got, ref, G, 1e-12, "c1_jvp_fp64")
     got32 = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
-    record("c1_jvp_fp32", rel_fields(got32, ref, G.N))
-    assert rel_fields(got32, ref, G.N) < 2e-5
+    check_fields(got32, ref, G, 2e-5, "c1_jvp_fp32")
 
 
 def test_c2_full_size_rhs_jvp_parity():
@@ -275,18 +267,14 @@ def test_c2_full_size_rhs_jvp_parity():
     G, D, Q = pair(C2)
     from paper_2101_05617_amd import dfrsw
     dfrsw.dfr_autotune(D, "fp64")
-    e_rhs = rel_fields(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G.rhs(Q), G.N)
-    record("c2_rhs_fp64", e_rhs)
-    assert e_rhs < rhs_bar(G, Q)
+    check_rhs(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G, Q, "c2_rhs_fp64")
     V = inputs.random_direction(3 * G.N, 21)
     ref = G.jvp(Q, V)
     got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V)))
-    record("c2_jvp_fp64", rel_fields(got, ref, G.N))
-    assert rel_fields(got, ref, G.N) < 1e-12
+    check_fields(got, ref, G, 1e-12, "c2_jvp_fp64")
     dfrsw.dfr_autotune(D, "fp32_jv")
     got32 = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
-    record("c2_jvp_fp32", rel_fields(got32, ref, G.N))
-    assert rel_fields(got32, ref, G.N) < 2e-5
+    check_fields(got32, ref, G, 2e-5, "c2_jvp_fp32")
 
 
 def test_c4_full_size_rhs_jvp_parity():
@@ -295,18 +283,14 @@ def test_c4_full_size_rhs_jvp_parity():
     G, D, Q = pair(C4)
     from paper_2101_05617_amd import dfrsw
     dfrsw.dfr_autotune(D, "fp64")
-    e_rhs = rel_fields(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G.rhs(Q), G.N)
-    record("c4_rhs_fp64", e_rhs)
-    assert e_rhs < rhs_bar(G, Q)
+    check_rhs(to_host(dfrsw.dfr_rhs(D, to_dev(Q))), G, Q, "c4_rhs_fp64")
     V = inputs.random_direction(3 * G.N, 41)
     ref = G.jvp(Q, V)
     got = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V)))
-    record("c4_jvp_fp64", rel_fields(got, ref, G.N))
-    assert rel_fields(got, ref, G.N) < 1e-12
+    check_fields(got, ref, G, 1e-12, "c4_jvp_fp64")
     dfrsw.dfr_autotune(D, "fp32_jv")
     got32 = to_host(dfrsw.dfr_jvp_complex_step(D, to_dev(Q), to_dev(V), 1e-20, "fp32_jv"))
-    record("c4_jvp_fp32", rel_fields(got32, ref, G.N))
-    assert rel_fields(got32, ref, G.N) < 2e-5
+    check_fields(got32, ref, G, 2e-5, "c4_jvp_fp32")
 
 
 def test_c1_full_size_epi5_parity():
@@ -324,7 +308,7 @@ def test_every_tile_shape_gives_the_same_result(ne, p):
     G, D, Q = pair(w)
     from paper_2101_05617_amd import dfrsw
     V = inputs.random_direction(3 * G.N, 77)
-    ref_f, ref_j = G.rhs(Q), G.jvp(Q, V)
+    ref_j = G.jvp(Q, V)
     q, v = to_dev(Q), to_dev(V)
     nn = (p + 1) ** 2
     tried = 0
@@ -334,17 +318,16 @@ def test_every_tile_shape_gives_the_same_result(ne, p):
                 continue
             dfrsw.dfr_set_tile(D, tx, ty)
             assert dfrsw.dfr_get_tile(D) == (tx, ty)
-            ef = rel_fields(to_host(dfrsw.dfr_rhs(D, q)), ref_f, G.N)
-            ej = rel_fields(to_host(dfrsw.dfr_jvp_complex_step(D, q, v)), ref_j, G.N)
-            record(f"tile_ne{ne}_p{p}_{tx}x{ty}", max(ef, ej))
-            assert ef < rhs_bar(G, Q) and ej < 1e-12, (tx, ty, ef, ej)
+            check_rhs(to_host(dfrsw.dfr_rhs(D, q)), G, Q, f"tile_rhs_ne{ne}_p{p}_{tx}x{ty}")
+            check_fields(to_host(dfrsw.dfr_jvp_complex_step(D, q, v)), ref_j, G, 1e-12,
+                         f"tile_jvp_ne{ne}_p{p}_{tx}x{ty}")
             tried += 1
     assert tried >= 3
     with pytest.raises(dfrsw.DfrError):
         dfrsw.dfr_set_tile(D, ne + 1, 1)
     tx, ty = dfrsw.dfr_autotune(D, "fp64")
     assert ne % tx == 0 and ne % ty == 0
-    assert rel_fields(to_host(dfrsw.dfr_jvp_complex_step(D, q, v)), ref_j, G.N) < 1e-12
+    check_fields(to_host(dfrsw.dfr_jvp_complex_step(D, q, v)), ref_j, G, 1e-12)
 
 
 def test_krylov_form_tiles_give_the_same_result():
@@ -362,20 +345,23 @@ def test_krylov_form_tiles_give_the_same_result():
                                          _kopts(1e-12, 32))
         assert (gst["n_substeps"], gst["n_rejected"], gst["n_matvec"]) == (rst.n_substeps, rst.n_rejected,
                                                                            rst.n_matvec)
-        err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
-        record(f"kiops_tile_{tx}x{ty}", err)
-        assert err <= 1e-11, (tx, ty, err)
+        check_krylov(to_host(got), ref, G, 1e-11, f"kiops_tile_{tx}x{ty}")
 
 
 def _h_error(got, ref, N):
     return np.linalg.norm(got[:N] - ref[:N]) / np.linalg.norm(ref[:N])
 
 
+def _h_max_error(got, ref, N):
+    return np.max(np.abs(got[:N] - ref[:N])) / np.max(np.abs(ref[:N]))
+
+
 def test_mixed_precision_epi6_jet_against_fp64_oracle():
     # complex-FP32 J v inside the FP64 Krylov / EPI6 machinery on the jet
     # workload (ne = 4, p = 6): four start-up steps and four EPI6 steps against
     # the FP64 oracle.  Bar: 1e-6 relative L2 in h (the accuracy the mixed
-    # form is held to), 1e-4 on every field.
+    # form is held to) and 1e-6 element-wise in h (against max h); 1e-4 on
+    # every field in every measure.
     w = small(C2, 4)
     G, D, Q = pair(w)
     from paper_2101_05617_amd import dfrsw
@@ -387,10 +373,11 @@ def test_mixed_precision_epi6_jet_against_fp64_oracle():
         E.step()
         dfrsw.epi_step(D, st, _kopts(w.tol, w.m_max))
         got = to_host(dfrsw.epi_get_state(st))
-        eh, ea = _h_error(got, E.q, G.N), rel_fields(got, E.q, G.N)
+        eh, ehm = _h_error(got, E.q, G.N), _h_max_error(got, E.q, G.N)
         record(f"mixed_epi6_jet_ne4_step{k + 1}_h", eh)
-        record(f"mixed_epi6_jet_ne4_step{k + 1}_all", ea)
-        assert eh < 1e-6 and ea < 1e-4, (k, eh, ea)
+        record(f"mixed_epi6_jet_ne4_step{k + 1}_h_max", ehm)
+        assert eh < 1e-6 and ehm < 1e-6, (k, eh, ehm)
+        check_fields(got, E.q, G, 1e-4, f"mixed_epi6_jet_ne4_step{k + 1}_all")
 
 
 def test_mixed_precision_kiops_against_fp64():
@@ -403,9 +390,7 @@ def test_mixed_precision_kiops_against_fp64():
     tau = w.dt_nd
     ref, _ = okiops.kiops(tau, lambda v: G.jvp(Q, v), [None, F], tol=1e-10, m_max=64)
     got, _ = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(1e-10, 64), w.eps, "fp32_jv")
-    err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
-    record("mixed_kiops_jet_ne3", err)
-    assert err < 1e-5
+    check_krylov(to_host(got), ref, G, 1e-5, "mixed_kiops_jet_ne3")
 
 
 def test_c2_full_size_kiops_parity():
@@ -422,15 +407,11 @@ def test_c2_full_size_kiops_parity():
     assert rst.n_rejected > 0
     got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(C2.tol, C2.m_max))
     assert (gst["n_substeps"], gst["n_rejected"], gst["n_matvec"]) == (rst.n_substeps, rst.n_rejected, rst.n_matvec)
-    err = np.linalg.norm(to_host(got) - ref) / np.linalg.norm(ref)
-    record("kiops_c2_full_fp64", err)
-    assert err <= 1e-11
+    check_krylov(to_host(got), ref, G, 1e-11, "kiops_c2_full_fp64")
     dfrsw.dfr_autotune(D, "fp32_jv")
     got32, _ = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F)], _kopts(C2.tol, C2.m_max), C2.eps,
                                      "fp32_jv")
-    err32 = np.linalg.norm(to_host(got32) - ref) / np.linalg.norm(ref)
-    record("kiops_c2_full_fp32_jv", err32)
-    assert err32 < 1e-5
+    check_krylov(to_host(got32), ref, G, 1e-5, "kiops_c2_full_fp32_jv")
 
 
 def test_ensemble_forms_match_members_run_alone():
@@ -455,17 +436,15 @@ def test_ensemble_forms_match_members_run_alone():
     for k, w in enumerate(ws):
         a, b, c = ref.state(k), bat.state(k), con.state(k)
         assert np.array_equal(a, c), (k, np.abs(a - c).max())
-        eb = rel_fields(b, a, len(a) // 3)
-        record(f"ensemble_batched_vs_single_member{k}", eb)
         # same kernels, tiles, reduction orders and EPI combinations
-        assert np.array_equal(a, b), (k, eb)
+        assert np.array_equal(a, b), (k, np.abs(a - b).max())
         G = oracle.OracleGrid(w.ne, w.ns, *w.constants())
         Q, _ = inputs.initial_state(w, *frames[k])
         E = oepi.EPI(G.rhs, lambda q, v: G.jvp(q, v), w.order, w.dt_nd, Q, startup_substeps=w.startup_substeps,
                      kiops_opts=dict(tol=1e-10, m_max=24))
         for _ in range(4):
             E.step()
-        assert rel_fields(b, E.q, G.N) < 1e-11
+        check_krylov(b, E.q, G, 1e-11, f"ensemble_member{k}_vs_oracle")
     with pytest.raises(dfrsw.DfrError):
         dfrsw.epi_step_concurrent([con.grids[0], con.grids[0]], [con.states[0], con.states[0]], opts, 2)
     for e in (ref, bat, con):
