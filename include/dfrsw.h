@@ -197,6 +197,22 @@ int dfr_diagnostics(dfr_ctx *ctx, const double *q, double *zeta, double *fcor, d
 int dfr_jvp_complex_step(dfr_ctx *ctx, const double *q, const double *v, double eps,
                          dfr_precision prec, double *jv);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * product as dfr_jvp_complex_step, with the same kernels and results, that
+ * allocates nothing and creates no runtime objects.  The complex-FP32 form
+ * keeps its FP32 copy of q in a device array of 16 MiB compiled into the
+ * library (one per device, held until the process ends) instead of context
+ * memory, so it serves grids of at most 16 MiB / 12 B = 1,398,101 nodes
+ * (DFR_E_INVAL beyond, the message stating the limit; DFR_FP64 has no such
+ * limit and uses no scratch).  Every call on a device shares that device's
+ * array: calls that overlap on one device (several streams or threads)
+ * race and give undefined results; calls ordered on one stream do not.
+ * The context's kernel timing (dfr_timing_enable) does not cover these
+ * calls.  Arguments and errors as for dfr_jvp_complex_step. */
+int dfr_jvp_complex_step_noalloc(dfr_ctx *ctx, const double *q, const double *v, double eps,
+                                 dfr_precision prec, double *jv);
+
 /* w = sum_{k=0}^{n_phi} tau_out^k phi_k(tau_out J(q_lin)) b_k   (Eq. 29)
  * with phi_k of Eq. (26) and J(q_lin) applied by complex-step products
  * (dfr_jvp_complex_step with the given eps and prec).  b: host array of

@@ -631,6 +631,7 @@ int dfr_create(const dfr_grid_desc *d, void *stream, dfr_ctx **out) {
   }
   int rc = setup_geometry(c, d->hB);
   if (!rc) rc = alloc_workspace(c);
+  if (!rc) rc = scratch_init(c.device);
   if (rc) {
     free_ctx(c);
     delete h;
@@ -694,6 +695,7 @@ int dfr_create_ode(int problem, int n, void *stream, dfr_ctx **out) {
   }
   c.ga.err_flag = c.d_err;
   if (!rc) rc = alloc_workspace(c);
+  if (!rc) rc = scratch_init(c.device);
   if (rc) {
     free_ctx(c);
     delete h;

@@ -22,6 +22,11 @@ constexpr int BLOCK = 256;       // threads per block of the DFR and vector kern
 #define DFR_EXPM_BLOCK 1024
 #endif
 constexpr int EXPM_BLOCK = DFR_EXPM_BLOCK;  // one workgroup of the small exponential (a multiple of 64)
+#ifndef DFR_NOALLOC_SCRATCH_BYTES
+#define DFR_NOALLOC_SCRATCH_BYTES (16u << 20)   // device scratch array of dfr_jvp_complex_step_noalloc
+#endif
+// look up the device address of that array for `device` (current), once
+int scratch_init(int device);
 
 void set_error(const std::string &msg);
 

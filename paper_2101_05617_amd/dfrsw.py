@@ -78,6 +78,7 @@ def lib():
             "dfr_sync": (i, [vp]),
             "dfr_rhs": (i, [vp, vp, vp]),
             "dfr_jvp_complex_step": (i, [vp, vp, vp, d, i, vp]),
+            "dfr_jvp_complex_step_noalloc": (i, [vp, vp, vp, d, i, vp]),
             "kiops_phi_apply": (i, [vp, vp, d, i, ctypes.POINTER(vp), ctypes.POINTER(KiopsOpts), d, i, vp,
                                     ctypes.POINTER(KiopsStats)]),
             "epi_create": (i, [vp, i, d, i, vp, d, i, ctypes.POINTER(vp)]),
@@ -121,7 +122,7 @@ def lib():
 
 def exported_symbols():
     return ["dfr_create", "dfr_destroy", "dfr_num_nodes", "dfr_create_ode", "dfr_num_unknowns", "dfr_node_frames", "dfr_sync", "dfr_rhs",
-            "dfr_jvp_complex_step", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
+            "dfr_jvp_complex_step", "dfr_jvp_complex_step_noalloc", "kiops_phi_apply", "epi_create", "epi_step", "epi_get_state",
             "epi_num_steps", "epi_destroy", "epi_save", "epi_load", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
             "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_diagnostics", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
@@ -224,6 +225,12 @@ def dfr_rhs(g: Grid, q, dqdt=None):
 def dfr_jvp_complex_step(g: Grid, q, v, eps=1e-150, prec="fp64", jv=None):
     jv = g.empty() if jv is None else jv
     _check(lib().dfr_jvp_complex_step(g.handle, _dev(q), _dev(v), float(eps), _PREC[prec], _dev(jv)))
+    return jv
+
+
+def dfr_jvp_complex_step_noalloc(g: Grid, q, v, jv, eps=1e-150, prec="fp64"):
+    """The allocation-free form: jv must be given (the call allocates nothing)."""
+    _check(lib().dfr_jvp_complex_step_noalloc(g.handle, _dev(q), _dev(v), float(eps), _PREC[prec], _dev(jv)))
     return jv
 
 
