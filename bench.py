@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -42,11 +43,21 @@ def jv_bytes_per_node(form):
     return {"fp64": 72, "fp32_jv": 12 + 24 + 24, "fp32_jv_basis32": 12 + 24 + 24}[form]
 
 
-def arnoldi_jv_bytes_per_node(p, iop=2):
+def arnoldi_jv_bytes_per_node(p, iop=2, prec="fp64"):
     # the J*v kernel as launched inside KIOPS additionally reads the p scaled
-    # b-columns of the augmented operator and the previous basis vector for the
-    # fused inner products: 72 + 24 p + 24 (iop = 2)
-    return 72 + 24 * p + (24 if iop >= 2 else 0)
+    # b-columns of the augmented operator (FP64) and the previous basis
+    # vector for the fused inner products: 72 + 24 p + 24 in FP64 (iop = 2);
+    # with FP32 products on an FP64 basis the state is read as an FP32 copy
+    # (60 + 24 p + 24); with an FP32 basis the basis vectors read and written
+    # are FP32 too (36 + 24 p + 12)
+    if prec == "fp64":
+        return 72 + 24 * p + (24 if iop >= 2 else 0)
+    if prec == "fp32_jv":
+        return 60 + 24 * p + (24 if iop >= 2 else 0)
+    return 36 + 24 * p + (12 if iop >= 2 else 0)
+
+
+EPI_M = {2: 1, 3: 2, 4: 3, 5: 4, 6: 4}   # phi-columns b_1..b_M of an EPI step
 
 
 def time_jv(g, q, vs, outs, eps, prec, reps):
@@ -102,13 +113,16 @@ def summarize_profile(args):
     for r in rows[:12]:
         lines.append(f"{r['Name'][:90]:90s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['TotalDurationNs']) / 1e6:9.3f} {float(r['Percentage']):6.2f}")
-    sel = [r for r in rows if args.kernel in r["Name"]]
+    sel = [r for r in rows if re.search(args.kernel, r["Name"])]
     if sel:
-        lines.append(f"selected kernel: {sel[0]['Name'][:120]}")
-        lines.append(f"selected_avg_us (all launches, tuning included): {float(sel[0]['AverageNs']) / 1e3:.3f} "
-                     f"over {sel[0]['Calls']} launches")
+        calls = sum(int(r["Calls"]) for r in sel)
+        total_ns = sum(float(r["TotalDurationNs"]) for r in sel)
+        for r in sel:
+            lines.append(f"selected kernel: {r['Name'][:120]}")
+        lines.append(f"selected_avg_us (all launches, tuning included): {total_ns / calls / 1e3:.3f} "
+                     f"over {calls} launches")
         tr = [r for r in csv.DictReader(open(os.path.join(args.summarize_profile, "run_kernel_trace.csv")))
-              if args.kernel in r["Kernel_Name"]]
+              if re.search(args.kernel, r["Kernel_Name"])]
         tr.sort(key=lambda r: int(r["Start_Timestamp"]))
         last = tr[-args.last:] if args.last else tr
         d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in last]
@@ -120,7 +134,8 @@ def summarize_profile(args):
         cc = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
         cal = max(float(r["Counter_Value"]) for r in cc
                   if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"])
-        vals = [float(r["Counter_Value"]) for r in cc if r["Counter_Name"] == counter and args.kernel in r["Kernel_Name"]]
+        vals = [float(r["Counter_Value"]) for r in cc
+                if r["Counter_Name"] == counter and re.search(args.kernel, r["Kernel_Name"])]
         if not vals:
             lines.append(f"{counter}: no dispatch of a kernel matching {args.kernel!r}")
             continue
@@ -139,7 +154,7 @@ def summarize_profile(args):
     util = {}
     for d in args.counters or []:
         cc = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
-              if args.kernel in r["Kernel_Name"]]
+              if re.search(args.kernel, r["Kernel_Name"])]
         by = {}
         for r in cc:
             by.setdefault(r["Counter_Name"], []).append((int(r.get("Dispatch_Id") or 0), float(r["Counter_Value"])))
@@ -286,52 +301,89 @@ def mixed_study(steps):
                 "rel_l2_error_h_fp64": e64_h, "rel_l2_error_max_field_fp64": e64_all}}
 
 
-def ensemble_study(n_members, steps, n_workers):
-    """The ensemble workload: `n_members` members (ne in {8..40}, p in {4,5,6},
-    EPI4, dt 900 s, tol 1e-10, m <= 32).  Plain FP64 with the members one
-    after another, against the batched form (one launch per operation for all
-    members) in FP64 and with complex-FP32 products, at the same tolerance and,
-    for the comparison at the stated error, at a tolerance of 1e-6.  Every form runs the EPI2
-    start-up steps untimed, then `steps` timed EPI4 steps; the error is the
-    relative L2 difference in h from the plain FP64 run, all members together
-    and the worst member."""
+# the ensemble forms compared in the headline: (name, precision, form, KIOPS
+# tolerance).  The first is the headline's mixed batched form at the stated
+# error (FP32 products, FP32 Krylov basis; inner products, norms, Hessenberg,
+# exponential and EPI update FP64; tolerance one decade above the relative
+# noise of a complex-FP32 product); the last is plain FP64, one member after
+# another, the reference of every error.
+ENSEMBLE_FORMS = [
+    ("fp32_jv_basis32_batched_tol1e-6", "fp32_jv_basis32", "batched", 1e-6),
+    ("fp32_jv_batched_tol1e-6", "fp32_jv", "batched", 1e-6),
+    ("fp64_batched_tol1e-6", "fp64", "batched", 1e-6),
+    ("fp64_sequential_tol1e-6", "fp64", "sequential", 1e-6),
+    ("fp32_jv_batched", "fp32_jv", "batched", 1e-10),
+    ("fp64_batched", "fp64", "batched", 1e-10),
+    ("fp64_sequential", "fp64", "sequential", 1e-10),
+]
+
+
+def ensemble_headline(args, forms=None):
+    """The ensemble workload (64 members, ne in {8..40}, p in {4,5,6}, EPI4,
+    dt 900 s, m <= 32) in every form of ENSEMBLE_FORMS: W untimed steps (the
+    EPI2 start-up steps first), K timed steps of all members, then untimed
+    steps to the end of the simulated day (96 steps), whose states give the
+    error in h of each form against plain FP64 sequential at tol 1e-10.  The
+    headline form's timed steps carry HIP-event timing of every batched
+    launch (the roofline of its Krylov-form product); its next K steps run
+    without it, for comparison."""
     import numpy as np
     import torch
 
     from paper_2101_05617_amd import dfrsw, inputs
     from paper_2101_05617_amd.ensemble import Ensemble
-    members = inputs.ensemble_members(n_members)
+    members = inputs.ensemble_members(args.ensemble_members)
     w0 = members[0]
-    opts = dfrsw.kiops_opts(tol=w0.tol, m_max=w0.m_max)
-    # the stated-error comparison: KIOPS tolerance one decade above the
-    # relative noise of a complex-FP32 product (about 1e-7)
-    tol_matched = 1e-6
-    opts_matched = dfrsw.kiops_opts(tol=tol_matched, m_max=w0.m_max)
-    n_start = w0.order - 2
+    W, K = args.warmup, args.steps
+    day = int(round(86400.0 / w0.dt_s))
     total_nodes = sum(w.n_nodes for w in members)
-    res = {}
-    finals = {}
-    for name, prec, form, opts in (("fp64_sequential", "fp64", "sequential", opts),
-                                   ("fp64_batched", "fp64", "batched", opts),
-                                   ("fp32_jv_batched", "fp32_jv", "batched", opts),
-                                   ("fp32_jv_batched_tol1e-6", "fp32_jv", "batched", opts_matched),
-                                   ("fp32_jv_basis32_batched_tol1e-6", "fp32_jv_basis32", "batched", opts_matched),
-                                   ("fp64_batched_tol1e-6", "fp64", "batched", opts_matched)):
+    forms = forms or ENSEMBLE_FORMS
+    res, finals = {}, {}
+    for name, prec, form, tol in forms:
+        opts = dfrsw.kiops_opts(tol=tol, m_max=w0.m_max)
         ens = Ensemble(members, prec=prec, form=form)
-        for _ in range(n_start):
-            ens.step(opts, n_workers)
+        for _ in range(W):
+            ens.step(opts)
+        headline = name == forms[0][0]
+        if headline and form == "batched":
+            dfrsw.dfr_ensemble_timing_enable(ens.eg, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nmv = 0
-        for _ in range(steps):
-            st = ens.step(opts, n_workers)
-            nmv += sum(x["n_matvec"] for x in st)
+        agg = {"n_matvec": 0, "n_substeps": 0, "n_rejected": 0, "n_expm": 0}
+        for _ in range(K):
+            for st in ens.step(opts):
+                for k in agg:
+                    agg[k] += st[k]
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        finals[name] = [ens.state(k) for k in range(len(members))]
-        res[name] = {"member_steps_per_s": n_members * steps / dt, "wall_s": dt,
-                     "jv_per_member_step": nmv / (n_members * steps)}
-        log(f"ensemble {name}: {n_members} x {steps} steps in {dt:.2f}s")
+        wall = time.perf_counter() - t0
+        r = {"member_steps_per_s": len(members) * K / wall, "wall_s": wall, "ms_per_step": 1e3 * wall / K,
+             "jv_per_member_step": agg["n_matvec"] / (len(members) * K),
+             "expm_per_member_step": agg["n_expm"] / (len(members) * K),
+             "substeps_per_member_step": agg["n_substeps"] / (len(members) * K),
+             "rejections_per_member_step": agg["n_rejected"] / (len(members) * K), "kiops_tol": tol}
+        done = W + K
+        if headline and form == "batched":
+            r["kernels"] = {k: dfrsw.dfr_ensemble_timing_read(ens.eg, k) for k in dfrsw.KERNEL_KINDS}
+            dfrsw.dfr_ensemble_timing_enable(ens.eg, False)
+            if not args.headline_only:
+                n2 = min(K, max(0, day - done))
+                if n2:
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    for _ in range(n2):
+                        ens.step(opts)
+                    torch.cuda.synchronize()
+                    r["member_steps_per_s_without_events"] = len(members) * n2 / (time.perf_counter() - t1)
+                    done += n2
+        if not args.headline_only:
+            for _ in range(max(0, day - done)):
+                ens.step(opts)
+            done = max(done, day)
+            finals[name] = [ens.state(k) for k in range(len(members))]
+        r["steps_at_error_check"] = done
+        res[name] = r
+        log(f"ensemble {name}: {len(members)} members x {K} timed steps in {wall:.3f}s "
+            f"({r['member_steps_per_s']:.0f} member steps/s, {r['jv_per_member_step']:.1f} J*v per member step)")
         ens.close()
         del ens
         torch.cuda.synchronize()
@@ -344,34 +396,25 @@ def ensemble_study(n_members, steps, n_workers):
             num += e2
             den += r2
             worst = max(worst, (e2 / r2) ** 0.5)
-        return (num / den) ** 0.5, worst
-    e32, w32 = err("fp32_jv_batched")
-    e64, w64 = err("fp64_batched")
-    e32m, w32m = err("fp32_jv_batched_tol1e-6")
-    e32b, w32b = err("fp32_jv_basis32_batched_tol1e-6")
-    e64m, w64m = err("fp64_batched_tol1e-6")
-    base = res["fp64_sequential"]["member_steps_per_s"]
-    return {"workload": f"{n_members} members, ne in {{8..40}}, p in {{4,5,6}} ({total_nodes} nodes in all), EPI4, "
-                        f"dt 900 s, tol {w0.tol:g}, m<={w0.m_max}; {n_start} start-up steps untimed, {steps} timed",
-            **res,
-            "speedup_fp32_batched_over_fp64_sequential": res["fp32_jv_batched"]["member_steps_per_s"] / base,
-            "speedup_fp64_batched_over_fp64_sequential": res["fp64_batched"]["member_steps_per_s"] / base,
-            "rel_l2_error_h_fp32_batched": {"all_members": e32, "worst_member": w32},
-            "rel_l2_error_h_fp64_batched": {"all_members": e64, "worst_member": w64},
-            "at_stated_error": {
-                "note": f"KIOPS tol {tol_matched:g} for the batched forms (one decade above the complex-FP32 "
-                        "product's relative noise); error and speed-up against plain FP64 sequential at tol "
-                        f"{w0.tol:g}; target error in h after one simulated day <= 1e-6",
-                "speedup_fp32_batched_over_fp64_sequential":
-                    res["fp32_jv_batched_tol1e-6"]["member_steps_per_s"] / base,
-                "speedup_fp64_batched_over_fp64_sequential":
-                    res["fp64_batched_tol1e-6"]["member_steps_per_s"] / base,
-                "speedup_fp32_basis32_batched_over_fp64_sequential":
-                    res["fp32_jv_basis32_batched_tol1e-6"]["member_steps_per_s"] / base,
-                "rel_l2_error_h_fp32_basis32_batched": {"all_members": e32b, "worst_member": w32b},
-                "rel_l2_error_h_fp32_batched": {"all_members": e32m, "worst_member": w32m},
-                "rel_l2_error_h_fp64_batched": {"all_members": e64m, "worst_member": w64m}},
-            "simulated_days": (n_start + steps) * w0.dt_s / 86400.0}
+        return {"all_members": (num / den) ** 0.5, "worst_member": worst}
+    if "fp64_sequential" in finals:
+        for name in finals:
+            res[name]["rel_l2_error_h_vs_fp64_sequential"] = err(name)
+    out = {"members": len(members), "nodes_all_members": total_nodes, "forms": res,
+           "simulated_days_at_error_check": (res[forms[0][0]]["steps_at_error_check"]) * w0.dt_s / 86400.0,
+           "day_steps": day}
+    if "fp64_sequential" in res:
+        base = res["fp64_sequential"]["member_steps_per_s"]
+        out["speedup_over_fp64_sequential"] = {n: v["member_steps_per_s"] / base for n, v in res.items()}
+    if "fp64_sequential_tol1e-6" in res:
+        base6 = res["fp64_sequential_tol1e-6"]["member_steps_per_s"]
+        out["speedup_over_fp64_sequential_tol1e-6"] = {n: v["member_steps_per_s"] / base6 for n, v in res.items()}
+    if "fp64_batched_tol1e-6" in res:
+        b6 = res["fp64_batched_tol1e-6"]["member_steps_per_s"]
+        out["precision_share"] = {
+            "note": "at tol 1e-6: each batched form over FP64 batched (what the precision adds to batching)",
+            **{n: v["member_steps_per_s"] / b6 for n, v in res.items() if "batched_tol1e-6" in n}}
+    return out
 
 
 def c4_study(steps, reps):
@@ -688,6 +731,38 @@ def cpu_baseline_leg(workload_name):
     return out
 
 
+def cpu_baseline_ensemble(_name=None):
+    """Time the oracle on the six smallest members of the ensemble: each
+    member's EPI2 start-up steps untimed, then four EPI4 steps timed (KIOPS
+    tol 1e-10, the plain method's)."""
+    import oracle
+    from oracle import epi as oepi
+    from paper_2101_05617_amd import inputs
+    members = inputs.ensemble_members(64)
+    pick = sorted(range(len(members)), key=lambda k: (members[k].n_nodes, k))[:6]
+    wall = 0.0
+    steps = nmv = 0
+    for k in pick:
+        w = members[k]
+        G = oracle.OracleGrid(w.ne, w.ns, *w.constants())
+        P, B1, B2 = G.node_frames()
+        Q, _ = inputs.initial_state(w, P, B1, B2)
+        E = oepi.EPI(G.rhs, lambda a, b, G=G: G.jvp(a, b), w.order, w.dt_nd, Q,
+                     startup_substeps=w.startup_substeps, kiops_opts=dict(tol=w.tol, m_max=w.m_max))
+        for _ in range(E.P):
+            E.step()
+        n0 = len(E.stats)
+        t0 = time.perf_counter()
+        for _ in range(4):
+            E.step()
+        wall += time.perf_counter() - t0
+        steps += 4
+        nmv += sum(x.n_matvec for x in E.stats[n0:])
+        del G, E
+    return {"member_steps": steps, "wall_s": wall, "n_matvec": nmv,
+            "members": [f"member {k}: ne={members[k].ne}, p={members[k].p}" for k in pick]}
+
+
 def jv_only(w, args):
     """Time the plain J*v kernel alone on workload w (buffers rotated past the
     last-level cache); prints one JSON line."""
@@ -713,70 +788,148 @@ def jv_only(w, args):
     return 0
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--workload", default="c1_ne30_p5")
-    ap.add_argument("--jv-reps", type=int, default=200)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-c2", action="store_true", help="skip the ne=60, p=6 J*v roofline figures")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the ne=60, p=6 mixed-precision EPI6 day")
-    ap.add_argument("--mixed-steps", type=int, default=72)
-    ap.add_argument("--no-c4", action="store_true", help="skip the ne=120, p=6 mountain figures")
-    ap.add_argument("--c4-steps", type=int, default=2)
-    ap.add_argument("--no-ensemble", action="store_true", help="skip the 64-member ensemble comparison")
-    ap.add_argument("--no-ausm", action="store_true", help="skip the AUSM-flux figures")
-    ap.add_argument("--no-diagnostics", action="store_true", help="skip the conservation-diagnostics figures")
-    ap.add_argument("--no-large-dt", action="store_true", help="skip the dt = 4 h figures")
-    ap.add_argument("--no-ode", action="store_true", help="skip the Sec. 5.1 test problems")
-    ap.add_argument("--ensemble-members", type=int, default=64)
-    ap.add_argument("--ensemble-steps", type=int, default=94,
-                    help="timed EPI4 steps after the two start-up steps (94: one simulated day in all)")
-    ap.add_argument("--ensemble-workers", type=int, default=8)
-    ap.add_argument("--headline-only", action="store_true",
-                    help="only the headline EPI run of --workload and its J*v figures (for profiling)")
-    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--jv-only", action="store_true",
-                    help="only time the plain complex-step J*v kernel of --workload (for profiling)")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_jv"], help="precision of --jv-only")
-    ap.add_argument("--summarize-profile", metavar="DIR",
-                    help="print a summary of rocprofv3 output in DIR (kernel trace) and exit")
-    ap.add_argument("--fetch", metavar="DIR", help="with --summarize-profile: a FETCH_SIZE pass")
-    ap.add_argument("--write", metavar="DIR", help="with --summarize-profile: a WRITE_SIZE pass")
-    ap.add_argument("--counters", metavar="DIR", action="append",
-                    help="with --summarize-profile: a further counter pass (repeatable)")
-    ap.add_argument("--kernel", default="true, true>", help="with --summarize-profile: kernel name substring")
-    ap.add_argument("--last", type=int, default=0,
-                    help="with --summarize-profile: average over the last N launches (the timed region)")
-    args = ap.parse_args()
+def run_cpu_legs(workload):
+    """The oracle leg of `workload` in a child process, with one thread and
+    with all of this host's share; {threads: result}."""
+    legs = {}
+    n_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    for nt in sorted({1, n_all}):
+        env = dict(os.environ, OMP_NUM_THREADS=str(nt), OPENBLAS_NUM_THREADS=str(nt), MKL_NUM_THREADS=str(nt))
+        log(f"cpu baseline: oracle ({workload}), {nt} thread(s)")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                            "--workload", workload], capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode != 0:
+            log("cpu baseline failed: " + r.stderr[-2000:])
+            break
+        legs[nt] = json.loads(r.stdout.strip().splitlines()[-1])
+    return legs, n_all
 
-    if args.summarize_profile:
-        return summarize_profile(args)
-    if args.headline_only:
-        args.no_c2 = args.no_mixed = args.no_c4 = args.no_ensemble = args.no_ausm = args.no_diagnostics = \
-            args.no_large_dt = args.no_ode = args.no_cpu_baseline = True
 
-    if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline_leg(args.workload)), flush=True)
-        return 0
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(the multi-GPU design is described, not built); use --gpus 1", file=sys.stderr)
-        return 2
+def cpu_baseline_entry(args, ens):
+    """The cpu_baseline object: the oracle on the headline's workload (for the
+    ensemble, its six smallest members) and, beside it, the single-grid leg
+    (one EPI5 step at ne = 30, p = 5 and the product alone at the three
+    largest grids)."""
+    from paper_2101_05617_amd import inputs
+    out = None
+    if ens:
+        legs, n_all = run_cpu_legs("c3_ensemble")
+        if 1 in legs:
+            cb = legs[1]
+            out = {"value": cb["member_steps"] / cb["wall_s"], "unit": "member EPI steps/s", "cores": 1,
+                   "kind": "oracle",
+                   "sample": f"the six smallest ensemble members ({'; '.join(cb['members'])}): each one's two "
+                             f"EPI2 start-up steps untimed, then four EPI4 steps timed ({cb['n_matvec']} J*v in "
+                             f"all), KIOPS tol 1e-10, FP64",
+                   "cpu": cpu_model()}
+            if n_all in legs and n_all != 1:
+                cm = legs[n_all]
+                out["all_threads"] = {"value": cm["member_steps"] / cm["wall_s"], "cores": n_all}
+    w = inputs.WORKLOADS["c1_ne30_p5" if ens else args.workload]
+    legs, n_all = run_cpu_legs(w.name)
+    if 1 in legs:
+        cb = legs[1]
+        sg = {"value": 1.0 / cb["step_s"], "unit": "EPI steps/s", "cores": 1, "kind": "oracle",
+              "sample": f"one EPI{w.order} step of {w.name} after {w.order - 2} untimed EPI2 start-up steps "
+                        f"({cb['n_matvec']} J*v); J*v alone {cb['jv_s'] * 1e3:.1f} ms",
+              "jv_per_s": 1.0 / cb["jv_s"], "jv_per_s_c2_ne60_p6": 1.0 / cb["jv_s_c2"],
+              "jv_per_s_c4_ne120_p6": 1.0 / cb["jv_s_c4"], "cpu": cpu_model()}
+        if n_all in legs and n_all != 1:
+            cm = legs[n_all]
+            sg["all_threads"] = {"value": 1.0 / cm["step_s"], "cores": n_all, "jv_per_s": 1.0 / cm["jv_s"],
+                                 "jv_per_s_c2_ne60_p6": 1.0 / cm["jv_s_c2"],
+                                 "jv_per_s_c4_ne120_p6": 1.0 / cm["jv_s_c4"]}
+        if out is None:
+            out = sg
+        else:
+            out["single_grid"] = sg
+    return out
 
-    import numpy as np
+
+def ensemble_headline_line(args):
+    """The JSON line of the ensemble headline: member EPI steps/s of the mixed
+    batched form at the stated error, with the roofline of its batched
+    Krylov-form product timed live in its timed region."""
+    from paper_2101_05617_amd import inputs
+    forms = ENSEMBLE_FORMS[:1] if args.headline_only else ENSEMBLE_FORMS
+    e = ensemble_headline(args, forms)
+    name, prec = forms[0][0], forms[0][1]
+    h = e["forms"][name]
+    members = inputs.ensemble_members(args.ensemble_members)
+    w0 = members[0]
+    M = EPI_M[w0.order]
+    ms, n_launch, nodes = h["kernels"]["jv_arnoldi"]
+    bpn = arnoldi_jv_bytes_per_node(M, 2, prec)
+    achieved = bpn * nodes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    prof = "dfr_kernel_batch_krylov_c3_ensemble.txt"
+    kernel_ms_total = sum(v[0] for v in h["kernels"].values())
+    out = {
+        "metric": METRIC,
+        "value": h["member_steps_per_s"],
+        "unit": "member EPI steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 complex-step products, f64 Krylov/expm/update",
+        "data": "synthetic",
+        "config": {"workload": f"c3_ensemble: {e['members']} independent members ({e['nodes_all_members']} nodes "
+                               f"in all), ne in {{8,12,16,24,32,40}}, p in {{4,5,6}}, EPI4, dt={w0.dt_s:g}s, "
+                               f"m<={w0.m_max}; mixed batched form: complex-FP32 J*v and FP32 Krylov basis, FP64 "
+                               f"inner products, Hessenberg, exponential and update, KIOPS tol {forms[0][3]:g}; "
+                               f"one step = one EPI step of every member",
+                   "members": e["members"], "nodes": e["nodes_all_members"], "order": w0.order,
+                   "dt_s": w0.dt_s, "kiops_tol": forms[0][3], "form": name},
+        "sim_days_per_wall_hour": (h["member_steps_per_s"] / e["members"]) * w0.dt_s / 86400.0 * 3600.0,
+        "jv_in_step_per_s": h["member_steps_per_s"] * h["jv_per_member_step"],
+        "kiops_per_member_step": {k: h[k] for k in ("jv_per_member_step", "substeps_per_member_step",
+                                                     "rejections_per_member_step", "expm_per_member_step")},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in h["kernels"].items()},
+        "kernel_launches_per_step": {k: v[1] / args.steps for k, v in h["kernels"].items()},
+        "gpu_busy_fraction": kernel_ms_total / (h["wall_s"] * 1e3),
+        "roofline": {
+            "kernel": "dfr_kernel_batch: batched complex-FP32 J*v with the fused Arnoldi epilogue, FP32 basis "
+                      "(every member's tiles in one launch per p group)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(prof),
+            "bytes_per_node": bpn, "avg_launch_us": ms / max(n_launch, 1) * 1e3, "launches": n_launch,
+            "nodes_per_launch": nodes / max(n_launch, 1),
+            "algorithmic_bytes_per_launch": bpn * nodes / max(n_launch, 1),
+            "utilisation": utilisation_summary(prof, ms / max(n_launch, 1) * 1e3),
+        },
+        "ensemble_c3": e,
+    }
+    if "member_steps_per_s_without_events" in h:
+        out["member_steps_per_s_without_events"] = h["member_steps_per_s_without_events"]
+    if not args.headline_only:
+        f = e["forms"]
+        out["at_stated_error"] = {
+            "target": ">= 2x plain FP64 EPI steps/s at <= 1e-6 relative L2 error in h after one simulated day",
+            "rel_l2_error_h_vs_fp64_sequential_tol1e-10": f[name]["rel_l2_error_h_vs_fp64_sequential"],
+            "speedup_over_fp64_sequential_tol1e-10": e["speedup_over_fp64_sequential"][name],
+            "speedup_over_fp64_sequential_tol1e-6": e["speedup_over_fp64_sequential_tol1e-6"][name],
+            "speedup_fp64_batched_tol1e-6_over_fp64_sequential_tol1e-6":
+                e["speedup_over_fp64_sequential_tol1e-6"]["fp64_batched_tol1e-6"],
+            "error_reference": "plain FP64 member by member at KIOPS tol 1e-10 on the GPU, itself checked against "
+                               "the FP64 oracle (tests: batched and sequential members bit for bit, the smallest "
+                               "members over the whole day against the oracle)",
+        }
+    return out
+
+
+def single_grid_run(w, steps, warmup, jv_reps):
+    """EPI steps of one grid in plain FP64 (warmup untimed, then `steps`
+    timed), the same number of steps again with every kernel timed by HIP
+    events on the library's stream, and the plain J*v kernel alone; the
+    result carries the roofline of the Krylov-form product."""
     import torch
 
     from paper_2101_05617_amd import dfrsw, inputs
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
-    w = inputs.WORKLOADS[args.workload]
-    log(f"workload {w.name}: ne={w.ne} p={w.p} N={w.n_nodes} EPI{w.order} dt={w.dt_s}s tol={w.tol} m<={w.m_max}")
-    if args.jv_only:
-        return jv_only(w, args)
-
+    args = argparse.Namespace(steps=steps, warmup=warmup, jv_reps=jv_reps)
     g = dfrsw.Grid(w.ne, w.p, *w.constants())
     tile = dfrsw.dfr_autotune(g, "fp64")
     tile_kr = dfrsw.dfr_get_krylov_tile(g)
@@ -839,18 +992,10 @@ def main():
     sim_days_per_hour = (args.steps * w.dt_s / 86400.0) / (wall / 3600.0)
 
     out = {
-        "metric": METRIC,
-        "value": steps_per_s,
-        "unit": "EPI steps/s",
-        "n_gpus": 1,
+        "steps_per_s": steps_per_s,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
         "config": {"workload": f"{w.name}: rotated cubed sphere ne={w.ne}, p={w.p} ({N} nodes, {3 * N} unknowns), "
                                f"EPI{w.order}, dt={w.dt_s:g}s, KIOPS tol={w.tol:g}, m<={w.m_max}, plain FP64",
                    "ne": w.ne, "p": w.p, "nodes": N, "order": w.order, "dt_s": w.dt_s,
@@ -891,6 +1036,93 @@ def main():
     del st, vs, outs, q, q0
     torch.cuda.synchronize()
     calibration_copy()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 94 for the ensemble, one simulated day with the start-up; 8 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 2 for the ensemble, its EPI2 start-up; 4 otherwise)")
+    ap.add_argument("--workload", default="c3_ensemble",
+                    help="c3_ensemble (the headline) or a single-grid workload of inputs.WORKLOADS")
+    ap.add_argument("--jv-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="skip the ne=30, p=5 EPI5 run (with the ensemble headline)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the ne=60, p=6 J*v roofline figures")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the ne=60, p=6 mixed-precision EPI6 day")
+    ap.add_argument("--mixed-steps", type=int, default=72)
+    ap.add_argument("--no-c4", action="store_true", help="skip the ne=120, p=6 mountain figures")
+    ap.add_argument("--c4-steps", type=int, default=2)
+    ap.add_argument("--no-ausm", action="store_true", help="skip the AUSM-flux figures")
+    ap.add_argument("--no-diagnostics", action="store_true", help="skip the conservation-diagnostics figures")
+    ap.add_argument("--no-large-dt", action="store_true", help="skip the dt = 4 h figures")
+    ap.add_argument("--no-ode", action="store_true", help="skip the Sec. 5.1 test problems")
+    ap.add_argument("--ensemble-members", type=int, default=64)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline run (for the ensemble: its headline form, no error check; for profiling)")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--jv-only", action="store_true",
+                    help="only time the plain complex-step J*v kernel of --workload (for profiling)")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_jv"], help="precision of --jv-only")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print a summary of rocprofv3 output in DIR (kernel trace) and exit")
+    ap.add_argument("--fetch", metavar="DIR", help="with --summarize-profile: a FETCH_SIZE pass")
+    ap.add_argument("--write", metavar="DIR", help="with --summarize-profile: a WRITE_SIZE pass")
+    ap.add_argument("--counters", metavar="DIR", action="append",
+                    help="with --summarize-profile: a further counter pass (repeatable)")
+    ap.add_argument("--kernel", default="true, true>",
+                    help="with --summarize-profile: regular expression matched against kernel names")
+    ap.add_argument("--last", type=int, default=0,
+                    help="with --summarize-profile: average over the last N launches (the timed region)")
+    args = ap.parse_args()
+
+    if args.summarize_profile:
+        return summarize_profile(args)
+    ens = args.workload == "c3_ensemble"
+    if args.steps is None:
+        args.steps = 94 if ens else 8
+    if args.warmup is None:
+        args.warmup = 2 if ens else 4
+    if args.headline_only:
+        args.no_c1 = args.no_c2 = args.no_mixed = args.no_c4 = args.no_ausm = args.no_diagnostics = \
+            args.no_large_dt = args.no_ode = args.no_cpu_baseline = True
+
+    if args.cpu_baseline_only:
+        leg = cpu_baseline_ensemble if ens else cpu_baseline_leg
+        print(json.dumps(leg(args.workload)), flush=True)
+        return 0
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(the multi-GPU design is described, not built); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2101_05617_amd import dfrsw, inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if not ens and args.workload not in inputs.WORKLOADS:
+        print(f"unknown workload {args.workload}", file=sys.stderr)
+        return 2
+    if args.jv_only:
+        return jv_only(inputs.WORKLOADS[args.workload], args)
+
+    if ens:
+        out = ensemble_headline_line(args)
+        if not args.no_c1:
+            w1 = inputs.WORKLOADS["c1_ne30_p5"]
+            out["epi5_c1_ne30_p5"] = single_grid_run(w1, 8, 4, args.jv_reps)
+    else:
+        w = inputs.WORKLOADS[args.workload]
+        log(f"workload {w.name}: ne={w.ne} p={w.p} N={w.n_nodes} EPI{w.order} dt={w.dt_s}s tol={w.tol} m<={w.m_max}")
+        r = single_grid_run(w, args.steps, args.warmup, args.jv_reps)
+        out = {"metric": METRIC, "value": r.pop("steps_per_s"), "unit": "EPI steps/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic", **r}
 
     # ---- the ne = 60, p = 6 J*v (the roofline target size), buffers rotated
     if not args.no_c2:
@@ -931,14 +1163,9 @@ def main():
     if not args.no_c4:
         out["c4_ne120_p6"] = c4_study(args.c4_steps, 50)
 
-    # ---- the ensemble workload: batched mixed form against plain FP64 one
-    # member after another
-    if not args.no_ensemble:
-        out["ensemble_c3"] = ensemble_study(args.ensemble_members, args.ensemble_steps, args.ensemble_workers)
-
     # ---- the AUSM interface flux (App. D) on the same path
     if not args.no_ausm:
-        out["ausm"] = ausm_study(args.steps, 50)
+        out["ausm"] = ausm_study(8, 50)
 
     # ---- conservation diagnostics (Sec. 5.4)
     if not args.no_diagnostics:
@@ -952,37 +1179,10 @@ def main():
     if not args.no_ode:
         out["ode_suite"] = ode_suite_study()
 
-    # ---- the oracle on this host's cores (bounded sample): one thread, then
+    # ---- the oracle on this host's cores (bounded samples): one thread, then
     # every thread of this host's share (its element loop runs under OpenMP)
     if not args.no_cpu_baseline:
-        legs = {}
-        n_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-        for nt in (1, n_all):
-            env = dict(os.environ, OMP_NUM_THREADS=str(nt), OPENBLAS_NUM_THREADS=str(nt), MKL_NUM_THREADS=str(nt))
-            log(f"cpu baseline: oracle, {nt} thread(s)")
-            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
-                                "--workload", args.workload], capture_output=True, text=True, env=env, timeout=900)
-            if r.returncode != 0:
-                log("cpu baseline failed: " + r.stderr[-2000:])
-                break
-            legs[nt] = json.loads(r.stdout.strip().splitlines()[-1])
-        if 1 in legs:
-            cb = legs[1]
-            out["cpu_baseline"] = {"value": 1.0 / cb["step_s"], "unit": "EPI steps/s", "cores": 1, "kind": "oracle",
-                                   "sample": f"one EPI{w.order} step of {w.name} after {P_hist} untimed EPI2 "
-                                             f"start-up steps ({cb['n_matvec']} J*v); J*v alone "
-                                             f"{cb['jv_s'] * 1e3:.1f} ms",
-                                   "jv_per_s": 1.0 / cb["jv_s"],
-                                   "jv_per_s_c2_ne60_p6": 1.0 / cb["jv_s_c2"],
-                                   "jv_per_s_c4_ne120_p6": 1.0 / cb["jv_s_c4"],
-                                   "cpu": cpu_model()}
-            if n_all in legs and n_all != 1:
-                cm = legs[n_all]
-                out["cpu_baseline"]["all_threads"] = {
-                    "value": 1.0 / cm["step_s"], "cores": n_all, "jv_per_s": 1.0 / cm["jv_s"],
-                    "jv_per_s_c2_ne60_p6": 1.0 / cm["jv_s_c2"], "jv_per_s_c4_ne120_p6": 1.0 / cm["jv_s_c4"]}
-        else:
-            out["cpu_baseline"] = None
+        out["cpu_baseline"] = cpu_baseline_entry(args, ens)
     print(json.dumps(out), flush=True)
     return 0
 
