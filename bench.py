@@ -1112,6 +1112,7 @@ def main():
 
     if ens:
         out = ensemble_headline_line(args)
+        calibration_copy()   # the 256 MiB reference of the traffic counters in profiled runs
         if not args.no_c1:
             w1 = inputs.WORKLOADS["c1_ne30_p5"]
             out["epi5_c1_ne30_p5"] = single_grid_run(w1, 8, 4, args.jv_reps)

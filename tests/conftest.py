@@ -18,3 +18,7 @@ def _oracle_built():
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build(force=True)
     yield
+    # the measures the GPU tests recorded, for the run's output folder
+    from tests import gpu_util
+    if gpu_util.METRICS:
+        gpu_util.dump_metrics("gpurun_out/parity_metrics.json")

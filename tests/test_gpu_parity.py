@@ -35,7 +35,7 @@ import oracle
 from oracle import epi as oepi
 from oracle import kiops as okiops
 from paper_2101_05617_amd import inputs
-from tests.gpu_util import (check_fields, check_krylov, check_rhs, dump_metrics, field_metrics, pair, record, small, to_dev,
+from tests.gpu_util import (check_fields, check_krylov, check_rhs, field_metrics, pair, record, small, to_dev,
                             to_host, torch_dev)
 
 pytestmark = pytest.mark.gpu
@@ -55,7 +55,6 @@ def _gpu():
     from paper_2101_05617_amd import dfrsw
     dfrsw.lib()
     yield
-    dump_metrics("gpurun_out/parity_metrics.json")
 
 
 @pytest.mark.parametrize("ne,p", GRIDS)
