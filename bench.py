@@ -49,12 +49,12 @@ def arnoldi_jv_bytes_per_node(p, iop=2, prec="fp64"):
     # vector for the fused inner products: 72 + 24 p + 24 in FP64 (iop = 2);
     # with FP32 products on an FP64 basis the state is read as an FP32 copy
     # (60 + 24 p + 24); with an FP32 basis the basis vectors read and written
-    # are FP32 too (36 + 24 p + 12)
+    # and the b-columns are FP32 too (36 + 12 p + 12)
     if prec == "fp64":
         return 72 + 24 * p + (24 if iop >= 2 else 0)
     if prec == "fp32_jv":
         return 60 + 24 * p + (24 if iop >= 2 else 0)
-    return 36 + 24 * p + (12 if iop >= 2 else 0)
+    return 36 + 12 * p + (12 if iop >= 2 else 0)
 
 
 EPI_M = {2: 1, 3: 2, 4: 3, 5: 4, 6: 4}   # phi-columns b_1..b_M of an EPI step
@@ -892,7 +892,7 @@ def ensemble_headline_line(args):
         "gpu_busy_fraction": kernel_ms_total / (h["wall_s"] * 1e3),
         "roofline": {
             "kernel": "dfr_kernel_batch: batched complex-FP32 J*v with the fused Arnoldi epilogue, FP32 basis "
-                      "(every member's tiles in one launch per p group)",
+                      "and b-columns (every member's tiles in one launch per p group)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": profiled_traffic(prof),

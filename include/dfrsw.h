@@ -55,8 +55,10 @@ enum {
  * the products J_n (q_{n-i} - q_n) of the EPI remainders.
  * DFR_FP32_JV_BASIS32: as DFR_FP32_JV with the Krylov basis stored in FP32
  * (its vectors rounded once when stored; inner products and norms
- * accumulate in FP64 over the stored values); KIOPS / EPI and the batched
- * ensemble form; dfr_jvp_complex_step treats it as DFR_FP32_JV. */
+ * accumulate in FP64 over the stored values), and with the b-columns of the
+ * augmented operator (at most four) kept in FP32 for the Krylov products;
+ * KIOPS / EPI and the batched ensemble form; dfr_jvp_complex_step treats it
+ * as DFR_FP32_JV. */
 typedef enum { DFR_FP64 = 0, DFR_FP32_JV = 1, DFR_FP32_JV_BASIS32 = 2 } dfr_precision;
 
 /* Smallest complex-step eps accepted with DFR_FP32_JV and DFR_FP32_JV_BASIS32

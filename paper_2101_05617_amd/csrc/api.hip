@@ -842,7 +842,7 @@ int dfr_autotune(dfr_ctx *h, dfr_precision prec, int *tile_tx, int *tile_ty) {
   ar.start = 1;
   {
     const double *cols[4] = {v, v, v, v};
-    rc = launch_w_interleave(&c, n3, ar.p, 1.0, cols, c.d_W);
+    rc = launch_w_interleave(&c, n3, ar.p, 1.0, cols, c.d_W, b32);
     if (rc) return rc;
   }
   for (int k = 0; k < ar.p; ++k) ar.W[k] = c.d_W;

@@ -190,6 +190,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
       wcall.nu = k.nu;
       for (int i = 0; i < k.p; ++i) wcall.cols[i] = k.n_phi == 0 ? nullptr : k.b[k.p - i];
       wcall.out = c.d_W;
+      wcall.f32 = basis32 ? 1 : 0;
       wil.push_back(wcall);
     } else {
       for (int i = 0; i < k.p; ++i)
@@ -565,7 +566,7 @@ int dfr_ensemble_autotune(dfr_ensemble *E, dfr_precision prec) {
     const int64_t n3 = 3 * c.n;
     rc = launch_fill(&c, c.d_V, c.d_V + n3);
     const double *cols[4] = {c.d_V + n3, c.d_V + n3, c.d_V + n3, c.d_V + n3};
-    if (!rc) rc = launch_w_interleave(&c, n3, 4, 1.0, cols, c.d_W);
+    if (!rc) rc = launch_w_interleave(&c, n3, 4, 1.0, cols, c.d_W, b32);
     if (!rc && fp32) rc = launch_copy_to_f32(&c, n3, c.d_V, (float *)c.d_qf32);
     // FP32 copies of the direction and of a previous vector (slots 3 and 4)
     if (!rc && b32) rc = launch_copy_to_f32(&c, n3, c.d_V + n3, reinterpret_cast<float *>(c.d_V + 3 * n3));

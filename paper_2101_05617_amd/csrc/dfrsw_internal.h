@@ -105,7 +105,9 @@ struct ArnoldiArgs {
   int p;                  // number of W columns
   int start;              // 1: v_j is the sub-step's start vector
   const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
-  int wil;                // 1: W[0] holds the columns interleaved, 4 per value (p <= 4)
+  int wil;                // 1: W[0] holds the columns interleaved, 4 per value (p <= 4): FP64, or
+                          //    FP32 when the basis is FP32
+
   const void *vprev;      // v~_{j-1} as stored (basis element type) or NULL (iop = 1)
   const double *pin;      // partial sums of the previous kernel, one per workgroup
   int np_in;
@@ -172,6 +174,7 @@ struct WilCall {         // W = nu [cols] interleaved four per value (a member's
   double nu;
   const double *cols[4];
   double *out;
+  int f32;                // 1: as four FP32 values (a member with an FP32 Krylov basis)
 };
 struct ExpmCall {        // one workgroup per member
   struct KDev *kd;
@@ -328,8 +331,10 @@ int launch_combine(Ctx *c, double *x);
 int launch_expm(Ctx *c, double tau, int jfin, const double *pin, int np_in, double tol, unsigned seq);   // -> d_mail
 int launch_axpby(Ctx *c, int64_t n, double a, const double *x, double b, const double *y, double *out);
 int launch_copy_to_f32(Ctx *c, int64_t n, const double *x, float *y);
-// W interleaved: out[4 i + k] = nu * cols[k][i] for k < p (NULL: zero), 0 for p <= k < 4
-int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out);
+// W interleaved: out[4 i + k] = nu * cols[k][i] for k < p (NULL: zero), 0 for p <= k < 4; FP64, or
+// FP32 (f32) for a KIOPS call with an FP32 basis, whose Krylov-form product reads it so
+int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out,
+                        bool f32 = false);
 int64_t diag_blocks(const Ctx *c);
 int launch_diagnostics(Ctx *c, const double *q, double *zeta, double *fcor);
 int launch_check_state(Ctx *c, const double *q);

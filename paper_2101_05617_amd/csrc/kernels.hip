@@ -258,6 +258,82 @@ __device__ __forceinline__ cx<T> csqrt1(cx<T> z) {
   return {z.r * rs, T(0.5) * z.i * rs};
 }
 
+// ---------------------------------------------------------------------------
+// Raw buffer access: a resource (base, size in bytes) in scalar registers and
+// 32-bit byte offsets per lane, so that an indexed load or store costs one
+// address instruction instead of 64-bit address arithmetic; offsets beyond
+// the size read 0 and write nothing.  Every stream the kernels index is
+// below 2 GiB (3N doubles at N = 4.2 M is 102 MB).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+// base and size are the same in every lane of the wave (workgroup-uniform
+// arguments); taking them from the first lane keeps the resource in scalar
+// registers, where the buffer instructions need it
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  const int nb = __builtin_amdgcn_readfirstlane((int)bytes);
+  void *u = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+  // word 3 of a raw buffer resource on gfx9-family devices: 32-bit data format
+  return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, nb, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t index);
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t index) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, index * 8u, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t index) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, index * 4u, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t index, T v);
+template <>
+__device__ __forceinline__ void bstore<double>(rsrc_t r, uint32_t index, double v) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, index * 8u, 0, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<float>(rsrc_t r, uint32_t index, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, index * 4u, 0, 0);
+}
+// a device-memory pointer as a global-address-space one: loads through it
+// are global loads (scalar base, 32-bit lane offsets) rather than flat ones,
+// also where the pointer itself was read from memory (the batched calls)
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gmem(const T *p) {
+  return (const __attribute__((address_space(1))) T *)p;
+}
+
+// four consecutive floats (16 bytes) at float4 index `index`
+__device__ __forceinline__ float4 bload4f(rsrc_t r, uint32_t index) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 w = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, index * 16u, 0, 0));
+  return make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), __uint_as_float(w.w));
+}
+
+// tangent record i of a device table, as global loads
+__device__ __forceinline__ Tan3 ld_tan3(const Tan3 *tab, int i) {
+  const auto r = gmem(tab) + i;
+  Tan3 t;
+  t.x = r->x;
+  t.ax = r->ax;
+  t.rax = r->rax;
+  t.pad = 0.0;
+  return t;
+}
+
+// two consecutive doubles (16 bytes) at double index `index`
+__device__ __forceinline__ double2 bload2(rsrc_t r, uint32_t index) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 w = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, index * 8u, 0, 0));
+  double2 d;
+  d.x = __hiloint2double((int)w.y, (int)w.x);
+  d.y = __hiloint2double((int)w.w, (int)w.z);
+  return d;
+}
+
 // physical flux through an x^n = const face per unit sqrt(g)/a^2, and the
 // Rusanov wave speed |u^n| + sqrt(h^nn g H), for Q = (H, H u^1, H u^2); the
 // state is taken by value and the normal momentum Mn = H u^n passed in (no
@@ -355,11 +431,19 @@ struct FaceDesc {
   int enode;    // element index along the face in the node-tangent table
 };
 
+// one neighbour element line of the tile's halo, set up once per workgroup:
+// the neighbour's node index (in one field) of the line through face point
+// 0, the index steps to the next face point and along the line, and which
+// end of the line the shared face is
+struct HaloDesc {
+  int base, tstep, kstep, lo;
+};
+
 // LDS layout of the tiled kernel, in values of the compute type T:
 // state [nel][3][NN][L], fluxes [nel][5][NN] (reused for the common fluxes
-// [nface*NS][3]), traces [4 nel + nhalo][3][NS][L], face table.
+// [nface*NS][3]), traces [4 nel + nhalo][3][NS][L], face table, halo table.
 struct DfrLds {
-  int state, flux, trace, faces, total;
+  int state, flux, trace, faces, halo, total;
 };
 __host__ __device__ inline DfrLds dfr_lds_layout(int ns, int tx, int ty, int lanes, int tsize) {
   const int nn = ns * ns, nel = tx * ty, nhalo = 2 * (tx + ty);
@@ -371,7 +455,9 @@ __host__ __device__ inline DfrLds dfr_lds_layout(int ns, int tx, int ty, int lan
   l.trace = l.flux + nflux;
   l.faces = l.trace + (4 * nel + nhalo) * 3 * ns * lanes;
   const int fvals = (nface * (int)sizeof(FaceDesc) + tsize - 1) / tsize;
-  l.total = l.faces + fvals;
+  l.halo = l.faces + fvals;
+  const int hvals = (nhalo * (int)sizeof(HaloDesc) + tsize - 1) / tsize;
+  l.total = l.halo + hvals;
   return l;
 }
 
@@ -409,6 +495,16 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   T *Fl = reinterpret_cast<T *>(dyn) + lay.flux;
   T *TR = reinterpret_cast<T *>(dyn) + lay.trace;
   FaceDesc *FD = reinterpret_cast<FaceDesc *>(reinterpret_cast<T *>(dyn) + lay.faces);
+  HaloDesc *HD = reinterpret_cast<HaloDesc *>(reinterpret_cast<T *>(dyn) + lay.halo);
+  // the state and direction streams (3N values each) and the output
+  const uint32_t n3 = 3u * (uint32_t)N;
+  const rsrc_t rq = make_rsrc(q, n3 * (uint32_t)sizeof(TQ));
+  const rsrc_t rv = make_rsrc(CS ? (const void *)v : (const void *)q, n3 * (uint32_t)sizeof(TV));
+  const rsrc_t ro = make_rsrc(out, n3 * (uint32_t)sizeof(TV));
+  // the complex step in the compute type: z = q + i epsT v, and the result
+  // Im F / epsT (epsT = eps in FP64; the FP32 value nearest eps in FP32)
+  const T epsT = (T)eps;
+  const double invE = CS ? 1.0 / (double)epsT : 1.0;
 
   // The direction enters unscaled: J (sigma v) = sigma J v, the scale sigma
   // (vscale, or the Arnoldi sigma_j) multiplies the result.  In Arnoldi mode
@@ -421,11 +517,11 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   int happy0 = 0;
   double pv[4] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (AR) {
-    happy0 = ar.kd->happy;
+    happy0 = gmem(ar.kd)->happy;
     if (tid < 256) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (tid + 256 * k < ar.np_in) pv[k] = ar.pin[tid + 256 * k];
+        if (tid + 256 * k < ar.np_in) pv[k] = gmem(ar.pin)[tid + 256 * k];
     }
   }
   const double vs_in = (!AR && CS && vscale) ? *vscale : 1.0;
@@ -477,6 +573,41 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     }
     FD[id] = d;
   }
+  // halo table: slots [0,TY) west, [TY,2TY) east, [2TY,2TY+TX) south, then
+  // north; across a panel edge the neighbour's face, element and line order
+  // come from the connectivity of App. C
+  for (int h = tid; h < nhalo; h += blockDim.x) {
+    int face, ai;
+    if (h < TY) { face = 0; ai = h; }
+    else if (h < 2 * TY) { face = 1; ai = h - TY; }
+    else if (h < 2 * TY + TX) { face = 2; ai = h - 2 * TY; }
+    else { face = 3; ai = h - 2 * TY - TX; }
+    int qp = p, qe, qi, qf, rev = 0;
+    if (face == 0) { qe = ej0 + ai; qi = ei0 - 1; qf = 1; }
+    else if (face == 1) { qe = ej0 + ai; qi = ei0 + TX; qf = 0; }
+    else if (face == 2) { qi = ei0 + ai; qe = ej0 - 1; qf = 3; }
+    else { qi = ei0 + ai; qe = ej0 + TY; qf = 2; }
+    if (qi < 0 || qi >= ne || qe < 0 || qe >= ne) {   // across a panel edge
+      const int along = (face < 2) ? ej0 + ai : ei0 + ai;
+      qp = g.nb_q[p][face];
+      qf = g.nb_e[p][face];
+      rev = g.nb_rev[p][face];
+      const int qa = rev ? ne - 1 - along : along;
+      if (qf == 0) { qi = 0; qe = qa; }
+      else if (qf == 1) { qi = ne - 1; qe = qa; }
+      else if (qf == 2) { qe = 0; qi = qa; }
+      else { qe = ne - 1; qi = qa; }
+    }
+    // face point t of the shared face is the neighbour's line qt = t (or
+    // NS-1-t when the orders oppose): a node row (x^1 faces) or column
+    const int t0 = rev ? NS - 1 : 0;
+    HaloDesc hd;
+    hd.base = ((qp * ne + qe) * ne + qi) * NN + ((qf < 2) ? t0 * NS : t0);
+    hd.tstep = (rev ? -1 : 1) * ((qf < 2) ? NS : 1);
+    hd.kstep = (qf < 2) ? 1 : NS;
+    hd.lo = (qf == 0 || qf == 2) ? 1 : 0;
+    HD[h] = hd;
+  }
 
   const int s = tid / NN, node = tid - s * NN, nj = node / NS, ni = node - nj * NS;
   const bool active = s < nel;
@@ -494,37 +625,57 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   // one left by the previous update), w_j = sigma_j (J v~_j + W u_j).
   double wb[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
   if (AR && active) {
-    const double *ub = ar.kd->botu + ar.j * MAX_P;
-    const double sp = ar.vprev ? ar.kd->sigma[ar.j - 1] : 0.0;   // v_{j-1} = sigma_{j-1} v~_{j-1}
+    const auto ub = gmem(ar.kd->botu) + ar.j * MAX_P;
+    const double sp = ar.vprev ? gmem(ar.kd->sigma)[ar.j - 1] : 0.0;   // v_{j-1} = sigma_{j-1} v~_{j-1}
     double uw[4];   // the bottom entries paired with the interleaved columns (0 beyond p)
 #pragma unroll
     for (int k = 0; k < 4; ++k) uw[k] = k < ar.p ? (ar.start ? ar.ybot[k] : ub[k]) : 0.0;
     if (ar.wil) {
-      // four interleaved columns, two 16-byte loads per value: every load of
-      // the three fields first (one memory round trip), then the sums.
-      // Without a previous vector the direction v is read for a zero term.
-      const TV *vpp = ar.vprev ? static_cast<const TV *>(ar.vprev) : v;
-      double2 x0[3], x1[3];
+      // four interleaved columns: every load of the three fields first (one
+      // memory round trip), then the sums.  Without a previous vector the
+      // direction v is read for a zero term.
+      const rsrc_t rp = make_rsrc(ar.vprev ? ar.vprev : (const void *)v, n3 * (uint32_t)sizeof(TV));
       double pv[3];
+      if constexpr (std::is_same<TV, float>::value) {
+        // FP32 basis: the columns are kept in FP32 too (what they feed is
+        // rounded to FP32 when stored), one 16-byte load per value
+        const rsrc_t rw = make_rsrc(ar.W[0], n3 * 16u);
+        float4 x[3];
 #pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        const int id = f * N + gidx;
-        const double2 *w2 = reinterpret_cast<const double2 *>(ar.W[0]) + 2 * (int64_t)id;
-        x0[f] = w2[0];
-        x1[f] = w2[1];
-        pv[f] = (double)vpp[id];
-      }
+        for (int f = 0; f < 3; ++f) {
+          const uint32_t id = (uint32_t)(f * N + gidx);
+          x[f] = bload4f(rw, id);
+          pv[f] = (double)bload<TV>(rp, id);
+        }
 #pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        wb[f] = ((x0[f].x * uw[0] + x0[f].y * uw[1]) + x1[f].x * uw[2]) + x1[f].y * uw[3];
-        vp[f] = sp * pv[f];
+        for (int f = 0; f < 3; ++f) {
+          wb[f] = (((double)x[f].x * uw[0] + (double)x[f].y * uw[1]) + (double)x[f].z * uw[2]) +
+                  (double)x[f].w * uw[3];
+          vp[f] = sp * pv[f];
+        }
+      } else {
+        // FP64: two 16-byte loads per value
+        const rsrc_t rw = make_rsrc(ar.W[0], n3 * 32u);
+        double2 x0[3], x1[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const uint32_t id = (uint32_t)(f * N + gidx);
+          x0[f] = bload2(rw, 4u * id);
+          x1[f] = bload2(rw, 4u * id + 2u);
+          pv[f] = (double)bload<TV>(rp, id);
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          wb[f] = ((x0[f].x * uw[0] + x0[f].y * uw[1]) + x1[f].x * uw[2]) + x1[f].y * uw[3];
+          vp[f] = sp * pv[f];
+        }
       }
     } else {
 #pragma unroll
       for (int f = 0; f < 3; ++f) {
         const int id = f * N + gidx;
         double a = 0.0;
-        for (int k = 0; k < ar.p; ++k) a += ar.W[k][id] * (ar.start ? ar.ybot[k] : ub[k]);
+        for (int k = 0; k < ar.p; ++k) a += gmem(ar.W[k])[id] * (ar.start ? ar.ybot[k] : ub[k]);
         wb[f] = a;
         if (ar.vprev) vp[f] = sp * (double)static_cast<const TV *>(ar.vprev)[id];
       }
@@ -533,7 +684,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
 
   // ---- A: state, nodal fluxes, sources
   if (active) {
-    const Tan3 tx = g.tnode[ei * NS + ni], ty = g.tnode[ej * NS + nj];
+    const Tan3 tx = ld_tan3(g.tnode, ei * NS + ni), ty = ld_tan3(g.tnode, ej * NS + nj);
     const T X = (T)tx.x, ax = (T)tx.ax, rax = (T)tx.rax;
     const T Y = (T)ty.x, ay = (T)ty.ax, ray = (T)ty.rax;
     const T d2 = ax + Y * Y;
@@ -551,12 +702,12 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     cx<T> Qz[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      const T qr = (T)q[f * N + gidx];
+      const T qr = (T)bload<TQ>(rq, (uint32_t)(f * N + gidx));
       T qi = T(0);
       if constexpr (CS) {
-        const double vv = (double)v[f * N + gidx];
-        vtrue[f] = vv;
-        qi = (T)(eps * vv);
+        const TV vv = bload<TV>(rv, (uint32_t)(f * N + gidx));
+        vtrue[f] = (double)vv;
+        qi = epsT * (T)vv;
       }
       Qz[f] = {qr, qi};
       T *sp = S + ((s * 3 + f) * NN + node) * L;
@@ -581,53 +732,9 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     src1 = -(T(2) * (G101 * l1 + G102 * l2) + (G111 * m11 + (T(2) * G112) * m12));
     src2 = -(T(2) * (G201 * l1 + G202 * l2) + ((T(2) * G212) * m12 + G222 * m22));
     if (g.orog) {
-      src1 -= (T)g.orog[gidx] * lH;
-      src2 -= (T)g.orog[N + gidx] * lH;
+      src1 -= (T)gmem(g.orog)[gidx] * lH;
+      src2 -= (T)gmem(g.orog)[N + gidx] * lH;
     }
-  }
-  // neighbour states extrapolated to the faces shared with the tile:
-  // task = (h * 3 + f) * NS + t
-  for (int task = tid; task < nhalo * 3 * NS; task += blockDim.x) {
-    const int t = task % NS;
-    const int r = task / NS;
-    const int f = r % 3, h = r / 3;
-    int face, ai;
-    if (h < TY) { face = 0; ai = h; }
-    else if (h < 2 * TY) { face = 1; ai = h - TY; }
-    else if (h < 2 * TY + TX) { face = 2; ai = h - 2 * TY; }
-    else { face = 3; ai = h - 2 * TY - TX; }
-    int qp = p, qe, qi, qf, rev = 0;
-    if (face == 0) { qe = ej0 + ai; qi = ei0 - 1; qf = 1; }
-    else if (face == 1) { qe = ej0 + ai; qi = ei0 + TX; qf = 0; }
-    else if (face == 2) { qi = ei0 + ai; qe = ej0 - 1; qf = 3; }
-    else { qi = ei0 + ai; qe = ej0 + TY; qf = 2; }
-    if (qi < 0 || qi >= ne || qe < 0 || qe >= ne) {   // across a panel edge
-      const int along = (face < 2) ? ej0 + ai : ei0 + ai;
-      qp = g.nb_q[p][face];
-      qf = g.nb_e[p][face];
-      rev = g.nb_rev[p][face];
-      const int qa = rev ? ne - 1 - along : along;
-      if (qf == 0) { qi = 0; qe = qa; }
-      else if (qf == 1) { qi = ne - 1; qe = qa; }
-      else if (qf == 2) { qe = 0; qi = qa; }
-      else { qe = ne - 1; qi = qa; }
-    }
-    const int qt = rev ? NS - 1 - t : t;
-    const bool wlo = (qf == 0 || qf == 2);
-    const int first = f * N + ((qp * ne + qe) * ne + qi) * NN + ((qf < 2) ? qt * NS : qt);
-    const int st = (qf < 2) ? 1 : NS;
-    // (the LDS copies of the weights are not yet visible here)
-    T ar_ = T(0), ai_ = T(0);
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const int id = first + k * st;
-      const T wk = wlo ? (T)ops.lm[k] : (T)ops.lp[k];
-      ar_ += wk * (T)q[id];
-      if constexpr (CS) ai_ += wk * (T)(eps * (double)v[id]);
-    }
-    T *tp = TR + (((4 * nel + h) * 3 + f) * NS + t) * L;
-    tp[0] = ar_;
-    if constexpr (CS) tp[1] = ai_;
   }
   if constexpr (AR) {
     if (happy0) return;   // uniform: the sub-step ended in a happy breakdown
@@ -644,6 +751,27 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       shappy = ok ? 0 : 1;
       ssig = sg_;
     }
+  }
+
+  // ---- B: the neighbours' states extrapolated to the faces they share with
+  // the tile (Eq. 7), task = (h * 3 + f) * NS + t: the loads of this thread's
+  // first task go out first and are used after the interior derivative and
+  // the own traces, which read only LDS
+  const int nhtask = nhalo * 3 * NS;
+  T hz[NS], hzi[NS];
+  int hdst = -1, hlo = 1;
+  if (tid < nhtask) {
+    const int t = tid % NS, r = tid / NS;
+    const int f = r % 3, h = r / 3;
+    const HaloDesc hd = HD[h];
+    const uint32_t id0 = (uint32_t)(f * N + hd.base + t * hd.tstep);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      hz[k] = (T)bload<TQ>(rq, id0 + (uint32_t)(k * hd.kstep));
+      if constexpr (CS) hzi[k] = (T)bload<TV>(rv, id0 + (uint32_t)(k * hd.kstep));
+    }
+    hlo = hd.lo;
+    hdst = (((4 * nel + h) * 3 + f) * NS + t) * L;
   }
 
   // ---- B: interior part of the derivative (linear lane), both directions
@@ -694,6 +822,35 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       up[1] = hi;
     }
   }
+  // the halo extrapolation: the first task from the loads above, any
+  // further ones (large tiles) in turn; eps multiplies each sum once
+  if (hdst >= 0) {
+    T a = T(0), b = T(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T wk = hlo ? slm[k] : slp[k];
+      a += wk * hz[k];
+      if constexpr (CS) b += wk * hzi[k];
+    }
+    TR[hdst] = a;
+    if constexpr (CS) TR[hdst + 1] = epsT * b;
+  }
+  for (int task = tid + (int)blockDim.x; task < nhtask; task += blockDim.x) {
+    const int t = task % NS, r = task / NS;
+    const int f = r % 3, h = r / 3;
+    const HaloDesc hd = HD[h];
+    const uint32_t id0 = (uint32_t)(f * N + hd.base + t * hd.tstep);
+    T a = T(0), b = T(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T wk = hd.lo ? slm[k] : slp[k];
+      a += wk * (T)bload<TQ>(rq, id0 + (uint32_t)(k * hd.kstep));
+      if constexpr (CS) b += wk * (T)bload<TV>(rv, id0 + (uint32_t)(k * hd.kstep));
+    }
+    T *tp = TR + (((4 * nel + h) * 3 + f) * NS + t) * L;
+    tp[0] = a;
+    if constexpr (CS) tp[1] = epsT * b;
+  }
   __syncthreads();
 
   if (AR && shappy) return;   // uniform: happy breakdown found above
@@ -712,7 +869,7 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     cx<T> L1 = ld_tr(d.lo, 1), L2 = ld_tr(d.lo, 2), R1 = ld_tr(d.hi, 1), R2 = ld_tr(d.hi, 2);
     if (d.xf >= 0) {
       // App. C: the neighbour's components -> this panel's basis
-      const double *M = g.xform + (int64_t)(d.xf + t) * 4;
+      const auto M = gmem(g.xform) + (int64_t)(d.xf + t) * 4;
       const T m00 = (T)M[0], m01 = (T)M[1], m10 = (T)M[2], m11 = (T)M[3];
       if (d.info & 2) {
         const cx<T> a1 = m00 * L1 + m01 * L2, a2 = m10 * L1 + m11 * L2;
@@ -727,13 +884,13 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
     // metric at the face point
     T X, Y, ax, ay, rax, ray;
     if (n == 0) {
-      X = (T)g.tedge[d.eedge]; ax = T(1) + X * X; rax = frcp(ax);
-      const Tan3 ty = g.tnode[d.enode * NS + t];
+      X = (T)gmem(g.tedge)[d.eedge]; ax = T(1) + X * X; rax = frcp(ax);
+      const Tan3 ty = ld_tan3(g.tnode, d.enode * NS + t);
       Y = (T)ty.x; ay = (T)ty.ax; ray = (T)ty.rax;
     } else {
-      const Tan3 tx = g.tnode[d.enode * NS + t];
+      const Tan3 tx = ld_tan3(g.tnode, d.enode * NS + t);
       X = (T)tx.x; ax = (T)tx.ax; rax = (T)tx.rax;
-      Y = (T)g.tedge[d.eedge]; ay = T(1) + Y * Y; ray = frcp(ay);
+      Y = (T)gmem(g.tedge)[d.eedge]; ay = T(1) + Y * Y; ray = frcp(ay);
     }
     const T d2 = ax + Y * Y;
     const T rd = frsqrt(d2);
@@ -766,7 +923,6 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   const double vs = AR ? ssig : vs_in;
   if (active) {
     const T scale = -(T)g.two_over_delta * rs;
-    const T invE = CS ? (T)(1.0 / eps) : T(1);
     const int iW = ((sx * TY + sy) * NS + nj) * 3, iE = (((sx + 1) * TY + sy) * NS + nj) * 3;
     const int iS = ((nvf + sy * TX + sx) * NS + ni) * 3, iN = ((nvf + (sy + 1) * TX + sx) * NS + ni) * 3;
     const T cw = sD[ni][0], ce = sD[ni][NS + 1], cs = sD[nj][0], cn = sD[nj][NS + 1];
@@ -776,12 +932,12 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       T r = scale * d;
       if (f == 1) r += src1;
       if (f == 2) r += src2;
-      w[f] = CS ? (double)(r * invE) * vs : (double)r;
+      w[f] = CS ? ((double)r * invE) * vs : (double)r;
       wr[f] = (double)r;
     }
     if constexpr (!AR) {
 #pragma unroll
-      for (int f = 0; f < 3; ++f) out[f * N + gidx] = (TV)w[f];
+      for (int f = 0; f < 3; ++f) bstore<TV>(ro, (uint32_t)(f * N + gidx), (TV)w[f]);
     }
   }
   if constexpr (!AR) return;
@@ -789,13 +945,11 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   // ---- Arnoldi epilogue: w = sigma_j (J v~_j + W u_j); partial <v_j, w>, <v_{j-1}, w>
   double d0 = 0.0, d1 = 0.0;
   if (active) {
-    const double invE = 1.0 / eps;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      const int id = f * N + gidx;
       // the inner products use the value as stored (rounded to the basis type)
       const TV a = (TV)(vs * (wr[f] * invE + wb[f]));
-      out[id] = a;
+      bstore<TV>(ro, (uint32_t)(f * N + gidx), a);
       d0 += (double)a * (vs * vtrue[f]);
       d1 += (double)a * vp[f];
     }
@@ -835,7 +989,8 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCal
     if (lbg >= b0 && lbg < b0 + calls[t].ntiles) s_m = t;
   }
   __syncthreads();
-  const DfrCall &c = calls[s_m];
+  // the member's call, at a workgroup-uniform index (scalar loads)
+  const DfrCall &c = calls[__builtin_amdgcn_readfirstlane(s_m)];
   dfr_body<NS, T, TQ, CS, AR, 0, TV>(*c.g, *c.ops, c.TX, c.TY, lbg - c.b0, reinterpret_cast<const TQ *>(c.q),
                                      static_cast<const TV *>(c.v), c.vscale, c.eps, static_cast<TV *>(c.out), c.ar);
 }
@@ -855,7 +1010,7 @@ __device__ __forceinline__ int find_call(const C *__restrict__ calls, int ncalls
     if (b >= b0 && b < b0 + calls[t].nblk) s_m = t;
   }
   __syncthreads();
-  return s_m;
+  return __builtin_amdgcn_readfirstlane(s_m);
 }
 
 // first Arnoldi step of a sub-step whose top block is identically zero:
@@ -869,8 +1024,13 @@ __device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n3; i += (int64_t)nblk * BLOCK) {
     double acc = 0.0;
     if (ar.wil) {
-      const double *w = ar.W[0] + 4 * i;
-      for (int k = 0; k < ar.p; ++k) acc += w[k] * bj[k];
+      if constexpr (std::is_same<TV, float>::value) {   // FP32 columns with an FP32 basis
+        const float *w = reinterpret_cast<const float *>(ar.W[0]) + 4 * i;
+        for (int k = 0; k < ar.p; ++k) acc += (double)w[k] * bj[k];
+      } else {
+        const double *w = ar.W[0] + 4 * i;
+        for (int k = 0; k < ar.p; ++k) acc += w[k] * bj[k];
+      }
     } else {
       for (int k = 0; k < ar.p; ++k) acc += ar.W[k][i] * bj[k];
     }
@@ -2108,29 +2268,34 @@ int launch_ode(Ctx *c, const double *q, const double *v, const double *vscale, b
 }
 
 __device__ __forceinline__ void w_interleave_body(int blk, int nblk, int64_t n, int p, double nu, const double *c0,
-                                                  const double *c1, const double *c2, const double *c3, double *out) {
+                                                  const double *c1, const double *c2, const double *c3, double *out,
+                                                  int f32) {
   for (int64_t i = (int64_t)blk * BLOCK + threadIdx.x; i < n; i += (int64_t)nblk * BLOCK) {
-    double2 a, b;
-    a.x = (p > 0 && c0) ? nu * c0[i] : 0.0;
-    a.y = (p > 1 && c1) ? nu * c1[i] : 0.0;
-    b.x = (p > 2 && c2) ? nu * c2[i] : 0.0;
-    b.y = (p > 3 && c3) ? nu * c3[i] : 0.0;
-    double2 *o = reinterpret_cast<double2 *>(out) + 2 * i;
-    o[0] = a;
-    o[1] = b;
+    const double a0 = (p > 0 && c0) ? nu * c0[i] : 0.0;
+    const double a1 = (p > 1 && c1) ? nu * c1[i] : 0.0;
+    const double a2 = (p > 2 && c2) ? nu * c2[i] : 0.0;
+    const double a3 = (p > 3 && c3) ? nu * c3[i] : 0.0;
+    if (f32) {   // the columns of a call with an FP32 Krylov basis
+      reinterpret_cast<float4 *>(out)[i] = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+    } else {
+      double2 *o = reinterpret_cast<double2 *>(out) + 2 * i;
+      o[0] = make_double2(a0, a1);
+      o[1] = make_double2(a2, a3);
+    }
   }
 }
 __global__ __launch_bounds__(BLOCK) void w_interleave_kernel(int64_t n, int p, double nu, const double *c0,
                                                              const double *c1, const double *c2, const double *c3,
-                                                             double *out) {
-  w_interleave_body(blockIdx.x, gridDim.x, n, p, nu, c0, c1, c2, c3, out);
+                                                             double *out, int f32) {
+  w_interleave_body(blockIdx.x, gridDim.x, n, p, nu, c0, c1, c2, c3, out, f32);
 }
 __global__ __launch_bounds__(BLOCK) void w_interleave_batch(const WilCall *__restrict__ calls, int ncalls) {
   const WilCall &c = calls[find_call(calls, ncalls)];
-  w_interleave_body(blockIdx.x - c.b0, c.nblk, c.n, c.p, c.nu, c.cols[0], c.cols[1], c.cols[2], c.cols[3], c.out);
+  w_interleave_body(blockIdx.x - c.b0, c.nblk, c.n, c.p, c.nu, c.cols[0], c.cols[1], c.cols[2], c.cols[3], c.out,
+                    c.f32);
 }
 
-int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out) {
+int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const *cols, double *out, bool f32) {
   if (p > 4) {
     set_error("interleaved W holds at most four columns");
     return DFR_E_INVAL;
@@ -2138,7 +2303,7 @@ int launch_w_interleave(Ctx *c, int64_t n, int p, double nu, const double *const
   const double *k[4] = {nullptr, nullptr, nullptr, nullptr};
   for (int i = 0; i < p; ++i) k[i] = cols[i];
   dfr_launch(c, DFR_K_OTHER, w_interleave_kernel, dim3(grid_for(n)), dim3(BLOCK), 0, n, p, nu, k[0], k[1], k[2], k[3],
-             out);
+             out, f32 ? 1 : 0);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }

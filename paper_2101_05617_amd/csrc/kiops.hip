@@ -265,7 +265,7 @@ static int kiops_core(Ctx &c, const double *q, const float *q32, double tau_out,
   if (c.w_il) {
     const double *cols[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int i = 0; i < k.p; ++i) cols[i] = n_phi == 0 ? nullptr : b[k.p - i];
-    rc = launch_w_interleave(&c, n3, k.p, k.nu, cols, c.d_W);
+    rc = launch_w_interleave(&c, n3, k.p, k.nu, cols, c.d_W, c.basis32);
     if (rc) return rc;
   } else {
     for (int i = 0; i < k.p; ++i) {
