@@ -3,10 +3,15 @@
 shallow-water model, each one KIOPS phi-combination driven by complex-step
 J*v products, plus the J*v kernel alone.
 
-Default workload: ne = 30, p = 5 (194,400 nodes, 583,200 unknowns), EPI5,
-dt = 1800 s, KIOPS tol 1e-10, Krylov dimension <= 64, plain FP64, on the
-balanced zonal flow with seeded perturbations (synthetic; see
-paper_2101_05617_amd/inputs.py).  One "step" is one EPI5 step.
+Default workload (the headline): an ensemble of 64 independent members (ne in
+{8, 12, 16, 24, 32, 40}, p in {4, 5, 6}), EPI4, dt = 900 s, Krylov dimension
+<= 32, in the mixed batched form (complex-FP32 products, FP32 Krylov basis,
+FP64 inner products, Hessenberg, exponential and update) at KIOPS tol 1e-6,
+on the balanced zonal flow with seeded perturbations (synthetic; see
+paper_2101_05617_amd/inputs.py).  One "step" is one EPI step of every member;
+the value is member EPI steps per second.  Alongside: the other ensemble
+forms (plain FP64, sequential, device-driven rounds) with their errors after
+one simulated day, and the single-grid workloads (--workload NAME for one).
 
 Prints ONE JSON line (rank 0).  Usage:
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
@@ -307,14 +312,17 @@ def mixed_study(steps):
 # exponential and EPI update FP64; tolerance one decade above the relative
 # noise of a complex-FP32 product); the last is plain FP64, one member after
 # another, the reference of every error.
+# (name, precision, form, KIOPS tol, who drives the batched form's rounds)
 ENSEMBLE_FORMS = [
-    ("fp32_jv_basis32_batched_tol1e-6", "fp32_jv_basis32", "batched", 1e-6),
-    ("fp32_jv_batched_tol1e-6", "fp32_jv", "batched", 1e-6),
-    ("fp64_batched_tol1e-6", "fp64", "batched", 1e-6),
-    ("fp64_sequential_tol1e-6", "fp64", "sequential", 1e-6),
-    ("fp32_jv_batched", "fp32_jv", "batched", 1e-10),
-    ("fp64_batched", "fp64", "batched", 1e-10),
-    ("fp64_sequential", "fp64", "sequential", 1e-10),
+    ("fp32_jv_basis32_batched_tol1e-6", "fp32_jv_basis32", "batched", 1e-6, "host"),
+    ("fp32_jv_basis32_batched_device_rounds_tol1e-6", "fp32_jv_basis32", "batched", 1e-6, "device"),
+    ("fp32_jv_batched_tol1e-6", "fp32_jv", "batched", 1e-6, "host"),
+    ("fp64_batched_tol1e-6", "fp64", "batched", 1e-6, "host"),
+    ("fp64_sequential_tol1e-6", "fp64", "sequential", 1e-6, "host"),
+    ("fp32_jv_batched", "fp32_jv", "batched", 1e-10, "host"),
+    ("fp64_batched", "fp64", "batched", 1e-10, "host"),
+    ("fp64_batched_device_rounds", "fp64", "batched", 1e-10, "device"),
+    ("fp64_sequential", "fp64", "sequential", 1e-10, "host"),
 ]
 
 
@@ -323,10 +331,10 @@ def ensemble_headline(args, forms=None):
     dt 900 s, m <= 32) in every form of ENSEMBLE_FORMS: W untimed steps (the
     EPI2 start-up steps first), K timed steps of all members, then untimed
     steps to the end of the simulated day (96 steps), whose states give the
-    error in h of each form against plain FP64 sequential at tol 1e-10.  The
-    headline form's timed steps carry HIP-event timing of every batched
-    launch (the roofline of its Krylov-form product); its next K steps run
-    without it, for comparison."""
+    error in h of each form against plain FP64 sequential at tol 1e-10.  In
+    the headline form's timed steps HIP events bracket the launches of its
+    Krylov-form product (the roofline); its next K steps bracket every
+    batched launch (the per-kind breakdown)."""
     import numpy as np
     import torch
 
@@ -339,13 +347,14 @@ def ensemble_headline(args, forms=None):
     total_nodes = sum(w.n_nodes for w in members)
     forms = forms or ENSEMBLE_FORMS
     res, finals = {}, {}
-    for name, prec, form, tol in forms:
+    for name, prec, form, tol, rounds in forms:
         opts = dfrsw.kiops_opts(tol=tol, m_max=w0.m_max)
-        ens = Ensemble(members, prec=prec, form=form)
+        ens = Ensemble(members, prec=prec, form=form, rounds=rounds)
         for _ in range(W):
             ens.step(opts)
         headline = name == forms[0][0]
         if headline and form == "batched":
+            dfrsw.dfr_ensemble_timing_kinds(ens.eg, ["jv_arnoldi"])
             dfrsw.dfr_ensemble_timing_enable(ens.eg, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -360,21 +369,30 @@ def ensemble_headline(args, forms=None):
              "jv_per_member_step": agg["n_matvec"] / (len(members) * K),
              "expm_per_member_step": agg["n_expm"] / (len(members) * K),
              "substeps_per_member_step": agg["n_substeps"] / (len(members) * K),
-             "rejections_per_member_step": agg["n_rejected"] / (len(members) * K), "kiops_tol": tol}
+             "rejections_per_member_step": agg["n_rejected"] / (len(members) * K), "kiops_tol": tol,
+             "rounds": rounds if form == "batched" else None}
+        if form == "batched" and rounds == "device":
+            r["rounds_with_work_and_launched"] = dfrsw.dfr_ensemble_round_counts(ens.eg)
         done = W + K
         if headline and form == "batched":
-            r["kernels"] = {k: dfrsw.dfr_ensemble_timing_read(ens.eg, k) for k in dfrsw.KERNEL_KINDS}
+            r["roofline_kernel"] = dfrsw.dfr_ensemble_timing_read(ens.eg, "jv_arnoldi")
             dfrsw.dfr_ensemble_timing_enable(ens.eg, False)
-            if not args.headline_only:
-                n2 = min(K, max(0, day - done))
-                if n2:
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    for _ in range(n2):
-                        ens.step(opts)
-                    torch.cuda.synchronize()
-                    r["member_steps_per_s_without_events"] = len(members) * n2 / (time.perf_counter() - t1)
-                    done += n2
+            n2 = min(K, max(0, day - done)) if not args.headline_only else 0
+            if n2:
+                # every batched launch bracketed: the time of each kind
+                dfrsw.dfr_ensemble_timing_kinds(ens.eg, None)
+                dfrsw.dfr_ensemble_timing_enable(ens.eg, True)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(n2):
+                    ens.step(opts)
+                torch.cuda.synchronize()
+                wall2 = time.perf_counter() - t1
+                r["kernels"] = {k: dfrsw.dfr_ensemble_timing_read(ens.eg, k) for k in dfrsw.KERNEL_KINDS}
+                r["kernels_steps"], r["kernels_wall_s"] = n2, wall2
+                r["member_steps_per_s_every_launch_evented"] = len(members) * n2 / wall2
+                dfrsw.dfr_ensemble_timing_enable(ens.eg, False)
+                done += n2
         if not args.headline_only:
             for _ in range(max(0, day - done)):
                 ens.step(opts)
@@ -858,11 +876,10 @@ def ensemble_headline_line(args):
     members = inputs.ensemble_members(args.ensemble_members)
     w0 = members[0]
     M = EPI_M[w0.order]
-    ms, n_launch, nodes = h["kernels"]["jv_arnoldi"]
+    ms, n_launch, nodes = h["roofline_kernel"]
     bpn = arnoldi_jv_bytes_per_node(M, 2, prec)
     achieved = bpn * nodes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     prof = "dfr_kernel_batch_krylov_c3_ensemble.txt"
-    kernel_ms_total = sum(v[0] for v in h["kernels"].values())
     out = {
         "metric": METRIC,
         "value": h["member_steps_per_s"],
@@ -887,9 +904,6 @@ def ensemble_headline_line(args):
         "jv_in_step_per_s": h["member_steps_per_s"] * h["jv_per_member_step"],
         "kiops_per_member_step": {k: h[k] for k in ("jv_per_member_step", "substeps_per_member_step",
                                                      "rejections_per_member_step", "expm_per_member_step")},
-        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in h["kernels"].items()},
-        "kernel_launches_per_step": {k: v[1] / args.steps for k, v in h["kernels"].items()},
-        "gpu_busy_fraction": kernel_ms_total / (h["wall_s"] * 1e3),
         "roofline": {
             "kernel": "dfr_kernel_batch: batched complex-FP32 J*v with the fused Arnoldi epilogue, FP32 basis "
                       "and b-columns (every member's tiles in one launch per p group)",
@@ -903,8 +917,13 @@ def ensemble_headline_line(args):
         },
         "ensemble_c3": e,
     }
-    if "member_steps_per_s_without_events" in h:
-        out["member_steps_per_s_without_events"] = h["member_steps_per_s_without_events"]
+    if "kernels" in h:
+        n2 = h["kernels_steps"]
+        out["every_launch_evented"] = {
+            "steps": n2, "member_steps_per_s": h["member_steps_per_s_every_launch_evented"],
+            "kernel_ms_per_step": {k: v[0] / n2 for k, v in h["kernels"].items()},
+            "kernel_launches_per_step": {k: v[1] / n2 for k, v in h["kernels"].items()},
+            "gpu_busy_fraction": sum(v[0] for v in h["kernels"].values()) / (h["kernels_wall_s"] * 1e3)}
     if not args.headline_only:
         f = e["forms"]
         out["at_stated_error"] = {

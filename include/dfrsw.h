@@ -266,9 +266,10 @@ int epi_load(dfr_ctx *ctx, const void *host_buf, size_t nbytes, epi_state **out)
  * iteration (Sec. 4, Eq. 29) is one launch for all members; every member
  * keeps its own KIOPS controller, and members take Arnoldi steps in lockstep
  * rounds with one read-back per round in which some member's sweep reaches
- * its exponential.  Member results equal those of epi_step on the member
- * alone with the same tiles, bit for bit (same kernels, reduction orders and
- * EPI combinations).  All members of
+ * its exponential (dfr_ensemble_set_rounds: or with the decisions taken on
+ * the device).  With host-driven rounds member results equal those of
+ * epi_step on the member alone with the same tiles, bit for bit (same
+ * kernels, reduction orders and EPI combinations).  All members of
  * an epi_ensemble must share order, dt, start-up sub-steps and precision
  * (DFR_E_INVAL otherwise).  q0: host array of n device pointers (3 N_i
  * doubles each, copied).  stats: NULL or n entries.  dfr_ensemble_member
@@ -291,6 +292,30 @@ int epi_ensemble_create(dfr_ensemble *e, int order, double dt, int startup_subst
 int epi_ensemble_step(dfr_ensemble *e, epi_ensemble *x, const kiops_opts *opts, kiops_stats *stats);
 int epi_ensemble_get_state(const epi_ensemble *x, int i, double *q);
 int epi_ensemble_destroy(epi_ensemble *x);
+/* Who drives the ensemble's KIOPS rounds (Sec. 4, Eq. 29: in each round
+ * every member whose evaluation is still running takes one Arnoldi step or
+ * evaluates its small exponential; one launch per kind for all members).
+ *   DFR_ROUNDS_HOST (default): the host takes the decisions from read-backs
+ *     of the exponentials' results and writes each round's call tables.
+ *   DFR_ROUNDS_DEVICE: a planner kernel takes each member's
+ *     controller decisions (the error ratio, acceptance, next sub-step and
+ *     Krylov dimension) on the device and writes the round's call tables
+ *     there; the round (planner and launches) is captured once in a HIP
+ *     graph and replayed, the host only watching a progress word.  A member
+ *     is decided in the round after its exponential, so none waits for a
+ *     read-back; each group of members with the same p runs its products
+ *     and updates on a graph branch of its own.  While ensemble timing is on
+ *     the rounds are launched without the graph, so that events can bracket
+ *     each launch.  At most 256 members.
+ * Each member takes the same operations either way; decisions agree up to
+ * the last bit of the log and pow of the two sides' math libraries.
+ * DFR_E_INVAL for another mode.  dfr_ensemble_round_counts returns the
+ * rounds with work and the rounds launched (those plus the few launched
+ * ahead that found none, at most two per KIOPS call) by the device form,
+ * summed since creation. */
+enum { DFR_ROUNDS_HOST = 0, DFR_ROUNDS_DEVICE = 1 };
+int dfr_ensemble_set_rounds(dfr_ensemble *e, int mode);
+int dfr_ensemble_round_counts(const dfr_ensemble *e, int64_t *planned, int64_t *launched);
 
 /* Concurrent form, for members that need not share order, dt or precision:
  * n_workers host threads take the members (contexts from dfr_create, each
@@ -326,6 +351,10 @@ int dfr_timing_read(dfr_ctx *ctx, int kind, double *total_ms, int64_t *launches)
  * the summed duration is the launches' algorithmic bandwidth. */
 int dfr_ensemble_timing_enable(dfr_ensemble *e, int enable);
 int dfr_ensemble_timing_read(dfr_ensemble *e, int kind, double *total_ms, int64_t *launches, double *nodes);
+/* The kinds the ensemble's timing brackets (bit k: kind k; all by default),
+ * so that a measurement can time one kind and leave the others unbracketed.
+ * DFR_E_INVAL for bits beyond DFR_K_NKINDS. */
+int dfr_ensemble_timing_kinds(dfr_ensemble *e, unsigned mask);
 
 const char *dfr_last_error(void);
 

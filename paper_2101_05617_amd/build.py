@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdfrsw.so")
-SOURCES = ["api.hip", "kernels.hip", "kiops.hip", "batch.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "kernels.hip", "kiops.hip", "batch.hip", "devctl.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DFRSW_ARCH", "gfx950")

@@ -462,7 +462,7 @@ static void free_ctx(Ctx &c) {
 }
 
 bool timing_slot(KTimer *t, int kind, double units, hipEvent_t *start, hipEvent_t *stop) {
-  if (!t->on) return false;
+  if (!t->on || !((t->kinds >> kind) & 1u)) return false;
   if (t->used == t->pool.size()) {
     KTimer::EvPair e{};
     if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {

@@ -7,7 +7,8 @@
 // lockstep rounds, and a round ends with one read-back for all members whose
 // sweep reached its exponential.  Results are those of the single-grid path
 // member by member, bit for bit with the same tiles (same kernels, reduction
-// orders and EPI combinations).
+// orders and EPI combinations).  The rounds can instead be planned on the
+// device and replayed from a HIP graph (kiops_rounds_dev, devctl.hip).
 #include "dfrsw_internal.h"
 
 #include <algorithm>
@@ -34,6 +35,28 @@ struct dfr_ensemble {
   int *d_errv = nullptr, *h_errv = nullptr;
   std::vector<hipEvent_t> evfree;    // events for read-backs in flight
   KTimer tm;                         // event timing of the batched launches (dfr_ensemble_timing_*)
+  int rounds_mode = DFR_ROUNDS_HOST;     // who drives the KIOPS rounds (dfr_ensemble_set_rounds)
+  // device-controlled rounds (devctl.hip): member constants and controller
+  // states, the call tables and counts the planner writes, the progress word
+  // (mapped host memory) and the captured round
+  struct Dev {
+    DevMember *d_mem = nullptr, *h_mem = nullptr;
+    KCtl *d_ctl = nullptr, *h_ctl = nullptr;
+    KHost *d_kh = nullptr;
+    DevCounts *d_cnt = nullptr;
+    unsigned long long *h_prog = nullptr, *d_prog = nullptr;
+    PreCall *d_pre = nullptr;
+    FirstCall *d_first = nullptr;
+    UpdateCall *d_upd = nullptr;
+    ExpmCall *d_expm = nullptr;
+    DfrCall *d_dfr = nullptr;
+    hipStream_t cap = nullptr;       // the capture stream (a graph is captured on its own stream)
+    DevBranches br{};                // the groups' branches of a captured round
+    hipGraph_t graph[2] = {};        // the captured rounds: a call's first round, the others
+    hipGraphExec_t exec[2] = {};
+    DevRound key{};                  // the captured rounds' arguments
+    int64_t planned = 0, launched = 0;   // rounds planned with work / round launches, summed over calls
+  } dev;
 };
 
 struct epi_ensemble {
@@ -123,6 +146,294 @@ static int sync_reset(dfr_ensemble &E) {
   return DFR_OK;
 }
 
+static int dev_alloc(dfr_ensemble &E) {
+  auto &D = E.dev;
+  const size_t n = (size_t)E.n;
+  if (hipMalloc(&D.d_mem, sizeof(DevMember) * n) != hipSuccess ||
+      hipHostMalloc((void **)&D.h_mem, sizeof(DevMember) * n, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&D.d_ctl, sizeof(KCtl) * n) != hipSuccess ||
+      hipHostMalloc((void **)&D.h_ctl, sizeof(KCtl) * n, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&D.d_kh, sizeof(KHost) * n) != hipSuccess || hipMemset(D.d_kh, 0, sizeof(KHost) * n) != hipSuccess ||
+      hipMalloc(&D.d_cnt, sizeof(DevCounts)) != hipSuccess ||
+      hipHostMalloc((void **)&D.h_prog, sizeof(unsigned long long), hipHostMallocCoherent | hipHostMallocMapped) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void **)&D.d_prog, D.h_prog, 0) != hipSuccess ||
+      hipMalloc(&D.d_pre, sizeof(PreCall) * n) != hipSuccess ||
+      hipMalloc(&D.d_first, sizeof(FirstCall) * n) != hipSuccess ||
+      hipMalloc(&D.d_upd, sizeof(UpdateCall) * n) != hipSuccess ||
+      hipMalloc(&D.d_expm, sizeof(ExpmCall) * n) != hipSuccess ||
+      hipMalloc(&D.d_dfr, sizeof(DfrCall) * n) != hipSuccess ||
+      hipStreamCreateWithFlags(&D.cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&D.br.fork, hipEventDisableTiming) != hipSuccess) {
+    set_error("device-controlled rounds: allocation failed");
+    return DFR_E_NOMEM;
+  }
+  for (int ns = 0; ns <= MAX_NS; ++ns)
+    if (hipStreamCreateWithFlags(&D.br.side[ns], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&D.br.join[ns], hipEventDisableTiming) != hipSuccess) {
+      set_error("device-controlled rounds: stream or event creation failed");
+      return DFR_E_HIP;
+    }
+  return DFR_OK;
+}
+
+// workgroups of the device rounds' combination / start and first launches
+static constexpr int DEV_VEC_GRID = 4096;
+
+static void dev_free(dfr_ensemble &E) {
+  auto &D = E.dev;
+  for (int g = 0; g < 2; ++g) {
+    if (D.exec[g]) (void)hipGraphExecDestroy(D.exec[g]);
+    if (D.graph[g]) (void)hipGraphDestroy(D.graph[g]);
+  }
+  if (D.cap) (void)hipStreamDestroy(D.cap);
+  if (D.br.fork) (void)hipEventDestroy(D.br.fork);
+  for (int ns = 0; ns <= MAX_NS; ++ns) {
+    if (D.br.side[ns]) (void)hipStreamDestroy(D.br.side[ns]);
+    if (D.br.join[ns]) (void)hipEventDestroy(D.br.join[ns]);
+  }
+  (void)hipFree(D.d_mem);
+  (void)hipHostFree(D.h_mem);
+  (void)hipFree(D.d_ctl);
+  (void)hipHostFree(D.h_ctl);
+  (void)hipFree(D.d_kh);
+  (void)hipFree(D.d_cnt);
+  (void)hipHostFree(D.h_prog);
+  (void)hipFree(D.d_pre);
+  (void)hipFree(D.d_first);
+  (void)hipFree(D.d_upd);
+  (void)hipFree(D.d_expm);
+  (void)hipFree(D.d_dfr);
+  D = dfr_ensemble::Dev{};
+}
+
+// The rounds of a batched KIOPS evaluation, planned on the device
+// (devctl.hip).  The machines K come initialised (scaling, W, x = b_0); the
+// host hands their constants and controller states to the device, launches
+// rounds, and reads the controller states back at the end.
+static int kiops_rounds_dev(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std::vector<int> &mi,
+                            const kiops_opts &o, bool basis32) {
+  auto &D = E.dev;
+  const int nk = (int)K.size();
+  int rc = DFR_OK;
+  if (nk > 256) {
+    set_error("device-controlled rounds: at most 256 members");
+    return DFR_E_INVAL;
+  }
+  if (!D.d_mem && (rc = dev_alloc(E))) return rc;
+  DevRound r;
+  std::memset(&r, 0, sizeof r);   // padding too: the struct is compared with the captured one
+  r.nmem = nk;
+  r.mem = D.d_mem;
+  r.ctl = D.d_ctl;
+  r.kh = D.d_kh;
+  r.cnt = D.d_cnt;
+  r.progress = D.d_prog;
+  r.pre = D.d_pre;
+  r.first = D.d_first;
+  r.upd = D.d_upd;
+  r.expm = D.d_expm;
+  r.dfr = D.d_dfr;
+  r.fp32 = K[0].fp32 ? 1 : 0;
+  r.basis32 = basis32 ? 1 : 0;
+  r.expm_lds = expm_lds_bytes(o.m_max);
+  int running = 0;
+  for (int a = 0; a < nk; ++a) {
+    const KiopsMachine &k = K[a];
+    const Ctx &c = *k.c;
+    if (c.ga.riemann != DFR_RUSANOV) {
+      set_error("member " + std::to_string(mi[a]) + ": the batched ensemble form uses the Rusanov flux "
+                "(epi_step_concurrent runs members with other fluxes)");
+      return DFR_E_INVAL;
+    }
+    if (k.fp32 != K[0].fp32) {
+      set_error("device-controlled rounds: members differ in precision");
+      return DFR_E_INVAL;
+    }
+    DevMember &d = D.h_mem[a];
+    std::memset(&d, 0, sizeof d);
+    d.n3 = 3 * c.n;
+    d.ns = c.ns;
+    d.esz = basis32 ? (int)sizeof(float) : (int)sizeof(double);
+    d.nblk_vec = vec_blocks(d.n3);
+    d.nblk_upd = std::min(vec_blocks(d.n3), UPDATE_BLOCKS_BATCHED);
+    d.TX = c.ar_tx;
+    d.TY = c.ar_ty;
+    d.ntiles = (int)dfr_num_tiles(&c, true);
+    d.g_ne = c.ne;
+    d.wil = c.w_il ? 1 : 0;
+    d.V = reinterpret_cast<char *>(c.d_V);
+    d.W = c.d_W;
+    d.w = k.w;
+    d.q = k.fp32 ? (const void *)k.q32 : (const void *)k.q;
+    d.pA = c.d_partials;
+    d.pB = c.d_partials2;
+    d.kd = c.d_kd;
+    d.g = E.d_ga + mi[a];
+    d.ops = E.d_ops + mi[a];
+    d.eps = k.eps;
+    d.tau_out = k.tau_out;
+    d.tol = o.tol;
+    d.nu = k.nu;
+    d.mu = k.mu;
+    d.p = k.p;
+    d.n_phi = k.n_phi;
+    d.b0_absent = k.b0_absent ? 1 : 0;
+    d.m_min = k.m_min;
+    d.m_max = k.m_max;
+    d.iop = o.iop;
+    d.max_attempts = o.max_attempts;
+    KCtl &t = D.h_ctl[a];
+    std::memset(&t, 0, sizeof t);
+    t.phase = k.phase == KiopsMachine::DONE ? KC_DONE : KC_BEGIN;
+    t.j = k.j;
+    t.m = k.m;
+    t.ireject = k.ireject;
+    t.old_m = k.old_m;
+    t.attempts = k.attempts;
+    t.t = k.t;
+    t.tau = k.tau;
+    t.beta0 = k.beta0;
+    t.old_tau = k.old_tau;
+    t.old_omega = k.old_omega;
+    running += t.phase != KC_DONE;
+    // the product launch of this member's group, sized for every member active
+    r.grp_n[c.ns]++;
+    r.grp_maxlog[c.ns] += d.ntiles;
+    r.grp_threads[c.ns] = std::max(r.grp_threads[c.ns], std::max(256, ((d.TX * d.TY * c.ns * c.ns + 63) / 64) * 64));
+    r.grp_lds[c.ns] = std::max(r.grp_lds[c.ns], dfr_lds_bytes(c.ns, d.TX, d.TY, k.fp32));
+    r.grid_vec += d.nblk_vec;
+    r.grp_maxupd[c.ns] += d.nblk_upd;
+  }
+  // the combination / start and first launches: a fixed grid whose
+  // workgroups take the blocks in turn (most rounds have few or none)
+  r.grid_vec = std::min(r.grid_vec, DEV_VEC_GRID);
+  if (!running) return DFR_OK;
+  for (int ns = 2, b = 0; ns <= MAX_NS; ++ns) {
+    r.grp_base[ns] = b;
+    b += r.grp_n[ns];
+  }
+  DFR_HIP(hipMemcpyAsync(D.d_mem, D.h_mem, sizeof(DevMember) * nk, hipMemcpyHostToDevice, E.stream));
+  DFR_HIP(hipMemcpyAsync(D.d_ctl, D.h_ctl, sizeof(KCtl) * nk, hipMemcpyHostToDevice, E.stream));
+  DFR_HIP(hipMemsetAsync(D.d_cnt, 0, sizeof(DevCounts), E.stream));
+  *(volatile unsigned long long *)D.h_prog = 0ull;   // no device write pending: calls end synchronised
+  const bool timed = E.tm.on;
+  if (!timed && (!D.exec[0] || std::memcmp(&D.key, &r, sizeof r) != 0)) {
+    // capture both rounds (on the capture stream) and instantiate them
+    for (int g = 0; g < 2; ++g) {
+      if (D.exec[g]) (void)hipGraphExecDestroy(D.exec[g]);
+      if (D.graph[g]) (void)hipGraphDestroy(D.graph[g]);
+      D.exec[g] = nullptr;
+      D.graph[g] = nullptr;
+    }
+    for (int g = 0; g < 2; ++g) {
+      DFR_HIP(hipStreamBeginCapture(D.cap, hipStreamCaptureModeThreadLocal));
+      rc = launch_dev_round(D.cap, r, g == 0, nullptr, &D.br);
+      hipGraph_t gr = nullptr;
+      const hipError_t ec = hipStreamEndCapture(D.cap, &gr);
+      if (rc || ec != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        if (!rc) set_error(std::string("device-controlled rounds: capture failed: ") + hipGetErrorString(ec));
+        return rc ? rc : DFR_E_HIP;
+      }
+      const hipError_t ei = hipGraphInstantiate(&D.exec[g], gr, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        D.exec[g] = nullptr;
+        set_error(std::string("device-controlled rounds: graph instantiation failed: ") + hipGetErrorString(ei));
+        return DFR_E_HIP;
+      }
+      D.graph[g] = gr;
+    }
+    D.key = r;
+  }
+  // Launch rounds: every round the planner has shown to be needed, plus two
+  // ahead so that the device does not wait for the host between rounds; the
+  // rounds launched after the last member has ended find no work.  Each
+  // attempt takes at most m_max + 1 rounds, which bounds the loop.
+  const int64_t cap = (int64_t)(o.max_attempts + 1) * (o.m_max + 2) + 8;
+  const int64_t AHEAD = 2;
+  int64_t launched = 0, target = 1, seen = 0;
+  int idle_polls = 0;
+  for (;;) {
+    while (launched < target + AHEAD && launched < cap) {
+      if (timed) rc = launch_dev_round(E.stream, r, launched == 0, &E.tm, nullptr);
+      else if (hipGraphLaunch(D.exec[launched == 0 ? 0 : 1], E.stream) != hipSuccess) rc = DFR_E_HIP;
+      if (rc) {
+        if (rc == DFR_E_HIP) set_error("device-controlled rounds: launch failed");
+        (void)hipStreamSynchronize(E.stream);
+        return rc;
+      }
+      ++launched;
+    }
+    const unsigned long long pw = *(volatile unsigned long long *)D.h_prog;
+    const int64_t round = (int64_t)(pw >> 32), need = (int64_t)(pw & 0xffffffffull);
+    if (round > seen) {
+      seen = round;
+      idle_polls = 0;
+      if (need == 0) break;
+      target = std::max(target, round + need);
+      if (target >= cap && launched >= cap) {
+        (void)hipStreamSynchronize(E.stream);
+        set_error("kiops: no convergence within max_attempts");
+        return DFR_E_KIOPS;
+      }
+      continue;
+    }
+    // nothing new: look at the stream now and then (a failed launch never
+    // moves the word)
+    if (++idle_polls % 4096 == 0) {
+      const hipError_t q = hipStreamQuery(E.stream);
+      if (q != hipSuccess && q != hipErrorNotReady) {
+        set_error(std::string("HIP error: ") + hipGetErrorString(q));
+        return DFR_E_HIP;
+      }
+      if (q == hipSuccess && *(volatile unsigned long long *)D.h_prog == pw) {
+        set_error("device-controlled rounds: the rounds ended without the planner's last word");
+        return DFR_E_HIP;
+      }
+    }
+  }
+  DevCounts cnt{};
+  DFR_HIP(hipMemcpyAsync(D.h_ctl, D.d_ctl, sizeof(KCtl) * nk, hipMemcpyDeviceToHost, E.stream));
+  DFR_HIP(hipMemcpyAsync(&cnt, D.d_cnt, sizeof(DevCounts), hipMemcpyDeviceToHost, E.stream));
+  DFR_HIP(hipStreamSynchronize(E.stream));
+  D.planned += cnt.last_work;
+  D.launched += launched;
+  double nodes = 0.0;
+  for (int a = 0; a < nk; ++a) {
+    const KCtl &t = D.h_ctl[a];
+    KiopsMachine &k = K[a];
+    k.st.n_matvec = t.n_matvec;
+    k.st.n_substeps = t.n_substeps;
+    k.st.n_rejected = t.n_rejected;
+    k.st.m_last = t.m_last;
+    k.st.happy = t.happy;
+    k.st.n_expm = t.n_expm;
+    nodes += (double)t.n_matvec * (double)k.c->n;
+  }
+  // the products' nodes (the timed launches were recorded with none)
+  if (timed && ((E.tm.kinds >> DFR_K_JV_ARNOLDI) & 1u)) E.tm.t_units[DFR_K_JV_ARNOLDI] += nodes;
+  for (int a = 0; a < nk; ++a) {
+    const KCtl &t = D.h_ctl[a];
+    if (t.phase != KC_FAILED) continue;
+    if (t.err == DFR_E_NONFINITE) {
+      const int le = ensemble_errors(E);   // a latched input error explains it (and names the member)
+      if (le) return le;
+    }
+    if (t.err == KC_E_FIRST_LATE) {
+      set_error("member " + std::to_string(mi[a]) + ": device-controlled rounds: a first Arnoldi step after the "
+                "call's first round");
+      return DFR_E_INVAL;
+    }
+    set_error("member " + std::to_string(mi[a]) + ": kiops: " +
+              (t.err == DFR_E_NONFINITE ? "non-finite Krylov quantities" : "no convergence within max_attempts "
+                                                                            "(or the step size collapsed)"));
+    return t.err;
+  }
+  return DFR_OK;
+}
+
 // KIOPS for machines K (K[a] belongs to member mi[a]), all at once
 // basis32: the members keep their Krylov bases in FP32 (with FP32 products)
 static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std::vector<int> &mi,
@@ -202,6 +513,7 @@ static int kiops_batch(dfr_ensemble &E, std::vector<KiopsMachine> &K, const std:
   }
   if ((rc = launch_wil_batch(E.stream, E.stage, wil))) return rc;
   if ((rc = launch_vec_batch(E.stream, E.stage, VB_AXPBY, wc))) return rc;
+  if (E.rounds_mode == DFR_ROUNDS_DEVICE) return kiops_rounds_dev(E, K, mi, o, basis32);
   const size_t lds = expm_lds_bytes(o.m_max);
 
   // Rounds.  Every member that is not waiting for a decision takes one
@@ -448,6 +760,7 @@ static void free_ensemble(dfr_ensemble *E) {
   (void)hipFree(E->d_errv);
   (void)hipHostFree(E->h_errv);
   for (hipEvent_t ev : E->evfree) (void)hipEventDestroy(ev);
+  dev_free(*E);
   delete E;
 }
 
@@ -525,12 +838,37 @@ int dfr_ensemble_timing_enable(dfr_ensemble *E, int enable) {
   return DFR_OK;
 }
 
+int dfr_ensemble_timing_kinds(dfr_ensemble *E, unsigned mask) {
+  if (!E || (mask >> DFR_K_NKINDS) != 0u) {
+    set_error("dfr_ensemble_timing_kinds: a mask of the DFR_K_* kinds");
+    return DFR_E_INVAL;
+  }
+  E->tm.kinds = mask;
+  return DFR_OK;
+}
+
 int dfr_ensemble_timing_read(dfr_ensemble *E, int kind, double *total_ms, int64_t *launches, double *nodes) {
   if (!E || kind < 0 || kind >= DFR_K_NKINDS || !total_ms || !launches) return DFR_E_INVAL;
   timing_fold(E->tm);
   *total_ms = E->tm.t_ms[kind];
   *launches = E->tm.t_n[kind];
   if (nodes) *nodes = E->tm.t_units[kind];
+  return DFR_OK;
+}
+
+int dfr_ensemble_set_rounds(dfr_ensemble *E, int mode) {
+  if (!E || (mode != DFR_ROUNDS_HOST && mode != DFR_ROUNDS_DEVICE)) {
+    set_error("dfr_ensemble_set_rounds: mode is DFR_ROUNDS_HOST or DFR_ROUNDS_DEVICE");
+    return DFR_E_INVAL;
+  }
+  E->rounds_mode = mode;
+  return DFR_OK;
+}
+
+int dfr_ensemble_round_counts(const dfr_ensemble *E, int64_t *planned, int64_t *launched) {
+  if (!E || !planned || !launched) return DFR_E_INVAL;
+  *planned = E->dev.planned;
+  *launched = E->dev.launched;
   return DFR_OK;
 }
 

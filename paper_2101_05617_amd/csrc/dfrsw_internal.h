@@ -167,6 +167,15 @@ struct CombineCall {
   const struct KDev *kd;
   double *x;
 };
+struct PreCall {          // device-controlled rounds: combination and / or start (arnoldi_pre_batch)
+  int b0, nblk;
+  int64_t n3;
+  int comb, start;        // the accepted sub-step's combination; the next sub-step's start vector
+  void *V;                // the member's basis (slot 0 is the start vector)
+  struct KDev *kd;
+  double *x;              // the result: written by the combination, read by the start
+  double *pout;           // the start's partial squared norms, one per workgroup
+};
 struct WilCall {         // W = nu [cols] interleaved four per value (a member's b-columns)
   int b0, nblk;
   int64_t n;
@@ -191,6 +200,54 @@ struct AxpbyCall {       // out = a x + b y (y may be NULL); also norms, copies,
   double a, b;
   const double *x, *y;
   double *out;
+};
+
+// Device-controlled rounds of the batched form.  A planner kernel takes each
+// member's controller decisions on the device and writes the round's call
+// tables and their counts into device memory; the batched kernels read the
+// counts from there (DevCounts), so that a round is a fixed sequence of
+// launches, captured once in a HIP graph and replayed.
+struct DevCounts {
+  int n_pre, nb_pre;               // calls and blocks of each launch
+  int n_first, nb_first;
+  int n_expm, pad0;
+  int dfr[MAX_NS + 1][2];          // the products, by number of GL points: calls, logical blocks
+  int upd[MAX_NS + 1][2];          // the updates, by the members' number of GL points: calls, workgroups
+  int last_work;                   // the last round with any work
+  int round;                       // rounds planned so far
+};
+// The planner's progress word, mirrored to mapped host memory in one 64-bit
+// store: rounds planned (high half) and the rounds certainly still needed
+// after the last one (low half; 0 once every member has ended).
+__host__ __device__ inline unsigned long long dev_progress(int round, int need) {
+  return ((unsigned long long)(unsigned)round << 32) | (unsigned)need;
+}
+// one member's constants for one KIOPS call (device copy)
+struct DevMember {
+  int64_t n3;
+  int ns, esz;                     // GL points; bytes per basis value (4: FP32 basis)
+  int nblk_vec, nblk_upd, ntiles;  // workgroups of its vector launches and update; product tiles
+  int TX, TY, g_ne, wil;
+  char *V;                         // basis slots of 3N values
+  double *W, *w;                   // b-columns; the result
+  const void *q;                   // the state the product reads (FP32 copy with FP32 products)
+  double *pA, *pB;                 // partial sums: product -> update, update / start -> product
+  struct KDev *kd;
+  const GridArgs *g;
+  const Ops1D *ops;
+  double eps, tau_out, tol, nu, mu;
+  int p, n_phi, b0_absent, m_min, m_max, iop, max_attempts, pad1;
+};
+// one member's controller state (the host KiopsMachine's fields, on the device)
+enum { KC_BEGIN = 0, KC_SWEEP = 1, KC_EXPM = 2, KC_WAIT = 3, KC_DONE = 4, KC_FAILED = 5 };
+constexpr int KC_E_FIRST_LATE = -100;   // planner: a first Arnoldi step after a call's first round
+struct KCtl {
+  int phase;                       // 0 begin, 1 sweep, 2 exponential, 3 waiting for its result, 4 done, 5 failed
+  int j, m, j_sweep, skipped, ireject, old_m, attempts;
+  int npA, npB, err, pad;
+  double t, tau, beta0, old_tau, old_omega;
+  double ybot[MAX_P];
+  int n_matvec, n_substeps, n_rejected, m_last, happy, n_expm;
 };
 
 // Device-side KIOPS state (one per context).
@@ -233,6 +290,7 @@ struct HostMail {
 // the caller chooses (the batched DFR launches record their nodes).
 struct KTimer {
   bool on = false;
+  unsigned kinds = ~0u;            // the kinds bracketed while on (bit k: kind k)
   struct EvPair {
     hipEvent_t a, b;
     int kind;
@@ -422,6 +480,48 @@ int launch_update_batch(hipStream_t s, Stage &st, bool basis32, std::vector<Upda
 int launch_start_batch(hipStream_t s, Stage &st, bool basis32, std::vector<StartCall> &calls);
 int launch_combine_batch(hipStream_t s, Stage &st, bool basis32, std::vector<CombineCall> &calls);
 int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, size_t lds);
+// the device-controlled round (devctl.hip): its launches, on stream s, with
+// every table and count in device memory (capturable); grids sized for every
+// member active
+struct DevRound {
+  int nmem;                        // members (at most 256: the planner's workgroup)
+  const DevMember *mem;            // device
+  KCtl *ctl;                       // device
+  KHost *kh;                       // device: the exponentials' results, per member
+  DevCounts *cnt;                  // device
+  unsigned long long *progress;    // device address of mapped host memory (dev_progress)
+  PreCall *pre;                    // device tables, nmem entries each
+  FirstCall *first;
+  UpdateCall *upd;                 // nmem entries, grouped like dfr
+  ExpmCall *expm;
+  DfrCall *dfr;                    // nmem entries, grouped by number of GL points
+  int grid_vec;                    // workgroups of the combination / start and first launches (blocks in turn)
+  int grp_base[MAX_NS + 1];        // first entry of each group in dfr and upd
+  int grp_n[MAX_NS + 1];           // members of each group (0: no launch)
+  int grp_maxlog[MAX_NS + 1];      // logical blocks of each group with every member active
+  int grp_maxupd[MAX_NS + 1];      // update workgroups of each group with every member active
+  int grp_threads[MAX_NS + 1];
+  size_t grp_lds[MAX_NS + 1];
+  size_t expm_lds;
+  int fp32, basis32;
+};
+// first: the first round of a KIOPS call (the only one with first Arnoldi
+// steps of a zero top block).  tm: NULL, or a timer whose events bracket
+// each launch.  br: NULL (every launch on s), or streams and events with
+// which each group's product and update run on a branch of their own
+// (forked from s after the first steps, joined before the exponentials;
+// for capture into a graph)
+struct DevBranches {
+  hipStream_t side[MAX_NS + 1];
+  hipEvent_t fork, join[MAX_NS + 1];
+};
+int launch_dev_round(hipStream_t s, const DevRound &r, bool first, KTimer *tm, const DevBranches *br);
+enum { KD_PRE = 0, KD_FIRST = 1, KD_UPDATE = 2 };
+int launch_dfr_batch_dev(hipStream_t s, int ns, bool fp32, bool basis32, const DfrCall *calls, const int *dc,
+                         int grid, int threads, size_t lds, KTimer *tm);
+int launch_krylov_dev(hipStream_t s, int kind, bool basis32, const void *calls, const int *dc, int grid,
+                      KTimer *tm);
+int launch_expm_dev(hipStream_t s, const ExpmCall *calls, const int *dc, int grid, size_t lds, KTimer *tm);
 enum { VB_AXPBY = 0, VB_TO_F32 = 1, VB_NORM2 = 2, VB_SUM = 3, VB_CHECK = 4 };
 int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls);
 int launch_wil_batch(hipStream_t s, Stage &st, std::vector<WilCall> &calls);   // W of several members, one launch

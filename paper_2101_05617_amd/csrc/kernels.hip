@@ -104,10 +104,14 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
 
 // XCD-aware logical block: consecutive logical blocks land on the same XCD
 // (the dispatcher places block b on XCD b % 8), so neighbouring elements
-// share an L2.
+// share an L2.  The stride per XCD follows the logical count, not the grid,
+// so a grid larger than 8 ceil(nlogical / 8) (sized for counts known only
+// on the device) still spreads the work over all eight XCDs; the blocks
+// beyond it idle.
 __device__ __forceinline__ int64_t logical_block(int64_t nlogical) {
-  const int64_t b = blockIdx.x, per = (gridDim.x + 7) / 8;
-  int64_t lb = (b % 8) * per + b / 8;
+  const int64_t b = blockIdx.x, per = (nlogical + 7) / 8;
+  if (b >= 8 * per) return -1;
+  const int64_t lb = (b % 8) * per + b / 8;
   return lb < nlogical ? lb : -1;
 }
 
@@ -977,11 +981,17 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 }
 
 // several grids (ensemble members) in one launch: member m owns the logical
-// blocks [b0, b0 + ntiles); Rusanov fluxes; TV: the basis type
+// blocks [b0, b0 + ntiles); Rusanov fluxes; TV: the basis type.  dc: NULL,
+// or the number of calls and of logical blocks in device memory (written by
+// the round planner; the grid is sized for every member)
 template <int NS, typename T, typename TQ, bool CS, bool AR, typename TV>
 __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCall *__restrict__ calls, int ncalls,
-                                                                     int nlogical) {
+                                                                     int nlogical, const int *__restrict__ dc) {
   __shared__ int s_m;
+  if (dc) {
+    ncalls = dc[0];
+    nlogical = dc[1];
+  }
   const int lbg = (int)logical_block(nlogical);
   if (lbg < 0) return;   // uniform
   for (int t = threadIdx.x; t < ncalls; t += blockDim.x) {
@@ -1002,15 +1012,18 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel_batch(const DfrCal
 // (member m owns the workgroups [b0, b0 + nblk); find_call locates it).
 
 template <typename C>
-__device__ __forceinline__ int find_call(const C *__restrict__ calls, int ncalls) {
+__device__ __forceinline__ int find_call_at(const C *__restrict__ calls, int ncalls, int b) {
   __shared__ int s_m;
-  const int b = blockIdx.x;
   for (int t = threadIdx.x; t < ncalls; t += blockDim.x) {
     const int b0 = calls[t].b0;
     if (b >= b0 && b < b0 + calls[t].nblk) s_m = t;
   }
   __syncthreads();
   return __builtin_amdgcn_readfirstlane(s_m);
+}
+template <typename C>
+__device__ __forceinline__ int find_call(const C *__restrict__ calls, int ncalls) {
+  return find_call_at(calls, ncalls, (int)blockIdx.x);
 }
 
 // first Arnoldi step of a sub-step whose top block is identically zero:
@@ -1045,10 +1058,19 @@ template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_first_kernel(int64_t n3, const ArnoldiArgs ar, TV *out) {
   arnoldi_first_body(blockIdx.x, gridDim.x, n3, ar, out);
 }
+// dc: NULL (one workgroup per block of the calls), or the number of calls
+// and blocks in device memory; then each workgroup takes the blocks
+// blockIdx.x, blockIdx.x + gridDim.x, ... (a grid of fixed size for any count)
 template <typename TV>
-__global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__restrict__ calls, int ncalls) {
-  const FirstCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_first_body(blockIdx.x - c.b0, c.nblk, c.n3, c.ar, static_cast<TV *>(c.out));
+__global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__restrict__ calls, int ncalls,
+                                                  const int *__restrict__ dc) {
+  const int total = dc ? dc[1] : (int)gridDim.x;
+  if (dc) ncalls = dc[0];
+  for (int lb = blockIdx.x; lb < total; lb += gridDim.x) {
+    __syncthreads();   // the previous block's use of shared memory
+    const FirstCall &c = calls[find_call_at(calls, ncalls, lb)];
+    arnoldi_first_body(lb - c.b0, c.nblk, c.n3, c.ar, static_cast<TV *>(c.out));
+  }
 }
 
 // Gram-Schmidt step.  Prologue: the inner products h_{j,j}, h_{j-1,j} (top
@@ -1184,7 +1206,12 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j
   arnoldi_update_body(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
 }
 template <typename TV>
-__global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls) {
+__global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls,
+                                                  const int *__restrict__ dc) {
+  if (dc) {   // counts in device memory: calls, workgroups
+    ncalls = dc[0];
+    if ((int)blockIdx.x >= dc[1]) return;
+  }
   const UpdateCall &c = calls[find_call(calls, ncalls)];
   arnoldi_update_body(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, static_cast<TV *>(c.w), static_cast<const TV *>(c.vj),
                       static_cast<const TV *>(c.vprev), c.pin, c.np_in, c.pout, c.kd);
@@ -1255,6 +1282,25 @@ template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_combine_batch(const CombineCall *__restrict__ calls, int ncalls) {
   const CombineCall &c = calls[find_call(calls, ncalls)];
   arnoldi_combine_body(blockIdx.x - c.b0, c.nblk, c.n3, static_cast<const TV *>(c.V), c.n3, c.kd, c.x);
+}
+
+// The device-controlled rounds' combination and start in one launch: per
+// member the accepted sub-step's combination (x = beta V E[:, 0]), the next
+// sub-step's start vector from x, or both.  The two share the element
+// mapping (block blk of nblk, grid-stride), so each thread reads back only
+// the x values it wrote, and reads its entries of basis slot 0 before the
+// start overwrites them: the results are those of the two kernels in turn.
+// Counts in device memory (dc: calls, blocks); fixed grid, blocks in turn.
+template <typename TV>
+__global__ __launch_bounds__(BLOCK) void arnoldi_pre_batch(const PreCall *__restrict__ calls, const int *__restrict__ dc) {
+  const int ncalls = dc[0], total = dc[1];
+  for (int lb = blockIdx.x; lb < total; lb += gridDim.x) {
+    __syncthreads();   // the previous block's use of shared memory
+    const PreCall &c = calls[find_call_at(calls, ncalls, lb)];
+    const int blk = lb - c.b0;
+    if (c.comb) arnoldi_combine_body(blk, c.nblk, c.n3, static_cast<const TV *>(c.V), c.n3, c.kd, c.x);
+    if (c.start) arnoldi_start_body(blk, c.nblk, c.n3, c.x, static_cast<TV *>(c.V), c.pout, c.kd);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1474,8 +1520,9 @@ __global__ __launch_bounds__(EXPM_BLOCK) void expm_kernel(KDev *kd, double tau, 
                                                           int np_in, double tol, unsigned *seq_out, unsigned seq) {
   expm_body(kd, tau, res, jfin, pin, np_in, tol, seq_out, seq);
 }
-// one workgroup per member
-__global__ __launch_bounds__(EXPM_BLOCK) void expm_batch(const ExpmCall *__restrict__ calls) {
+// one workgroup per member; dc: NULL, or the number of calls in device memory
+__global__ __launch_bounds__(EXPM_BLOCK) void expm_batch(const ExpmCall *__restrict__ calls, const int *__restrict__ dc) {
+  if (dc && (int)blockIdx.x >= dc[0]) return;
   const ExpmCall &c = calls[blockIdx.x];
   expm_body(c.kd, c.tau, c.res, c.jfin, c.pin, c.np_in, c.tol, nullptr, 0u);
 }
@@ -2112,7 +2159,7 @@ static int launch_dfr_batch_ns(hipStream_t s, Stage &st, std::vector<DfrCall> &c
   KTimer *tm = st.timer;
   return stage_launch(st, [=]() -> int {
     timed_launch(tm, kind, nodes, s, dfr_kernel_batch<NS, T, TQ, CS, AR, TV>, dim3(grid), dim3(threads), lds,
-                 (const DfrCall *)d, n, nlog);
+                 (const DfrCall *)d, n, nlog, (const int *)nullptr);
     DFR_HIP(hipGetLastError());
     return DFR_OK;
   });
@@ -2166,13 +2213,30 @@ static int launch_calls(hipStream_t s, Stage &st, std::vector<C> &calls, K kerne
   });
 }
 
+// the same for the Krylov kernels, which also take device-side counts (NULL here)
+template <typename C, typename K>
+static int launch_calls_k(hipStream_t s, Stage &st, std::vector<C> &calls, K kernel, int kind = DFR_K_OTHER) {
+  if (calls.empty()) return DFR_OK;
+  const int nb = set_b0(calls);
+  void *d = nullptr;
+  int rc = stage_put(st, s, calls.data(), sizeof(C) * calls.size(), &d);
+  if (rc) return rc;
+  const int n = (int)calls.size();
+  KTimer *tm = st.timer;
+  return stage_launch(st, [=]() -> int {
+    timed_launch(tm, kind, 0.0, s, kernel, dim3(nb), dim3(BLOCK), 0, (const C *)d, n, (const int *)nullptr);
+    DFR_HIP(hipGetLastError());
+    return DFR_OK;
+  });
+}
+
 int launch_first_batch(hipStream_t s, Stage &st, bool basis32, std::vector<FirstCall> &calls) {
-  return basis32 ? launch_calls(s, st, calls, arnoldi_first_batch<float>)
-                 : launch_calls(s, st, calls, arnoldi_first_batch<double>);
+  return basis32 ? launch_calls_k(s, st, calls, arnoldi_first_batch<float>)
+                 : launch_calls_k(s, st, calls, arnoldi_first_batch<double>);
 }
 int launch_update_batch(hipStream_t s, Stage &st, bool basis32, std::vector<UpdateCall> &calls) {
-  return basis32 ? launch_calls(s, st, calls, arnoldi_update_batch<float>, DFR_K_UPDATE)
-                 : launch_calls(s, st, calls, arnoldi_update_batch<double>, DFR_K_UPDATE);
+  return basis32 ? launch_calls_k(s, st, calls, arnoldi_update_batch<float>, DFR_K_UPDATE)
+                 : launch_calls_k(s, st, calls, arnoldi_update_batch<double>, DFR_K_UPDATE);
 }
 int launch_start_batch(hipStream_t s, Stage &st, bool basis32, std::vector<StartCall> &calls) {
   return basis32 ? launch_calls(s, st, calls, arnoldi_start_batch<float>)
@@ -2191,10 +2255,83 @@ int launch_expm_batch(hipStream_t s, Stage &st, std::vector<ExpmCall> &calls, si
   const unsigned n = (unsigned)calls.size();
   KTimer *tm = st.timer;
   return stage_launch(st, [=]() -> int {
-    timed_launch(tm, DFR_K_EXPM, 0.0, s, expm_batch, dim3(n), dim3(EXPM_BLOCK), lds, (const ExpmCall *)d);
+    timed_launch(tm, DFR_K_EXPM, 0.0, s, expm_batch, dim3(n), dim3(EXPM_BLOCK), lds, (const ExpmCall *)d,
+                 (const int *)nullptr);
     DFR_HIP(hipGetLastError());
     return DFR_OK;
   });
+}
+
+// The device-controlled round's launches: tables and counts in device
+// memory (dc), grids sized by the caller for every member active.  tm: NULL
+// (the launches may be captured into a graph), or a timer to bracket each
+// launch with events (units 0: the caller adds the nodes afterwards).
+template <int NS>
+static void launch_dfr_dev_ns(hipStream_t s, bool fp32, bool basis32, const DfrCall *calls, const int *dc, int grid,
+                              int threads, size_t lds, KTimer *tm) {
+  const int k = DFR_K_JV_ARNOLDI;
+  if (fp32 && basis32)
+    timed_launch(tm, k, 0.0, s, dfr_kernel_batch<NS, float, float, true, true, float>, dim3(grid), dim3(threads), lds,
+                 calls, 0, 0, dc);
+  else if (fp32)
+    timed_launch(tm, k, 0.0, s, dfr_kernel_batch<NS, float, float, true, true, double>, dim3(grid), dim3(threads),
+                 lds, calls, 0, 0, dc);
+  else
+    timed_launch(tm, k, 0.0, s, dfr_kernel_batch<NS, double, double, true, true, double>, dim3(grid), dim3(threads),
+                 lds, calls, 0, 0, dc);
+}
+
+int launch_dfr_batch_dev(hipStream_t s, int ns, bool fp32, bool basis32, const DfrCall *calls, const int *dc,
+                         int grid, int threads, size_t lds, KTimer *tm) {
+  if (basis32 && !fp32) {
+    set_error("an FP32 basis goes with the complex-FP32 Krylov-form product only");
+    return DFR_E_INVAL;
+  }
+  switch (ns) {
+    case 2: launch_dfr_dev_ns<2>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    case 3: launch_dfr_dev_ns<3>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    case 4: launch_dfr_dev_ns<4>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    case 5: launch_dfr_dev_ns<5>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    case 6: launch_dfr_dev_ns<6>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    case 7: launch_dfr_dev_ns<7>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    case 8: launch_dfr_dev_ns<8>(s, fp32, basis32, calls, dc, grid, threads, lds, tm); break;
+    default: set_error("unsupported number of GL points"); return DFR_E_INVAL;
+  }
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+template <typename TV>
+static void launch_krylov_dev_t(hipStream_t s, int kind, const void *calls, const int *dc, int grid, KTimer *tm) {
+  switch (kind) {
+    case KD_PRE:
+      timed_launch(tm, DFR_K_OTHER, 0.0, s, arnoldi_pre_batch<TV>, dim3(grid), dim3(BLOCK), 0,
+                   (const PreCall *)calls, dc);
+      break;
+    case KD_FIRST:
+      timed_launch(tm, DFR_K_OTHER, 0.0, s, arnoldi_first_batch<TV>, dim3(grid), dim3(BLOCK), 0,
+                   (const FirstCall *)calls, 0, dc);
+      break;
+    case KD_UPDATE:
+      timed_launch(tm, DFR_K_UPDATE, 0.0, s, arnoldi_update_batch<TV>, dim3(grid), dim3(BLOCK), 0,
+                   (const UpdateCall *)calls, 0, dc);
+      break;
+    default: break;
+  }
+}
+
+int launch_krylov_dev(hipStream_t s, int kind, bool basis32, const void *calls, const int *dc, int grid,
+                      KTimer *tm) {
+  if (basis32) launch_krylov_dev_t<float>(s, kind, calls, dc, grid, tm);
+  else launch_krylov_dev_t<double>(s, kind, calls, dc, grid, tm);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
+
+int launch_expm_dev(hipStream_t s, const ExpmCall *calls, const int *dc, int grid, size_t lds, KTimer *tm) {
+  timed_launch(tm, DFR_K_EXPM, 0.0, s, expm_batch, dim3(grid), dim3(EXPM_BLOCK), lds, calls, dc);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
 }
 
 int launch_vec_batch(hipStream_t s, Stage &st, int kind, std::vector<AxpbyCall> &calls) {

@@ -108,7 +108,10 @@ def lib():
             "dfr_autotune": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "dfr_timing_enable": (i, [vp, i]),
             "dfr_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64)]),
+            "dfr_ensemble_set_rounds": (i, [vp, i]),
+            "dfr_ensemble_round_counts": (i, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
             "dfr_ensemble_timing_enable": (i, [vp, i]),
+            "dfr_ensemble_timing_kinds": (i, [vp, ctypes.c_uint]),
             "dfr_ensemble_timing_read": (i, [vp, i, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(d)]),
             "dfr_last_error": (ctypes.c_char_p, []),
         }
@@ -126,7 +129,8 @@ def exported_symbols():
             "epi_num_steps", "epi_destroy", "epi_save", "epi_load", "epi_step_concurrent", "dfr_ensemble_create", "dfr_ensemble_destroy",
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
             "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_diagnostics", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
-            "dfr_timing_read", "dfr_ensemble_timing_enable", "dfr_ensemble_timing_read", "dfr_last_error"]
+            "dfr_timing_read", "dfr_ensemble_set_rounds", "dfr_ensemble_round_counts", "dfr_ensemble_timing_enable",
+            "dfr_ensemble_timing_read", "dfr_ensemble_timing_kinds", "dfr_last_error"]
 
 
 def _check(rc):
@@ -467,8 +471,30 @@ def dfr_ensemble_autotune(eg: EnsembleGrid, prec="fp64"):
     return [dfr_get_krylov_tile(m) for m in eg.members]
 
 
+ROUNDS = {"host": 0, "device": 1}
+
+
+def dfr_ensemble_set_rounds(eg: EnsembleGrid, mode="host"):
+    """Who drives the KIOPS rounds of epi_ensemble_step: "host" (the default)
+    or "device" (a planner kernel, the round replayed from a HIP graph)."""
+    _check(lib().dfr_ensemble_set_rounds(eg.handle, ROUNDS.get(mode, mode)))
+
+
+def dfr_ensemble_round_counts(eg: EnsembleGrid):
+    """(rounds with work, rounds launched) of the device-driven form so far."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().dfr_ensemble_round_counts(eg.handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 def dfr_ensemble_timing_enable(eg: EnsembleGrid, enable=True):
     _check(lib().dfr_ensemble_timing_enable(eg.handle, int(bool(enable))))
+
+
+def dfr_ensemble_timing_kinds(eg: EnsembleGrid, kinds=None):
+    """Bracket only the given kinds (names or codes; None: all) with events."""
+    mask = (1 << len(KERNEL_KINDS)) - 1 if kinds is None else sum(1 << KERNEL_KINDS.get(k, k) for k in kinds)
+    _check(lib().dfr_ensemble_timing_kinds(eg.handle, mask))
 
 
 def dfr_ensemble_timing_read(eg: EnsembleGrid, kind):

@@ -22,9 +22,11 @@ class Ensemble:
     """Members built from `inputs.Workload`s (same order, dt and start-up for
     the batched form); `prec` is "fp64", "fp32_jv" or "fp32_jv_basis32".  autotune: pick each
     member's tiles by timing (dfr_autotune).  frames: optional per-member
-    (P, B1, B2) node frames for the initial states (default: the library's)."""
+    (P, B1, B2) node frames for the initial states (default: the library's).
+    rounds: who drives the batched form's KIOPS rounds, "device" or "host"
+    (dfr_ensemble_set_rounds)."""
 
-    def __init__(self, workloads, prec="fp32_jv", form="batched", autotune=True, frames=None):
+    def __init__(self, workloads, prec="fp32_jv", form="batched", autotune=True, frames=None, rounds="host"):
         import torch
         self.prec, self.form = prec, form
         self.workloads = list(workloads)
@@ -34,6 +36,7 @@ class Ensemble:
             self.eg = dfrsw.dfr_ensemble_create([dict(ne=w.ne, p=w.p, radius=c[0], omega=c[1], gravity=c[2])
                                                  for w in self.workloads for c in [w.constants()]])
             self.grids = self.eg.members
+            dfrsw.dfr_ensemble_set_rounds(self.eg, rounds)
         else:
             for w in self.workloads:
                 s = torch.cuda.Stream() if form == "concurrent" else torch.cuda.current_stream()

@@ -47,3 +47,6 @@ def test_constants_match_header():
     for name in ("DFR_FP64", "DFR_FP32_JV", "DFR_FP32_JV_BASIS32"):
         v = re.search(name + r"\s*=\s*(\d+)", src)
         assert v and int(v.group(1)) == getattr(dfrsw, name)
+    for name, key in (("DFR_ROUNDS_HOST", "host"), ("DFR_ROUNDS_DEVICE", "device")):
+        v = re.search(name + r"\s*=\s*(\d+)", src)
+        assert v and int(v.group(1)) == dfrsw.ROUNDS[key]

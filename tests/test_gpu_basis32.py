@@ -137,7 +137,7 @@ def test_batched_ensemble_fp32_basis_matches_members_run_alone():
     opts = dfrsw.kiops_opts(tol=1e-10, m_max=32)
     ref64 = Ensemble(ws, prec="fp64", form="sequential", autotune=False)
     seq = Ensemble(ws, prec="fp32_jv_basis32", form="sequential", autotune=False)
-    bat = Ensemble(ws, prec="fp32_jv_basis32", form="batched", autotune=False)
+    bat = Ensemble(ws, prec="fp32_jv_basis32", form="batched", autotune=False, rounds="host")
     try:
         for _ in range(5):
             ref64.step(opts)

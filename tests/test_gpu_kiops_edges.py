@@ -150,6 +150,7 @@ def test_happy_breakdowns_in_the_batched_form():
     kopt = dict(tol=1e-10, m_max=24)
     opts = dfrsw.kiops_opts(**kopt)
     eg = dfrsw.dfr_ensemble_create(descs)
+    dfrsw.dfr_ensemble_set_rounds(eg, "host")   # bit for bit with the members run alone
     x = dfrsw.epi_ensemble_create(eg, 4, C0.dt_nd, [to_dev(q) for q in states], startup_substeps=2)
     alone = [dfrsw.Grid(d["ne"], d["p"], 1.0, d["omega"], g) for d in descs]
     sts = [dfrsw.epi_create(a, 4, C0.dt_nd, to_dev(q), startup_substeps=2) for a, q in zip(alone, states)]
