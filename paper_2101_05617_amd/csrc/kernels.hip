@@ -1081,11 +1081,14 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__
 // scales sigma_k kept in KDev.  The first UNROLL elements of each thread are
 // read before the prologue, in flight during its reductions.  With !two the
 // third stream rereads v~_j, multiplied by a zero coefficient.
-template <typename TV>
+template <typename TV, int UNROLL>
 __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n3, int j, int p, TV *w,
                                                     const TV *vj, const TV *vprev, const double *pin,
                                                     int np_in, double *pout, KDev *kd) {
-  constexpr int UNROLL = 4;
+  // UNROLL grid strides per chunk: a chunk's loads are issued together (one
+  // memory round trip per chunk); the first chunk before the reduction.  A
+  // single grid takes up to 1024 workgroups and needs few strides (4); a
+  // member of a batch, at most 256 workgroups, more (8)
   static_assert(BLOCK == 256, "one virtual lane of the fixed-order reduction per thread");
   __shared__ double red[512];
   const bool two = (j >= 1) && (vprev != nullptr);
@@ -1105,13 +1108,13 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
   }
   __builtin_amdgcn_sched_barrier(0);
   const TV *vp2 = two ? vprev : vj;
-  double xw[UNROLL], xv[UNROLL], xp[UNROLL];
+  TV xw[UNROLL], xv[UNROLL], xp[UNROLL];
 #pragma unroll
   for (int u = 0; u < UNROLL; ++u) {
     const int64_t i = i0 + u * gs < n3 ? i0 + u * gs : n3 - 1;
-    xw[u] = (double)w[i];
-    xv[u] = (double)vj[i];
-    xp[u] = (double)vp2[i];
+    xw[u] = w[i];
+    xv[u] = vj[i];
+    xp[u] = vp2[i];
   }
   // the bottom blocks b_j, b_{j-1} and the scales, read ahead of the
   // reduction's barriers (whole rows of MAX_P values: no branch on p)
@@ -1178,23 +1181,29 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
   }
   const double ca = hjj * sgj;
   const double cb = two ? hpj * sgp : 0.0;
+  // the values in increasing i, chunk by chunk (the order of acc's sum is
+  // that of a plain grid-stride loop)
   double acc = 0.0;
+  for (int64_t base = i0;;) {
 #pragma unroll
-  for (int u = 0; u < UNROLL; ++u) {
-    const int64_t i = i0 + u * gs;
-    if (i < n3) {
-      // the norm is that of the vector as stored (rounded to the basis type)
-      const TV x = (TV)((xw[u] - ca * xv[u]) - cb * xp[u]);
-      if (!happy) w[i] = x;
-      acc += (double)x * (double)x;
+    for (int u = 0; u < UNROLL; ++u) {
+      const int64_t i = base + u * gs;
+      if (i < n3) {
+        // the norm is that of the vector as stored (rounded to the basis type)
+        const TV x = (TV)(((double)xw[u] - ca * (double)xv[u]) - cb * (double)xp[u]);
+        if (!happy) w[i] = x;
+        acc += (double)x * (double)x;
+      }
     }
-  }
-  for (int64_t i = i0 + UNROLL * gs; i < (happy ? 0 : n3); i += gs) {
-    double y = (double)w[i] - ca * (double)vj[i];
-    if (two) y -= cb * (double)vprev[i];
-    const TV x = (TV)y;
-    w[i] = x;
-    acc += (double)x * (double)x;
+    base += UNROLL * gs;
+    if (happy || base >= n3) break;
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int64_t i = base + u * gs < n3 ? base + u * gs : n3 - 1;
+      xw[u] = w[i];
+      xv[u] = vj[i];
+      xp[u] = vp2[i];
+    }
   }
   const double b = block_sum(acc, red);
   if (!happy && threadIdx.x == 0) pout[blk] = b;
@@ -1203,7 +1212,7 @@ template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j, int p, TV *w, const TV *vj,
                                                                const TV *vprev, const double *pin, int np_in,
                                                                double *pout, KDev *kd) {
-  arnoldi_update_body(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
+  arnoldi_update_body<TV, 4>(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
 }
 template <typename TV>
 __global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls,
@@ -1213,7 +1222,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *
     if ((int)blockIdx.x >= dc[1]) return;
   }
   const UpdateCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_update_body(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, static_cast<TV *>(c.w), static_cast<const TV *>(c.vj),
+  arnoldi_update_body<TV, 8>(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, static_cast<TV *>(c.w), static_cast<const TV *>(c.vj),
                       static_cast<const TV *>(c.vprev), c.pin, c.np_in, c.pout, c.kd);
 }
 
