@@ -304,6 +304,7 @@ static int kiops_rounds_dev(dfr_ensemble &E, std::vector<KiopsMachine> &K, const
     r.grp_lds[c.ns] = std::max(r.grp_lds[c.ns], dfr_lds_bytes(c.ns, d.TX, d.TY, k.fp32));
     r.grid_vec += d.nblk_vec;
     r.grp_maxupd[c.ns] += d.nblk_upd;
+    r.pmax = std::max(r.pmax, d.p);
   }
   // the combination / start and first launches: a fixed grid whose
   // workgroups take the blocks in turn (most rounds have few or none)

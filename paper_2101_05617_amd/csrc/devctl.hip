@@ -351,8 +351,8 @@ int launch_dev_round(hipStream_t s, const DevRound &r, bool first, KTimer *tm, c
   timed_launch(tm, DFR_K_OTHER, 0.0, s, plan_round_kernel, dim3(1), dim3(PLAN_THREADS), 0, r);
   DFR_HIP(hipGetLastError());
   const bool f32 = r.fp32 != 0, b32 = r.basis32 != 0;
-  int rc = launch_krylov_dev(s, KD_PRE, b32, r.pre, &r.cnt->n_pre, r.grid_vec, tm);
-  if (!rc && first) rc = launch_krylov_dev(s, KD_FIRST, b32, r.first, &r.cnt->n_first, r.grid_vec, tm);
+  int rc = launch_krylov_dev(s, KD_PRE, b32, r.pre, &r.cnt->n_pre, r.grid_vec, r.pmax, tm);
+  if (!rc && first) rc = launch_krylov_dev(s, KD_FIRST, b32, r.first, &r.cnt->n_first, r.grid_vec, r.pmax, tm);
   if (rc) return rc;
   // each group: its products, then its updates (on a branch of its own)
   bool forked = false;
@@ -370,7 +370,7 @@ int launch_dev_round(hipStream_t s, const DevRound &r, bool first, KTimer *tm, c
     rc = launch_dfr_batch_dev(gs, ns, f32, b32, r.dfr + r.grp_base[ns], &r.cnt->dfr[ns][0], grid,
                               r.grp_threads[ns], r.grp_lds[ns], tm);
     if (!rc) rc = launch_krylov_dev(gs, KD_UPDATE, b32, r.upd + r.grp_base[ns], &r.cnt->upd[ns][0],
-                                    r.grp_maxupd[ns], tm);
+                                    r.grp_maxupd[ns], r.pmax, tm);
     if (!rc && gs != s) DFR_HIP(hipEventRecord(br->join[ns], gs));
   }
   if (rc) return rc;

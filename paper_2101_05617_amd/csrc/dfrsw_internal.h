@@ -504,6 +504,7 @@ struct DevRound {
   size_t grp_lds[MAX_NS + 1];
   size_t expm_lds;
   int fp32, basis32;
+  int pmax;                        // the largest p of the members
 };
 // first: the first round of a KIOPS call (the only one with first Arnoldi
 // steps of a zero top block).  tm: NULL, or a timer whose events bracket
@@ -519,7 +520,8 @@ int launch_dev_round(hipStream_t s, const DevRound &r, bool first, KTimer *tm, c
 enum { KD_PRE = 0, KD_FIRST = 1, KD_UPDATE = 2 };
 int launch_dfr_batch_dev(hipStream_t s, int ns, bool fp32, bool basis32, const DfrCall *calls, const int *dc,
                          int grid, int threads, size_t lds, KTimer *tm);
-int launch_krylov_dev(hipStream_t s, int kind, bool basis32, const void *calls, const int *dc, int grid,
+// pmax: the largest p of the calls (the update's bottom-block loops)
+int launch_krylov_dev(hipStream_t s, int kind, bool basis32, const void *calls, const int *dc, int grid, int pmax,
                       KTimer *tm);
 int launch_expm_dev(hipStream_t s, const ExpmCall *calls, const int *dc, int grid, size_t lds, KTimer *tm);
 enum { VB_AXPBY = 0, VB_TO_F32 = 1, VB_NORM2 = 2, VB_SUM = 3, VB_CHECK = 4 };

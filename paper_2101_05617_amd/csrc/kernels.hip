@@ -1092,14 +1092,17 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_first_batch(const FirstCall *__
 // scales sigma_k kept in KDev.  The first UNROLL elements of each thread are
 // read before the prologue, in flight during its reductions.  With !two the
 // third stream rereads v~_j, multiplied by a zero coefficient.
-template <typename TV, int UNROLL>
+template <typename TV, int UNROLL, int MP = MAX_P>
 __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n3, int j, int p, TV *w,
                                                     const TV *vj, const TV *vprev, const double *pin,
                                                     int np_in, double *pout, KDev *kd) {
   // UNROLL grid strides per chunk: a chunk's loads are issued together (one
   // memory round trip per chunk); the first chunk before the reduction.  A
   // single grid takes up to 1024 workgroups and needs few strides (4); a
-  // member of a batch, at most 256 workgroups, more (8)
+  // member of a batch, at most 256 workgroups, more (8).  MP: the largest p
+  // of the calls (the bottom-block loops are unrolled to it: MAX_P, or 4
+  // for a batch whose calls all have p <= 4, which needs fewer registers)
+  static_assert(MP >= 1 && MP <= MAX_P, "bottom blocks of at most MAX_P entries");
   static_assert(BLOCK == 256, "one virtual lane of the fixed-order reduction per thread");
   __shared__ double red[512];
   const bool two = (j >= 1) && (vprev != nullptr);
@@ -1128,12 +1131,12 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
     xp[u] = vp2[i];
   }
   // the bottom blocks b_j, b_{j-1} and the scales, read ahead of the
-  // reduction's barriers (whole rows of MAX_P values: no branch on p)
+  // reduction's barriers (the first MP values of each row: no branch on p)
   const double *bj = kd->bot + j * MAX_P;
   const double *bp = kd->bot + (j - (j >= 1 ? 1 : 0)) * MAX_P;
-  double bjv[MAX_P], bpv[MAX_P];
+  double bjv[MP], bpv[MP];
 #pragma unroll
-  for (int k = 0; k < MAX_P; ++k) {
+  for (int k = 0; k < MP; ++k) {
     bjv[k] = bj[k];
     bpv[k] = bp[k];
   }
@@ -1159,18 +1162,18 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
     reduce_fixed2_finish(red, d0, d1);
   }
   const int ld = MAX_M + 2;
-  // (loops over all MAX_P slots, unrolled, with k < p selecting: no
-  // run-time index into the register arrays)
-  double wb[MAX_P];
+  // (loops over all MP slots, unrolled, with k < p selecting: no run-time
+  // index into the register arrays)
+  double wb[MP];
 #pragma unroll
-  for (int k = 0; k < MAX_P; ++k) wb[k] = (k + 1 < MAX_P && k + 1 < p) ? bjv[k + 1 < MAX_P ? k + 1 : 0] : 0.0;   // K b_j
+  for (int k = 0; k < MP; ++k) wb[k] = (k + 1 < MP && k + 1 < p) ? bjv[k + 1 < MP ? k + 1 : 0] : 0.0;   // K b_j
   double hjj = d0, hpj = d1;
 #pragma unroll
-  for (int k = 0; k < MAX_P; ++k)
+  for (int k = 0; k < MP; ++k)
     if (k < p) hjj += bjv[k] * wb[k];
   if (two) {
 #pragma unroll
-    for (int k = 0; k < MAX_P; ++k)
+    for (int k = 0; k < MP; ++k)
       if (k < p) hpj += bpv[k] * wb[k];
   } else {
     hpj = 0.0;
@@ -1180,7 +1183,7 @@ __device__ __forceinline__ void arnoldi_update_body(int blk, int nblk, int64_t n
     if (two) kd->H[(j - 1) * ld + j] = hpj;
     double nb2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < MAX_P; ++k) {
+    for (int k = 0; k < MP; ++k) {
       if (k < p) {
         double v = wb[k] - hjj * bjv[k];
         if (two) v -= hpj * bpv[k];
@@ -1225,15 +1228,22 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_update_kernel(int64_t n3, int j
                                                                double *pout, KDev *kd) {
   arnoldi_update_body<TV, 4>(blockIdx.x, gridDim.x, n3, j, p, w, vj, vprev, pin, np_in, pout, kd);
 }
-template <typename TV>
-__global__ __launch_bounds__(BLOCK) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls,
+// Waves per SIMD asked of the batched update: with an FP32 basis and p <= 4
+// it fits the registers of eight waves without spilling (64 VGPRs, against
+// 75 and six waves); more waves keep more of the streaming loads in flight.
+template <typename TV, int MP>
+constexpr int update_waves_per_eu() {
+  return (std::is_same<TV, float>::value && MP <= 4) ? 8 : 1;
+}
+template <typename TV, int MP>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(update_waves_per_eu<TV, MP>()))) void arnoldi_update_batch(const UpdateCall *__restrict__ calls, int ncalls,
                                                   const int *__restrict__ dc) {
   if (dc) {   // counts in device memory: calls, workgroups
     ncalls = dc[0];
     if ((int)blockIdx.x >= dc[1]) return;
   }
   const UpdateCall &c = calls[find_call(calls, ncalls)];
-  arnoldi_update_body<TV, 8>(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, static_cast<TV *>(c.w), static_cast<const TV *>(c.vj),
+  arnoldi_update_body<TV, 8, MP>(blockIdx.x - c.b0, c.nblk, c.n3, c.j, c.p, static_cast<TV *>(c.w), static_cast<const TV *>(c.vj),
                       static_cast<const TV *>(c.vprev), c.pin, c.np_in, c.pout, c.kd);
 }
 
@@ -2255,8 +2265,13 @@ int launch_first_batch(hipStream_t s, Stage &st, bool basis32, std::vector<First
                  : launch_calls_k(s, st, calls, arnoldi_first_batch<double>);
 }
 int launch_update_batch(hipStream_t s, Stage &st, bool basis32, std::vector<UpdateCall> &calls) {
-  return basis32 ? launch_calls_k(s, st, calls, arnoldi_update_batch<float>, DFR_K_UPDATE)
-                 : launch_calls_k(s, st, calls, arnoldi_update_batch<double>, DFR_K_UPDATE);
+  int pmax = 0;
+  for (const UpdateCall &c : calls) pmax = std::max(pmax, c.p);
+  if (pmax <= 4)
+    return basis32 ? launch_calls_k(s, st, calls, arnoldi_update_batch<float, 4>, DFR_K_UPDATE)
+                   : launch_calls_k(s, st, calls, arnoldi_update_batch<double, 4>, DFR_K_UPDATE);
+  return basis32 ? launch_calls_k(s, st, calls, arnoldi_update_batch<float, MAX_P>, DFR_K_UPDATE)
+                 : launch_calls_k(s, st, calls, arnoldi_update_batch<double, MAX_P>, DFR_K_UPDATE);
 }
 int launch_start_batch(hipStream_t s, Stage &st, bool basis32, std::vector<StartCall> &calls) {
   return basis32 ? launch_calls(s, st, calls, arnoldi_start_batch<float>)
@@ -2322,7 +2337,8 @@ int launch_dfr_batch_dev(hipStream_t s, int ns, bool fp32, bool basis32, const D
 }
 
 template <typename TV>
-static void launch_krylov_dev_t(hipStream_t s, int kind, const void *calls, const int *dc, int grid, KTimer *tm) {
+static void launch_krylov_dev_t(hipStream_t s, int kind, const void *calls, const int *dc, int grid, int pmax,
+                                KTimer *tm) {
   switch (kind) {
     case KD_PRE:
       timed_launch(tm, DFR_K_OTHER, 0.0, s, arnoldi_pre_batch<TV>, dim3(grid), dim3(BLOCK), 0,
@@ -2333,17 +2349,21 @@ static void launch_krylov_dev_t(hipStream_t s, int kind, const void *calls, cons
                    (const FirstCall *)calls, 0, dc);
       break;
     case KD_UPDATE:
-      timed_launch(tm, DFR_K_UPDATE, 0.0, s, arnoldi_update_batch<TV>, dim3(grid), dim3(BLOCK), 0,
-                   (const UpdateCall *)calls, 0, dc);
+      if (pmax <= 4)
+        timed_launch(tm, DFR_K_UPDATE, 0.0, s, arnoldi_update_batch<TV, 4>, dim3(grid), dim3(BLOCK), 0,
+                     (const UpdateCall *)calls, 0, dc);
+      else
+        timed_launch(tm, DFR_K_UPDATE, 0.0, s, arnoldi_update_batch<TV, MAX_P>, dim3(grid), dim3(BLOCK), 0,
+                     (const UpdateCall *)calls, 0, dc);
       break;
     default: break;
   }
 }
 
-int launch_krylov_dev(hipStream_t s, int kind, bool basis32, const void *calls, const int *dc, int grid,
+int launch_krylov_dev(hipStream_t s, int kind, bool basis32, const void *calls, const int *dc, int grid, int pmax,
                       KTimer *tm) {
-  if (basis32) launch_krylov_dev_t<float>(s, kind, calls, dc, grid, tm);
-  else launch_krylov_dev_t<double>(s, kind, calls, dc, grid, tm);
+  if (basis32) launch_krylov_dev_t<float>(s, kind, calls, dc, grid, pmax, tm);
+  else launch_krylov_dev_t<double>(s, kind, calls, dc, grid, pmax, tm);
   DFR_HIP(hipGetLastError());
   return DFR_OK;
 }
