@@ -965,13 +965,15 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
   }
 }
 
-// Waves per SIMD asked of the batched kernel: the complex-FP32 forms with up
+// Waves per SIMD asked of the product kernels: the complex-FP32 forms with up
 // to seven GL points fit the registers of six waves without spilling (80
-// VGPRs, against 82-90 left to themselves at five), which shortened the
-// ensemble's products by 12%; the FP64 forms and eight points would spill
-// there and keep the compiler's choice (1: no bound).
+// VGPRs, against 77-90 left to themselves at five or six), which shortened
+// the ensemble's batched products by 12% and sped up EPI6 at ne 120 with
+// FP32 products and basis by 17%; the FP64 forms and eight points would
+// spill there (a five-wave bound slowed the plain FP64 J*v by 11%) and keep
+// the compiler's choice (1: no bound).
 template <int NS, typename T>
-constexpr int batch_waves_per_eu() {
+constexpr int product_waves_per_eu() {
   return (std::is_same<T, float>::value && NS <= 7) ? 6 : 1;
 }
 
@@ -980,7 +982,8 @@ constexpr int batch_waves_per_eu() {
 // (0 Rusanov, 1 AUSM), a template argument so that each kernel keeps the
 // registers of its own flux
 template <int NS, typename T, typename TQ, bool CS, bool AR, int RS, typename TV>
-__global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
+__global__ __launch_bounds__(DFR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(product_waves_per_eu<NS, T>())))
+void dfr_kernel(const GridArgs g, const Ops1D ops, const int TX,
                                                                const int TY, const TQ *__restrict__ q,
                                                                const TV *__restrict__ v,
                                                                const double *__restrict__ vscale, double eps,
@@ -995,7 +998,7 @@ __global__ __launch_bounds__(DFR_MAX_THREADS) void dfr_kernel(const GridArgs g, 
 // or the number of calls and of logical blocks in device memory (written by
 // the round planner; the grid is sized for every member)
 template <int NS, typename T, typename TQ, bool CS, bool AR, typename TV>
-__global__ __launch_bounds__(DFR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<NS, T>())))
+__global__ __launch_bounds__(DFR_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(product_waves_per_eu<NS, T>())))
 void dfr_kernel_batch(const DfrCall *__restrict__ calls, int ncalls,
                                                                      int nlogical, const int *__restrict__ dc) {
   __shared__ int s_m;
