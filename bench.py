@@ -168,6 +168,16 @@ def summarize_profile(args):
             v = [x for _, x in (v[-args.last:] if args.last else v)]
             util[name] = sum(v) / len(v)
             lines.append(f"counter {name}: mean {util[name]:.6g} over {len(v)} dispatches")
+    if "SQ_WAVES" in util and util["SQ_WAVES"] > 0:
+        # instruction mix per wave and the share of wave cycles spent waiting
+        waves = util["SQ_WAVES"]
+        per = {k[len("SQ_INSTS_"):]: util[k] / waves for k in sorted(util) if k.startswith("SQ_INSTS_")
+               and not k.startswith("SQ_INSTS_VALU_FLOPS")}
+        lines.append("per_wave: " + " ".join(f"{k}={v:.1f}" for k, v in per.items()))
+        if util.get("SQ_WAVE_CYCLES"):
+            for k in ("SQ_WAIT_INST_ANY", "SQ_WAIT_ANY"):
+                if k in util:
+                    lines.append(f"{k} / SQ_WAVE_CYCLES: {util[k] / util['SQ_WAVE_CYCLES']:.3f}")
     if util:
         lines.append("utilisation: " + " ".join(f"{k}={v:.6g}" for k, v in sorted(util.items())) +
                      f" kernel_source: {kernel_source_digest()}")
@@ -206,6 +216,12 @@ def utilisation_summary(name, avg_us):
     out = {k2: u.get(k1) for k1, k2 in (("VALUBusy", "valu_busy_pct"), ("LdsUtil", "lds_util_pct"),
                                          ("OccupancyPercent", "occupancy_pct"), ("MfmaUtil", "mfma_util_pct"),
                                          ("VALUUtilization", "valu_active_lanes_pct"))}
+    if u.get("SQ_WAVES"):
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"):
+            if k in u:
+                out[k[len("SQ_INSTS_"):].lower() + "_insts_per_wave"] = u[k] / u["SQ_WAVES"]
+        if u.get("SQ_WAVE_CYCLES") and "SQ_WAIT_ANY" in u:
+            out["wait_fraction_of_wave_cycles"] = u["SQ_WAIT_ANY"] / u["SQ_WAVE_CYCLES"]
     for key, peak, tag in (("SQ_INSTS_VALU_FLOPS_FP64", FP64_VECTOR_PEAK_TFLOPS, "fp64"),
                            ("SQ_INSTS_VALU_FLOPS_FP32", FP32_VECTOR_PEAK_TFLOPS, "fp32")):
         if key in u and avg_us:
