@@ -19,7 +19,8 @@ members of four different p (four product launches per round), rejections
 and Krylov-size changes (a tolerance the first Krylov size misses), happy
 breakdowns in the start-up, non-convergence naming the member, event timing
 (the rounds launched without the graph), a change of options between calls
-(a new capture), and the round counts."""
+(a new capture), the round counts, and timing restricted to chosen kernel
+kinds."""
 from dataclasses import replace
 
 import numpy as np
@@ -199,4 +200,33 @@ def test_device_rounds_timed_and_recaptured():
     finally:
         host.close()
         dev.close()
+        torch.cuda.synchronize()
+
+
+def test_ensemble_timing_brackets_only_the_chosen_kinds():
+    # dfr_ensemble_timing_kinds: with only the Krylov-form product chosen, the
+    # other kinds record no launch; a mask beyond the kinds is refused
+    import torch
+    from paper_2101_05617_amd import dfrsw
+    from paper_2101_05617_amd.ensemble import Ensemble
+    ws = [small(C0, 2, 3), small(C0, 2, 4)]
+    ens = Ensemble(ws, prec="fp64", form="batched", autotune=False, rounds="host")
+    try:
+        opts = dfrsw.kiops_opts(tol=1e-10, m_max=24)
+        dfrsw.dfr_ensemble_timing_kinds(ens.eg, ["jv_arnoldi"])
+        dfrsw.dfr_ensemble_timing_enable(ens.eg, True)
+        st = ens.step(opts)
+        ms, n, nodes = dfrsw.dfr_ensemble_timing_read(ens.eg, "jv_arnoldi")
+        assert ms > 0 and n > 0 and nodes == sum(s["n_matvec"] * 6 * w.ne ** 2 * w.ns ** 2 for s, w in zip(st, ws))
+        for kind in ("update", "expm", "other", "rhs"):
+            assert dfrsw.dfr_ensemble_timing_read(ens.eg, kind)[1] == 0, kind
+        dfrsw.dfr_ensemble_timing_kinds(ens.eg, None)
+        dfrsw.dfr_ensemble_timing_enable(ens.eg, True)
+        ens.step(opts)
+        assert dfrsw.dfr_ensemble_timing_read(ens.eg, "update")[1] > 0
+        with pytest.raises(dfrsw.DfrError):
+            dfrsw._check(dfrsw.lib().dfr_ensemble_timing_kinds(ens.eg.handle, 1 << 12))
+    finally:
+        dfrsw.dfr_ensemble_timing_enable(ens.eg, False)
+        ens.close()
         torch.cuda.synchronize()
