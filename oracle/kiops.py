@@ -44,6 +44,14 @@ K6  Step-size / dimension update (gamma = 0.2, gamma_mmax = 0.6):
     A rejected attempt keeps the basis: a larger m continues the Arnoldi
     process, a smaller tau only recomputes E.
 K7  The sub-step that reaches tau_out ends exactly at tau_out.
+
+Decision replay: every attempt's decisions (the tau it ran with, the Krylov
+dimension J of its exponential, accepted or not) are recorded in
+KiopsStats.decisions.  Given a DecisionReplay, the attempts take its
+decisions in order instead of the controller's (K5-K6): each attempt runs
+with the recorded tau (which may not pass tau_out), extends the basis to the
+recorded m and is accepted or rejected as recorded.  The arithmetic of an attempt is unchanged, so a
+run that replays another's decisions differs from it by arithmetic alone.
 """
 from __future__ import annotations
 
@@ -62,6 +70,16 @@ class KiopsError(RuntimeError):
     pass
 
 
+class DecisionReplay:
+    """Decisions (tau, m, accept) that successive KIOPS attempts take in order,
+    in place of the controller's; the calls that share one object (the KIOPS
+    calls of an EPI step) continue its position."""
+
+    def __init__(self, decisions):
+        self.decisions = [(float(t), int(m), bool(a)) for t, m, a in decisions]
+        self.pos = 0
+
+
 @dataclass
 class KiopsStats:
     n_matvec: int = 0
@@ -74,10 +92,11 @@ class KiopsStats:
 
 
 def kiops(tau_out, matvec, bs, tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2,
-          max_attempts=1000):
+          max_attempts=1000, replay=None):
     """w = sum_k tau_out^k phi_k(tau_out A) b_k for bs = [b_0, ..., b_p].
 
-    b_0 may be None (zero).  Returns (w, KiopsStats)."""
+    b_0 may be None (zero).  replay: None or a DecisionReplay.  Returns
+    (w, KiopsStats)."""
     bs = list(bs)
     n = len(next(b for b in bs if b is not None))
     b0_absent = bs[0] is None
@@ -113,6 +132,16 @@ def kiops(tau_out, matvec, bs, tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2,
         attempts += 1
         if attempts > max_attempts:
             raise KiopsError("KIOPS did not converge")
+        if replay is not None:
+            if replay.pos >= len(replay.decisions):
+                raise KiopsError(f"replay: the decisions ran out at decision {replay.pos}")
+            tau, m, _ = replay.decisions[replay.pos]
+            # a sub-step may not pass tau_out (K7: the controller clips tau to
+            # the remaining interval; a relative 1e-12 allows for rounding)
+            if not (tau > 0.0 and math.isfinite(tau)) or tau > (tau_out - t) + 1e-12 * tau_out \
+                    or m < max(1, j) or m > m_max:
+                raise KiopsError(f"replay: decision {replay.pos} (tau {tau}, m {m}) cannot be taken "
+                                 f"at t = {t} of {tau_out} with {j} basis vectors built and m_max {m_max}")
         if j == 0:
             y = np.array([mu * t ** (p - 1 - k) / math.factorial(p - 1 - k) for k in range(p)])
             u = np.concatenate([x, y])
@@ -192,6 +221,15 @@ def kiops(tau_out, matvec, bs, tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2,
             else:
                 m_new = m_opt
                 tau_new = min(remaining, tau)
+        if replay is not None:
+            _, m_rec, accept_rec = replay.decisions[replay.pos]
+            if J != m_rec:
+                raise KiopsError(f"replay: decision {replay.pos}: a happy breakdown ended the basis at "
+                                 f"{J} vectors, below m = {m_rec}")
+            if happy and not accept_rec:
+                raise KiopsError(f"replay: decision {replay.pos}: a happy breakdown in a rejected attempt")
+            accept = accept_rec
+            replay.pos += 1
         st.decisions.append((tau, J, bool(accept)))
         if accept:
             x = beta * (V[:J, :n].T @ E[:J, 0])
@@ -208,6 +246,6 @@ def kiops(tau_out, matvec, bs, tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2,
             st.n_rejected += 1
         old_tau, old_m, old_omega = tau, m, omega
         tau, m = tau_new, m_new
-        if t < tau_out and not (tau > 0.0):
+        if replay is None and t < tau_out and not (tau > 0.0):
             raise KiopsError("KIOPS step size collapsed")
     return x, st
