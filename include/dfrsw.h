@@ -86,6 +86,50 @@ typedef struct {
   const double *hB;
 } dfr_grid_desc;
 
+/* One attempt of the Krylov controller (Sec. 4, Eq. 29: a sub-step of the
+ * phi-combination tried with one small exponential): the sub-step length tau
+ * it was tried with, the Krylov dimension m of its exponential, and whether
+ * the sub-step was accepted (1) or rejected (0). */
+typedef struct {
+  double tau;
+  int m;
+  int accept;
+} kiops_decision;
+
+/* Decision record and replay, an instrument for separating the arithmetic of
+ * a precision form from the controller's path: record the decisions of one
+ * run (or take them from another implementation of the same controller) and
+ * make a second run, possibly in another precision, take exactly those
+ * decisions, so that the two results differ by arithmetic alone.  Owned by
+ * the caller (host memory); the fields the library advances are counters the
+ * caller zeroes before the first call.
+ *   rec, rec_cap: NULL / 0, or host room for rec_cap decisions; each attempt
+ *     appends its decisions (tau it ran with, m = the Krylov dimension its
+ *     exponential used, accept).  n_rec counts the attempts recorded,
+ *     including those beyond rec_cap, which are not stored.
+ *   play, n_play: NULL / 0, or decisions that successive attempts take in
+ *     order, from entry pos on: the attempt runs with that tau, extends the
+ *     Krylov basis to that m and is accepted or rejected as stated, whatever
+ *     the controller's own error estimate says.  pos is advanced past each
+ *     decision taken.  Record and play may be used together.
+ * Calls that share the struct continue its counters, so one epi_step (several
+ * KIOPS calls in its start-up) records and replays as one sequence.
+ * Errors (DFR_E_KIOPS, the message naming the attempt): the decisions run out
+ * before tau_out is reached; a decision's tau passes tau_out (by more than a
+ * relative 1e-12); a decision's m is below the basis already built
+ * (a sweep cannot shrink), above m_max, or below 1; a happy breakdown (an
+ * invariant Krylov space) ends the basis below the decision's m.  Single-grid
+ * calls only (kiops_phi_apply, epi_step): the ensemble and concurrent forms
+ * return DFR_E_INVAL when opts->replay is set. */
+typedef struct {
+  kiops_decision *rec;
+  int rec_cap;
+  int n_rec;
+  const kiops_decision *play;
+  int n_play;
+  int pos;
+} kiops_replay;
+
 /* Adaptive Krylov (KIOPS-type) controller settings; see kiops_phi_apply. */
 typedef struct {
   double tol;        /* relative tolerance of the phi-combination */
@@ -93,6 +137,7 @@ typedef struct {
   int m_min, m_max;  /* bounds of the Krylov dimension (m_max <= 64) */
   int iop;           /* incomplete orthogonalisation length: 1 or 2 */
   int max_attempts;  /* cap on sub-step attempts before DFR_E_KIOPS */
+  kiops_replay *replay;  /* NULL, or the decision record / replay above */
 } kiops_opts;
 
 typedef struct {

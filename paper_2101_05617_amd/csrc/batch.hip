@@ -1034,6 +1034,10 @@ int epi_ensemble_step(dfr_ensemble *E, epi_ensemble *X, const kiops_opts *o, kio
     set_error("epi_ensemble_step: invalid argument");
     return DFR_E_INVAL;
   }
+  if (o->replay) {
+    set_error("epi_ensemble_step: decision record / replay is for single-grid calls (kiops_phi_apply, epi_step)");
+    return DFR_E_INVAL;
+  }
   const int n = E->n;
   epi_state *s0 = X->st[0];
   for (int i = 0; i < n; ++i) {

@@ -98,6 +98,34 @@ int km_begin_attempt(KiopsMachine &k, const kiops_opts &o) {
     set_error("kiops: no convergence within max_attempts");
     return DFR_E_KIOPS;
   }
+  if (o.replay && o.replay->play) {
+    // replay: the attempt takes the next recorded (tau, m) instead of the
+    // controller's; its accept is applied by km_decide
+    const kiops_replay &R = *o.replay;
+    const std::string at = "kiops replay, decision " + std::to_string(R.pos) + ": ";
+    if (R.pos < 0 || R.pos >= R.n_play) {
+      set_error(at + "the decisions ran out before the end of the step");
+      return DFR_E_KIOPS;
+    }
+    const kiops_decision &d = R.play[R.pos];
+    if (!(d.tau > 0.0) || !std::isfinite(d.tau)) {
+      set_error(at + "tau is not a positive finite number");
+      return DFR_E_KIOPS;
+    }
+    // K7: a sub-step may not pass tau_out (the controller clips tau to the
+    // remaining interval; a relative 1e-12 allows for rounding)
+    if (d.tau > (k.tau_out - k.t) + 1e-12 * k.tau_out) {
+      set_error(at + "tau passes the end of the interval");
+      return DFR_E_KIOPS;
+    }
+    if (d.m < 1 || d.m > k.m_max || d.m < k.j) {
+      set_error(at + "m = " + std::to_string(d.m) + " outside [max(1, " + std::to_string(k.j) +
+                " basis vectors built), m_max = " + std::to_string(k.m_max) + "]");
+      return DFR_E_KIOPS;
+    }
+    k.tau = d.tau;
+    k.m = d.m;
+  }
   k.j_sweep = k.j;
   k.skipped = false;
   k.need_start = (k.j == 0);
@@ -194,6 +222,31 @@ int km_decide(KiopsMachine &k, const KHost &r, const kiops_opts &o, bool *accept
       tau_new = std::min(remaining, tau);
     }
   }
+  const bool replaying = o.replay && o.replay->play;
+  if (replaying) {
+    // the recorded decision (validated when the attempt began) overrides
+    // the controller's; a happy breakdown must end the basis where the
+    // record's did
+    kiops_replay &R = *o.replay;
+    const kiops_decision &d = R.play[R.pos];
+    const std::string at = "kiops replay, decision " + std::to_string(R.pos) + ": ";
+    if (J != d.m) {
+      set_error(at + "a happy breakdown ended the Krylov basis at " + std::to_string(J) + " vectors, below m = " +
+                std::to_string(d.m));
+      return DFR_E_KIOPS;
+    }
+    if (r.happy && !d.accept) {
+      set_error(at + "a happy breakdown in an attempt the record rejects");
+      return DFR_E_KIOPS;
+    }
+    accept = d.accept != 0;
+    R.pos++;
+  }
+  if (o.replay) {
+    kiops_replay &R = *o.replay;
+    if (R.rec && R.n_rec >= 0 && R.n_rec < R.rec_cap) R.rec[R.n_rec] = kiops_decision{tau, J, accept ? 1 : 0};
+    R.n_rec++;
+  }
   if (accept) {
     if (tau >= tau_out - t) k.t = tau_out;
     else k.t = t + tau;
@@ -212,7 +265,7 @@ int km_decide(KiopsMachine &k, const KHost &r, const kiops_opts &o, bool *accept
   k.m = m_new;
   *accept_out = accept;
   k.phase = k.t < tau_out ? KiopsMachine::BEGIN : KiopsMachine::DONE;
-  if (k.t < tau_out && !(k.tau > 0.0)) {
+  if (!replaying && k.t < tau_out && !(k.tau > 0.0)) {
     set_error("kiops: step size collapsed");
     return DFR_E_KIOPS;
   }
@@ -704,6 +757,10 @@ int epi_step_concurrent(int n, dfr_ctx *const *ctxs, epi_state *const *states, c
                         kiops_stats *stats) {
   if (n < 1 || !ctxs || !states || !o) {
     set_error("epi_step_concurrent: invalid argument");
+    return DFR_E_INVAL;
+  }
+  if (o->replay) {
+    set_error("epi_step_concurrent: decision record / replay is for single-grid calls (kiops_phi_apply, epi_step)");
     return DFR_E_INVAL;
   }
   std::vector<int> order(n);

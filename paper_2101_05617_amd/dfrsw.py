@@ -40,9 +40,51 @@ class _GridDesc(ctypes.Structure):
                 ("phi0", ctypes.c_double), ("alpha0", ctypes.c_double), ("hB", ctypes.c_void_p)]
 
 
+class KiopsDecision(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("m", ctypes.c_int), ("accept", ctypes.c_int)]
+
+
+class _KiopsReplay(ctypes.Structure):
+    _fields_ = [("rec", ctypes.POINTER(KiopsDecision)), ("rec_cap", ctypes.c_int), ("n_rec", ctypes.c_int),
+                ("play", ctypes.POINTER(KiopsDecision)), ("n_play", ctypes.c_int), ("pos", ctypes.c_int)]
+
+
+class DecisionReplay:
+    """A kiops_replay: record the controller's decisions (tau, m, accept) of
+    the attempts of one or more calls, and/or make the attempts take given
+    decisions in order.  Pass it as kiops_opts(..., replay=...)."""
+
+    def __init__(self, play=None, rec_cap=4096):
+        self._rec = (KiopsDecision * rec_cap)() if rec_cap else None
+        self._play = None
+        self.struct = _KiopsReplay()
+        if self._rec is not None:
+            self.struct.rec = ctypes.cast(self._rec, ctypes.POINTER(KiopsDecision))
+            self.struct.rec_cap = rec_cap
+        if play is not None:
+            play = list(play)
+            self._play = (KiopsDecision * max(len(play), 1))(*[KiopsDecision(float(t), int(m), int(bool(a)))
+                                                               for t, m, a in play])
+            self.struct.play = ctypes.cast(self._play, ctypes.POINTER(KiopsDecision))
+            self.struct.n_play = len(play)
+
+    @property
+    def pos(self):
+        """Decisions of the replay list taken so far."""
+        return self.struct.pos
+
+    def recorded(self):
+        """The recorded decisions, a list of (tau, m, accept)."""
+        n = self.struct.n_rec
+        if self._rec is None or n > len(self._rec):
+            raise ValueError(f"{n} decisions recorded, room for {0 if self._rec is None else len(self._rec)}")
+        return [(d.tau, d.m, bool(d.accept)) for d in self._rec[:n]]
+
+
 class KiopsOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("m_init", ctypes.c_int), ("m_min", ctypes.c_int),
-                ("m_max", ctypes.c_int), ("iop", ctypes.c_int), ("max_attempts", ctypes.c_int)]
+                ("m_max", ctypes.c_int), ("iop", ctypes.c_int), ("max_attempts", ctypes.c_int),
+                ("replay", ctypes.POINTER(_KiopsReplay))]
 
 
 class KiopsStats(ctypes.Structure):
@@ -53,8 +95,13 @@ class KiopsStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-def kiops_opts(tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2, max_attempts=1000):
-    return KiopsOpts(tol, m_init, m_min, m_max, iop, max_attempts)
+def kiops_opts(tol=1e-10, m_init=10, m_min=10, m_max=64, iop=2, max_attempts=1000, replay=None):
+    """kiops_opts; replay: None or a DecisionReplay (kept alive by the returned object)."""
+    o = KiopsOpts(tol, m_init, m_min, m_max, iop, max_attempts)
+    if replay is not None:
+        o.replay = ctypes.pointer(replay.struct)
+        o._keep = replay
+    return o
 
 
 _lib = None

@@ -50,3 +50,36 @@ def test_constants_match_header():
     for name, key in (("DFR_ROUNDS_HOST", "host"), ("DFR_ROUNDS_DEVICE", "device")):
         v = re.search(name + r"\s*=\s*(\d+)", src)
         assert v and int(v.group(1)) == dfrsw.ROUNDS[key]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the structs passed by pointer through the boundary: every field's offset
+    # and each struct's size as the C compiler lays them out from the header,
+    # against the binding's ctypes declarations
+    import shutil
+    import subprocess
+    from paper_2101_05617_amd import dfrsw
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"dfr_grid_desc": dfrsw._GridDesc, "kiops_opts": dfrsw.KiopsOpts,
+               "kiops_stats": dfrsw.KiopsStats, "kiops_decision": dfrsw.KiopsDecision,
+               "kiops_replay": dfrsw._KiopsReplay}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-o", str(exe), str(src)], check=True, capture_output=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
