@@ -209,3 +209,44 @@ def test_shallow_water_epi_conserves_mass():
     for _ in range(3):
         E.step()
         assert abs(wq @ E.q[: G.N] - m0) / m0 < 1e-14
+
+
+def test_epi_observed_order_shallow_water_c0():
+    # Sec. 4 methods on the shallow-water problem itself (ne = 4, p = 4; the
+    # zonal flow with a 5% height perturbation, 4 h): exact starting values
+    # from an independent reference (DOP853, rtol 1e-13, about 2e-13 from
+    # itself at rtol 1e-12), then EPI4/5/6 at dt = 1800, 900, 450 s.  The
+    # slopes approach the design orders from below (measured 3.68/3.85,
+    # 4.57/4.89, 5.22/5.35): these dt are not yet asymptotic, and dt cannot
+    # shrink much further, since the errors then meet the floor set by the
+    # rounding of F, a small residual of the fluxes of a near-balanced state
+    # (about 4e-12 here).  Asserted: each slope >= order - 1, and at every
+    # dt the higher order is the more accurate.
+    import scipy.integrate
+    w = replace(inputs.WORKLOADS["c0_ne4_p4"], u_amp=1.0, h_amp=0.05)
+    G = oracle.OracleGrid(w.ne, w.ns, *w.constants())
+    Q, _ = inputs.initial_state(w, *G.node_frames())
+    T = 14400.0 * w.dt_nd / w.dt_s
+    nref = 32
+    sol = scipy.integrate.solve_ivp(lambda t, y: G.rhs(y), (0.0, T), Q, method="DOP853", rtol=1e-13, atol=1e-16,
+                                    t_eval=np.linspace(0.0, T, nref + 1))
+    assert sol.status == 0
+    R = sol.y.T
+    errs = {}
+    for order in (4, 5, 6):
+        errs[order] = []
+        for nst in (8, 16, 32):
+            E = epi.EPI(G.rhs, lambda q, v: G.jvp(q, v, 1e-150), order, T / nst, Q,
+                        kiops_opts=dict(tol=1e-14, m_max=64))
+            k = nref // nst
+            E.q = R[E.P * k].copy()
+            E.hist_q = [R[(E.P - i) * k].copy() for i in range(1, E.P + 1)]
+            E.hist_F = [G.rhs(x) for x in E.hist_q]
+            E.n = E.P
+            for _ in range(nst - E.P):
+                E.step()
+            errs[order].append(np.linalg.norm(E.q - R[-1]) / np.linalg.norm(R[-1]))
+        slopes = np.log2(np.array(errs[order][:-1]) / np.array(errs[order][1:]))
+        assert np.all(slopes >= order - 1), (order, errs[order], slopes)
+    for i in range(3):
+        assert errs[6][i] < errs[5][i] < errs[4][i], [errs[o][i] for o in (4, 5, 6)]
