@@ -9,6 +9,7 @@ import oracle
 from paper_2101_05617_amd import inputs
 
 C0 = inputs.WORKLOADS["c0_ne4_p4"]
+C2 = inputs.WORKLOADS["c2_ne60_p6_jet"]
 
 
 def grid_and_state(w, rotation=inputs.ROTATION, **kw):
@@ -188,3 +189,39 @@ def test_jvp_additive_where_a_velocity_component_is_exactly_zero():
     for _ in range(3):
         v = rng.standard_normal(n)
         assert rel(G.jvp(Q, v), J @ v) < 1e-13
+
+
+@pytest.mark.parametrize("ne,p,rotation,kind", [(1, 2, inputs.ROTATION, "zonal"), (2, 3, inputs.ROTATION, "zonal"),
+                                                (3, 4, (0.3, 0.5, 0.2), "zonal"), (2, 5, inputs.ROTATION, "jet"),
+                                                (2, 5, (0.3, 0.5, 0.2), "jet")])
+def test_jvp_matches_hand_written_tangent_linear(ne, p, rotation, kind):
+    # tests/tl_ref.py differentiates the right-hand side by hand, rule by rule
+    # (forward mode, value and derivative pairs), in an assembly of its own.
+    # Its value is F to the rounding floor of F (a small residual of the
+    # fluxes: the bar is max(1e-12, 4 x the oracle's own change under a 1-ulp
+    # perturbation of Q)); its derivative is the complex-step J v to 1e-14,
+    # per field in L2 and node by node against the field's largest value.
+    # The flows carry contravariant velocities of both signs, so both
+    # branches of |u^n| and of the max of the wave speeds occur.  Elements
+    # with a face point where a branch is decided within rounding have
+    # several correct one-sided derivatives and are left out of the J v
+    # comparison: on the paper's rotation the jet is mirror-symmetric across
+    # panel lines, where both sides' wave speeds tie exactly (a third of the
+    # elements at ne = 2); rotated otherwise, nothing is left out.
+    from tests.tl_ref import rhs_tangent
+    w = replace(C2, ne=ne, p=p) if kind == "jet" else replace(C0, ne=ne, p=p, u_amp=1.0, h_amp=0.05)
+    G, Q, _ = grid_and_state(w, rotation=rotation)
+    V = inputs.random_direction(3 * G.N, 5) * np.abs(Q).max() * 1e-3
+    F, JV, amb = rhs_tangent(G, Q, V)
+    Fo, Jo = G.rhs(Q), G.jvp(Q, V)
+    assert amb.mean() <= (0.4 if (kind == "jet" and rotation == inputs.ROTATION) else 0.0), amb.mean()
+    JV, Jo = np.where(amb, 0.0, JV), np.where(amb, 0.0, Jo)
+    N = G.N
+    rng = np.random.default_rng(1)
+    Fp = G.rhs(Q * (1.0 + np.finfo(float).eps * rng.choice([-1.0, 1.0], size=Q.size)))
+    for f in range(3):
+        s = slice(f * N, (f + 1) * N)
+        floor = rel(Fp[s], Fo[s])
+        assert rel(F[s], Fo[s]) < max(1e-12, 4.0 * floor), (f, rel(F[s], Fo[s]), floor)
+        assert rel(JV[s], Jo[s]) < 1e-14, (f, rel(JV[s], Jo[s]))
+        assert np.abs(JV[s] - Jo[s]).max() < 1e-14 * np.abs(Jo[s]).max()
