@@ -23,8 +23,15 @@ Tolerances:
       phi-combination elsewhere in the tests: a complex-FP32 product carries
       ~1e-6 relative error (unit roundoff 6e-8 times the flux cancellation),
       and the Krylov combination of products of one sweep does not amplify
-      it beyond a decade.  EPI steps: 1e-6 in h (relative L2 and element-wise
-      against max h), the accuracy the mixed form is held to.
+      it beyond a decade (measured: 2.9e-6).  EPI steps on the replayed path:
+      1e-8 in h in relative L2 and 1e-7 node by node against max h.  Only the
+      Krylov products are FP32 (the remainders stay FP64), so a step carries
+      the ~3e-6 relative error of its phi-combination times the size of the
+      update against the state (~1e-4), about 3e-10, over eight steps a few
+      1e-9 at most (measured: 5e-11 after one step, 1.7e-10 after eight).
+      Left to their own controller the FP32 forms may take other decisions,
+      and are held to 1e-6 in h, the accuracy the mixed form is held to
+      (the mixed-precision tests).
 """
 
 import numpy as np
@@ -91,9 +98,9 @@ def test_fp64_records_the_oracle_decisions_and_replays_them():
 @pytest.mark.parametrize("prec", ["fp32_jv", "fp32_jv_basis32"])
 def test_fp32_forms_on_the_fp64_path(prec):
     # a tolerance of 1e-12 lies below the noise of a complex-FP32 product:
-    # left to its own controller the FP32 form takes another path (recorded,
-    # not asserted); on the oracle's path its difference from the FP64 result
-    # is that of its products' arithmetic
+    # left to its own controller the FP32 form may take another path (its
+    # attempts are recorded, not asserted); on the oracle's path its
+    # difference from the FP64 result is that of its products' arithmetic
     from paper_2101_05617_amd import dfrsw
     w = small(C2, 3)
     G, D, Q = pair(w)
@@ -154,7 +161,8 @@ def test_mixed_epi_steps_on_the_oracle_path(prec):
         eh = np.linalg.norm(got[:N] - ref[:N]) / np.linalg.norm(ref[:N])
         ehm = np.max(np.abs(got[:N] - ref[:N])) / np.max(np.abs(ref[:N]))
         record(f"replay_epi6_{prec}_step{k + 1}_h", eh)
-        assert eh < 1e-6 and ehm < 1e-6, (k, eh, ehm)
+        record(f"replay_epi6_{prec}_step{k + 1}_h_max", ehm)
+        assert eh < 1e-8 and ehm < 1e-7, (k, eh, ehm)
     assert rp.pos == len(decisions)
     st.close()
 
