@@ -18,7 +18,9 @@ def _oracle_built():
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build(force=True)
     yield
-    # the measures the GPU tests recorded, for the run's output folder
+    # the measures the GPU tests recorded, written as JSON to the file that
+    # DFRSW_METRICS names (if set)
     from tests import gpu_util
-    if gpu_util.METRICS:
-        gpu_util.dump_metrics("gpurun_out/parity_metrics.json")
+    path = os.environ.get("DFRSW_METRICS")
+    if gpu_util.METRICS and path:
+        gpu_util.dump_metrics(path)
