@@ -83,3 +83,26 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_decision_replay_marshalling():
+    # the binding's kiops_replay: the replay list as the library reads it,
+    # the record as the library writes it, and the pointer in kiops_opts
+    from paper_2101_05617_amd import dfrsw
+    play = [(0.25, 12, True), (0.125, 16, False), (0.125, 20, True)]
+    r = dfrsw.DecisionReplay(play=play, rec_cap=4)
+    st = r.struct
+    assert st.n_play == 3 and st.pos == 0 and st.n_rec == 0 and st.rec_cap == 4
+    assert [(st.play[i].tau, st.play[i].m, st.play[i].accept) for i in range(3)] == \
+        [(0.25, 12, 1), (0.125, 16, 0), (0.125, 20, 1)]
+    # what the library does after two attempts
+    st.rec[0] = dfrsw.KiopsDecision(0.25, 12, 1)
+    st.rec[1] = dfrsw.KiopsDecision(0.125, 16, 0)
+    st.n_rec, st.pos = 2, 2
+    assert r.recorded() == [(0.25, 12, True), (0.125, 16, False)] and r.pos == 2
+    st.n_rec = 5      # more attempts than the record holds
+    with pytest.raises(ValueError):
+        r.recorded()
+    o = dfrsw.kiops_opts(tol=1e-8, replay=r)
+    assert ctypes.addressof(o.replay.contents) == ctypes.addressof(st)
+    assert not dfrsw.kiops_opts(tol=1e-8).replay
