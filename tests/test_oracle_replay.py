@@ -10,9 +10,13 @@ What fixes the result independently of the replay code:
   - a rejected attempt keeps its Krylov basis (K4), so rejecting at m and then
     accepting at m' > m gives the same result, bit for bit, as accepting at m'
     directly;
-  - decisions that cannot be taken are errors."""
+  - decisions that cannot be taken are errors;
+  - (property test) any admissible path of resolved sub-steps, with rejected
+    attempts anywhere in it, gives the dense result, and its rejections
+    change nothing."""
 import numpy as np
 import pytest
+from hypothesis import given, settings, strategies as hst
 
 from oracle import epi, kiops, ode, phi
 
@@ -122,3 +126,47 @@ def test_epi_steps_replay_across_their_kiops_calls():
         rep.step()
     assert np.array_equal(ref.q, rep.q)
     assert r.pos == len(decisions) == sum(len(st.decisions) for st in rep.stats)
+
+
+def _mild_problem():
+    # a non-normal operator with ||A|| ~ 2, so that any sub-step of at most the
+    # whole interval is resolved by 24 Krylov vectors (||tau A||^24 / 24! ~ 3e-17)
+    rng = np.random.default_rng(11)
+    n = 40
+    A = -np.diag(np.linspace(0.1, 2.0, n)) + 0.2 * rng.standard_normal((n, n)) / np.sqrt(n)
+    bs = [rng.standard_normal(n)] + [rng.standard_normal(n) for _ in range(2)]
+    return A, bs, 1.0
+
+
+def _random_path(fracs, rejects, m):
+    """Accepted sub-steps in proportion to fracs (clipped to end at tau_out),
+    each preceded by a rejected attempt at m' = rejects[k] < m if nonzero."""
+    tau_out = 1.0
+    total = sum(fracs)
+    acc = _path(tau_out, [tau_out * f / total for f in fracs[:-1]] + [tau_out], m)
+    full, plain = [], []
+    for d, r in zip(acc, rejects):
+        if r:
+            full.append((d[0], r, False))
+        full.append(d)
+        plain.append(d)
+    return full, plain
+
+
+@settings(max_examples=25, deadline=None, derandomize=True)
+@given(fracs=hst.lists(hst.floats(0.05, 1.0), min_size=1, max_size=5),
+       rejects=hst.lists(hst.integers(0, 20), min_size=5, max_size=5))
+def test_any_admissible_path_gives_the_phi_combination(fracs, rejects):
+    # property: whatever sub-steps a path takes (each resolved), with rejected
+    # attempts anywhere in it, the result is the dense phi-combination (K2:
+    # sub-steps compose exactly); a rejected attempt followed by the accepted
+    # one leaves the result unchanged bit for bit (K4: the basis is kept)
+    A, bs, tau = _mild_problem()
+    ref = phi.phi_combination_dense(A, tau, bs)
+    full, plain = _random_path(fracs, rejects[:len(fracs)], 24)
+    w1, st1 = kiops.kiops(tau, lambda v: A @ v, bs, tol=1e-12, m_max=24, replay=kiops.DecisionReplay(full))
+    w2, st2 = kiops.kiops(tau, lambda v: A @ v, bs, tol=1e-12, m_max=24, replay=kiops.DecisionReplay(plain))
+    assert np.array_equal(w1, w2)
+    assert st1.n_substeps == st2.n_substeps == len(plain)
+    assert st1.n_rejected == sum(1 for r in rejects[:len(fracs)] if r)
+    assert np.linalg.norm(w1 - ref) <= 1e-10 * np.linalg.norm(ref)
