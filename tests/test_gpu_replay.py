@@ -204,3 +204,53 @@ def test_ensemble_forms_refuse_replay():
         assert e.value.code == -1 and "single-grid" in str(e.value)
         ens.close()
     torch.cuda.synchronize()
+
+
+def _clipped(tau_out, steps):
+    """accepted (tau, m) sub-steps whose last one is clipped to end at tau_out,
+    as the controller clips it."""
+    out, t = [], 0.0
+    for h, m, acc in steps:
+        if t == tau_out:
+            break
+        tau = min(h, tau_out - t)
+        out.append((tau, m, acc))
+        if acc:
+            t = tau_out if tau >= tau_out - t else t + tau
+    assert t == tau_out
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_jv", "fp32_jv_basis32"])
+def test_paths_the_controller_does_not_take(prec):
+    # both sides replay the same hand-made paths: uneven sub-steps; a
+    # rejection continued at a larger m; a rejection followed by a smaller tau
+    # on the same basis (an attempt that only recomputes the exponential); many
+    # short sub-steps.  The library follows each path exactly and agrees with
+    # the oracle at the FP64 bar, or at the FP32 bar for the FP32 forms.
+    from paper_2101_05617_amd import dfrsw
+    w = small(C0, 3, 4, u_amp=1.0)
+    G, D, Q = pair(w)
+    F = G.rhs(Q)
+    rng = np.random.default_rng(7)
+    b2 = 1e-3 * rng.standard_normal(3 * G.N)
+    tau = 8 * w.dt_nd
+    paths = {
+        "uneven": _clipped(tau, [(0.5 * tau, 16, True), (0.125 * tau, 8, False), (0.125 * tau, 20, True),
+                                 (tau, 16, True)]),
+        "same_basis": _clipped(tau, [(tau, 20, False), (0.5 * tau, 20, True), (tau, 24, True)]),
+        "many": _clipped(tau, [(tau / 6, 10, True)] * 7),
+    }
+    eps = 1e-150 if prec == "fp64" else C2.eps
+    bar = 1e-11 if prec == "fp64" else 1e-5
+    for name, path in paths.items():
+        ref, rst = okiops.kiops(tau, lambda v: G.jvp(Q, v), [None, F, b2], tol=1e-10, m_max=32,
+                                replay=okiops.DecisionReplay(path))
+        rp = dfrsw.DecisionReplay(play=path, rec_cap=64)
+        got, gst = dfrsw.kiops_phi_apply(D, to_dev(Q), tau, [None, to_dev(F), to_dev(b2)],
+                                         dfrsw.kiops_opts(tol=1e-10, m_max=32, replay=rp), eps, prec)
+        assert rp.pos == len(path), name
+        assert [d[1:] for d in rp.recorded()] == [(m, bool(a)) for _, m, a in path], name
+        assert (gst["n_matvec"], gst["n_substeps"], gst["n_rejected"], gst["n_expm"]) == \
+            (rst.n_matvec, rst.n_substeps, rst.n_rejected, rst.n_expm), name
+        check_krylov(to_host(got), ref, G, bar, f"replay_path_{name}_{prec}")
