@@ -97,6 +97,31 @@ def calibration_copy():
     del a, b
 
 
+MEASURED_COPY_BYTES = 2 * 1024 ** 3
+
+
+def measured_copy_gbs(reps=5):
+    """Bandwidth a plain device-to-device copy of 2 GiB reaches (read + write
+    bytes over its duration, best of `reps`, HIP events): the practical ceiling
+    of a streaming kernel on this GPU, reported beside the published peak."""
+    import torch
+    a = torch.ones(MEASURED_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.synchronize()
+    return 2 * MEASURED_COPY_BYTES / (best * 1e-3) / 1e9
+
+
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -1149,6 +1174,10 @@ def main():
     if ens:
         out = ensemble_headline_line(args)
         calibration_copy()   # the 256 MiB reference of the traffic counters in profiled runs
+        copy_gbs = measured_copy_gbs()
+        log(f"a plain 2 GiB device copy: {copy_gbs:.0f} GB/s")
+        out["roofline"]["measured_copy"] = {"GBs": copy_gbs, "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+                                            "achieved_frac_of_copy": out["roofline"]["achieved"] / copy_gbs}
         if not args.no_c1:
             w1 = inputs.WORKLOADS["c1_ne30_p5"]
             out["epi5_c1_ne30_p5"] = single_grid_run(w1, 8, 4, args.jv_reps)
@@ -1177,8 +1206,11 @@ def main():
         tile2_32 = dfrsw.dfr_autotune(g2, "fp32_jv")
         t32 = time_jv(g2, q2, v2, o2, 1e-20, "fp32_jv", args.jv_reps)
         log(f"ne=60 p=6 J*v: fp64 {t64 * 1e3:.1f} us, fp32 {t32 * 1e3:.1f} us")
+        copy_gbs = measured_copy_gbs()
         out["jv_ne60_p6"] = {
             "nodes": N2, "tile_fp64": tile2, "tile_fp32": tile2_32,
+            "measured_copy_GBs": copy_gbs,
+            "fp64_frac_of_copy": 72 * N2 / (t64 * 1e-3) / 1e9 / copy_gbs,
             "fp64": {"us": t64 * 1e3, "jv_per_s": 1e3 / t64, "GBs": 72 * N2 / (t64 * 1e-3) / 1e9,
                      "frac_hbm": 72 * N2 / (t64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": profiled_traffic("dfr_kernel_jv_fp64_c2_ne60_p6_jet.txt"),
