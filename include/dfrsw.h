@@ -401,6 +401,16 @@ int dfr_ensemble_timing_read(dfr_ensemble *e, int kind, double *total_ms, int64_
  * DFR_E_INVAL for bits beyond DFR_K_NKINDS. */
 int dfr_ensemble_timing_kinds(dfr_ensemble *e, unsigned mask);
 
+/* Measurement helper, not part of the method: copies `bytes` from src to dst
+ * (device pointers, both 16-byte aligned, bytes a multiple of 16, not
+ * overlapping) on `hip_stream` (NULL = default stream) with one 16-byte load
+ * and store per lane, in a grid of up to 131072 workgroups of 512 threads.
+ * Timed over a large buffer it gives the streaming bandwidth a kernel
+ * reaches on the device, the practical ceiling beside the published peak.
+ * Asynchronous.  DFR_E_INVAL for a null pointer, misalignment or a size not
+ * a multiple of 16. */
+int dfr_stream_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 const char *dfr_last_error(void);
 
 #ifdef __cplusplus

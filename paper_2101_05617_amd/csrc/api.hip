@@ -589,6 +589,13 @@ static int time_launches(Ctx &c, hipEvent_t e0, hipEvent_t e1, int reps, F launc
   return DFR_OK;
 }
 
+// a plain streaming copy, 16 bytes per lane, grid-stride (measurement only)
+__global__ __launch_bounds__(512) void stream_copy_kernel(const float4 *__restrict__ a, float4 *__restrict__ b,
+                                                          size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
 }  // namespace dfrsw
 
 using namespace dfrsw;
@@ -596,6 +603,20 @@ using namespace dfrsw;
 extern "C" {
 
 const char *dfr_last_error(void) { return g_last_error.c_str(); }
+
+int dfr_stream_copy(const void *src, void *dst, size_t bytes, void *hip_stream) {
+  if (!src || !dst || (bytes % 16) || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) {
+    set_error("dfr_stream_copy: null pointer, or a pointer or size not a multiple of 16 bytes");
+    return DFR_E_INVAL;
+  }
+  const size_t n = bytes / 16;
+  if (n == 0) return DFR_OK;
+  const size_t blocks = std::min<size_t>(131072, (n + 511) / 512);
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(512), 0, (hipStream_t)hip_stream,
+                     (const float4 *)src, (float4 *)dst, n);
+  DFR_HIP(hipGetLastError());
+  return DFR_OK;
+}
 
 int dfr_create(const dfr_grid_desc *d, void *stream, dfr_ctx **out) {
   if (!d || !out) {

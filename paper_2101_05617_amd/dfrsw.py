@@ -123,6 +123,7 @@ def lib():
             "dfr_num_unknowns": (i64, [vp]),
             "dfr_node_frames": (i, [vp, vp, vp, vp]),
             "dfr_sync": (i, [vp]),
+            "dfr_stream_copy": (i, [vp, vp, ctypes.c_size_t, vp]),
             "dfr_rhs": (i, [vp, vp, vp]),
             "dfr_jvp_complex_step": (i, [vp, vp, vp, d, i, vp]),
             "dfr_jvp_complex_step_noalloc": (i, [vp, vp, vp, d, i, vp]),
@@ -177,7 +178,17 @@ def exported_symbols():
             "dfr_ensemble_size", "dfr_ensemble_member", "dfr_ensemble_autotune", "epi_ensemble_create", "epi_ensemble_step",
             "epi_ensemble_get_state", "epi_ensemble_destroy", "dfr_set_riemann", "dfr_get_riemann", "dfr_diagnostics", "dfr_set_tile", "dfr_get_tile", "dfr_get_krylov_tile", "dfr_autotune", "dfr_timing_enable",
             "dfr_timing_read", "dfr_ensemble_set_rounds", "dfr_ensemble_round_counts", "dfr_ensemble_timing_enable",
-            "dfr_ensemble_timing_read", "dfr_ensemble_timing_kinds", "dfr_last_error"]
+            "dfr_ensemble_timing_read", "dfr_ensemble_timing_kinds", "dfr_stream_copy", "dfr_last_error"]
+
+
+def dfr_stream_copy(src, dst, stream=None):
+    """Copy the bytes of device tensor src into dst (same size) with the
+    library's streaming copy (a measurement helper)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dfr_stream_copy: sizes differ")
+    _check(lib().dfr_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                 None if stream is None else ctypes.c_void_p(stream)))
 
 
 def _check(rc):
