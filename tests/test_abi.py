@@ -106,3 +106,16 @@ def test_decision_replay_marshalling():
     o = dfrsw.kiops_opts(tol=1e-8, replay=r)
     assert ctypes.addressof(o.replay.contents) == ctypes.addressof(st)
     assert not dfrsw.kiops_opts(tol=1e-8).replay
+
+
+def test_header_is_self_contained_c99(tmp_path):
+    # a C caller includes the header alone
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "only_header.c"
+    src.write_text(f'#include "{HEADER}"\nint main(void) {{ return DFR_OK; }}\n')
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-c", str(src), "-o", str(tmp_path / "o.o")],
+                   check=True, capture_output=True)
