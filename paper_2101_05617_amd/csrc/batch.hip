@@ -261,7 +261,7 @@ static int kiops_rounds_dev(dfr_ensemble &E, std::vector<KiopsMachine> &K, const
     d.TY = c.ar_ty;
     d.ntiles = (int)dfr_num_tiles(&c, true);
     d.g_ne = c.ne;
-    d.wil = c.w_il ? 1 : 0;
+    d.wil = c.w_il ? wil_code(basis32, k.p) : 0;
     d.V = reinterpret_cast<char *>(c.d_V);
     d.W = c.d_W;
     d.w = k.w;

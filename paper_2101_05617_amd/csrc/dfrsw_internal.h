@@ -105,7 +105,9 @@ struct ArnoldiArgs {
   int p;                  // number of W columns
   int start;              // 1: v_j is the sub-step's start vector
   const double *W[MAX_P]; // scaled b-vectors, column k pairs with bottom entry k
-  int wil;                // 1: W[0] holds the columns interleaved, 4 per value (p <= 4): FP64, or
+  int wil;                // 0: W[k] separate; 1: W[0] holds the columns interleaved, 4 per value
+                          //    (p <= 4), FP64 or FP32; 3: three FP32 per value (FP32 basis, p <= 3):
+                          //    see wil_code.  Otherwise, for 1: FP64, or
                           //    FP32 when the basis is FP32
 
   const void *vprev;      // v~_{j-1} as stored (basis element type) or NULL (iop = 1)
@@ -176,6 +178,12 @@ struct PreCall {          // device-controlled rounds: combination and / or star
   double *x;              // the result: written by the combination, read by the start
   double *pout;           // the start's partial squared norms, one per workgroup
 };
+// The interleaved layout of the b-columns W for p columns: FP32 columns (an
+// FP32 Krylov basis) with at most three are stored three per value (12 bytes,
+// read with one 12-byte load); otherwise four per value (padded).  Returns
+// the ArnoldiArgs::wil code, 3 or 1.
+inline int wil_code(bool f32, int p) { return (f32 && p <= 3) ? 3 : 1; }
+
 struct WilCall {         // W = nu [cols] interleaved four per value (a member's b-columns)
   int b0, nblk;
   int64_t n;

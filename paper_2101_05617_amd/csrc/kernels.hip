@@ -311,6 +311,12 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T *gmem(const
 }
 
 // four consecutive floats (16 bytes) at float4 index `index`
+// three FP32 values at index (12-byte records)
+__device__ __forceinline__ float4 bload3f(rsrc_t r, uint32_t index) {
+  typedef unsigned int u3 __attribute__((ext_vector_type(3)));
+  const u3 w = __builtin_bit_cast(u3, __builtin_amdgcn_raw_buffer_load_b96(r, index * 12u, 0, 0));
+  return make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z), 0.0f);
+}
 __device__ __forceinline__ float4 bload4f(rsrc_t r, uint32_t index) {
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   const u4 w = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(r, index * 16u, 0, 0));
@@ -643,12 +649,14 @@ __device__ __forceinline__ void dfr_body(const GridArgs &g, const Ops1D &ops, co
       if constexpr (std::is_same<TV, float>::value) {
         // FP32 basis: the columns are kept in FP32 too (what they feed is
         // rounded to FP32 when stored), one 16-byte load per value
-        const rsrc_t rw = make_rsrc(ar.W[0], n3 * 16u);
+        // (three per value when p <= 3, one 12-byte load; else four)
+        const bool w3 = ar.wil == 3;
+        const rsrc_t rw = make_rsrc(ar.W[0], n3 * (w3 ? 12u : 16u));
         float4 x[3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
           const uint32_t id = (uint32_t)(f * N + gidx);
-          x[f] = bload4f(rw, id);
+          x[f] = w3 ? bload3f(rw, id) : bload4f(rw, id);
           pv[f] = (double)bload<TV>(rp, id);
         }
 #pragma unroll
@@ -1052,7 +1060,7 @@ __device__ __forceinline__ void arnoldi_first_body(int blk, int nblk, int64_t n3
     double acc = 0.0;
     if (ar.wil) {
       if constexpr (std::is_same<TV, float>::value) {   // FP32 columns with an FP32 basis
-        const float *w = reinterpret_cast<const float *>(ar.W[0]) + 4 * i;
+        const float *w = reinterpret_cast<const float *>(ar.W[0]) + (ar.wil == 3 ? 3 : 4) * i;
         for (int k = 0; k < ar.p; ++k) acc += (double)w[k] * bj[k];
       } else {
         const double *w = ar.W[0] + 4 * i;
@@ -2455,7 +2463,12 @@ __device__ __forceinline__ void w_interleave_body(int blk, int nblk, int64_t n, 
     const double a1 = (p > 1 && c1) ? nu * c1[i] : 0.0;
     const double a2 = (p > 2 && c2) ? nu * c2[i] : 0.0;
     const double a3 = (p > 3 && c3) ? nu * c3[i] : 0.0;
-    if (f32) {   // the columns of a call with an FP32 Krylov basis
+    if (f32 && p <= 3) {   // FP32 columns, three per value (wil_code)
+      float *o = reinterpret_cast<float *>(out) + 3 * i;
+      o[0] = (float)a0;
+      o[1] = (float)a1;
+      o[2] = (float)a2;
+    } else if (f32) {      // the columns of a call with an FP32 Krylov basis
       reinterpret_cast<float4 *>(out)[i] = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
     } else {
       double2 *o = reinterpret_cast<double2 *>(out) + 2 * i;

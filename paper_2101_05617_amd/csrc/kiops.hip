@@ -154,7 +154,7 @@ void km_arnoldi_args(const KiopsMachine &k, const kiops_opts &o, ArnoldiArgs &ar
     ar.W[i] = c.w_il ? c.d_W : c.d_W + i * n3;
     ar.ybot[i] = k.ybot[i];
   }
-  ar.wil = c.w_il ? 1 : 0;
+  ar.wil = c.w_il ? wil_code(c.basis32, k.p) : 0;
   ar.vprev = (k.j >= 1 && o.iop >= 2) ? c.vslot(k.j - 1) : nullptr;
   ar.pin = c.d_partials2;
   ar.np_in = k.npB;
